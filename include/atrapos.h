@@ -1,0 +1,196 @@
+/*
+ * atrapos.h -- C-ABI of the MI355X metapath query engine.
+ *
+ * The engine evaluates constrained metapath queries over a heterogeneous
+ * information network (HIN) held in GPU memory and returns, for every pair of
+ * end nodes connected by at least one instance of the metapath, the number of
+ * instances (paper Sec. 2: Def. 1 HIN, Def. 2 metapath and instance, Def. 3
+ * constrained metapath, Problem 1 MQE).  Evaluation is a chain of sparse
+ * matrix products over the typed 0/1 adjacency matrices A_r, with each
+ * constraint c_i applied as the 0/1 diagonal matrix M_{c_i} (Sec. 2, the
+ * paragraph after Problem 1):
+ *
+ *      R = M_1 A_{r_1} M_2 A_{r_2} ... A_{r_{n-1}} M_n .
+ *
+ * The multiplication order is chosen by dynamic programming over estimated
+ * sparse-product costs (Sec. 3.1 Eq. 1, Sec. 3.2 Eq. 2); the order never
+ * changes the result (associativity, Sec. 3.1).
+ *
+ * Conventions shared by every call
+ *   - Every call returns an atp_status; it never aborts the process.  On error
+ *     no output handle is created and *out (where present) is set to NULL.
+ *     A context stays usable after any error except ATP_EDEVICE.
+ *   - Node ids are 0-based indices within their node type.
+ *   - Sparse matrices are CSR: int64 row pointers (rows + 1 entries, first 0,
+ *     non-decreasing), int32 column indices strictly ascending within a row.
+ *   - Input arrays are host pointers unless a flag says otherwise; they are
+ *     copied, the caller keeps ownership and may free them after the call.
+ *   - All GPU work of a context is issued on the stream given in atp_options
+ *     (NULL = the default stream) of the device given there.
+ *   - A context is not internally locked: use one context per host thread.
+ */
+#ifndef ATRAPOS_H
+#define ATRAPOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t atp_status;
+enum {
+    ATP_OK = 0,
+    ATP_EINVAL = -1,     /* malformed argument: bad CSR, id out of range, bad kind, n_types < 2 */
+    ATP_ENOMEM = -2,     /* a device allocation failed */
+    ATP_EOVERFLOW = -3,  /* some path count of the result is >= 2^63 (does not fit int64) */
+    ATP_ESCHEMA = -4,    /* metapath step without a (unique) relation between the two types */
+    ATP_EDEVICE = -5,    /* HIP runtime error; the context must be destroyed */
+    ATP_EBUDGET = -6,    /* the context's memory budget would be exceeded */
+    ATP_ESTATE = -7      /* call not valid in the current state (e.g. no GPU present) */
+};
+
+typedef struct atp_ctx atp_ctx;
+typedef struct atp_result atp_result;
+
+/* flags of atp_options.flags */
+#define ATP_OPT_PROFILE (1u << 0)   /* time every kernel launch with HIP events (atp_kernel_times) */
+#define ATP_OPT_PLAN_EAC (1u << 1)  /* planner uses the paper's uniform E_ac estimate (Sec. 3.2) */
+
+typedef struct {
+    int device;                 /* HIP device ordinal */
+    void *hip_stream;           /* hipStream_t to issue work on, or NULL for the default stream */
+    /* optional device allocator; both NULL = the library's own caching pool */
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *alloc_user;
+    uint64_t mem_budget_bytes;  /* 0 = unlimited; otherwise allocations beyond it fail with ATP_EBUDGET */
+    uint32_t flags;             /* ATP_OPT_* */
+} atp_options;
+
+/* Create a context on options->device (options may be NULL: device 0,
+ * default stream, own pool).  ATP_ESTATE if no HIP device is present. */
+atp_status atp_create(const atp_options *options, atp_ctx **out);
+/* Release every device buffer, result handle and the context itself. */
+atp_status atp_destroy(atp_ctx *ctx);
+
+/* --- the network (Def. 1): node types, relations, properties -------------- */
+
+/* Register a node type with `count` nodes (ids 0..count-1). */
+atp_status atp_add_node_type(atp_ctx *ctx, const char *name, int64_t count, int32_t *type_id);
+
+#define ATP_REL_DEVICE_PTRS (1u << 0)  /* row_ptr / col are device pointers (still copied) */
+#define ATP_REL_ADD_REVERSE (1u << 1)  /* also register the transpose as relation dst -> src */
+
+/* Register the 0/1 adjacency matrix A_r of an edge type from src_type to
+ * dst_type (the adjacency-matrix definition after Def. 1) as CSR with
+ * count(src_type) rows and count(dst_type) columns.  ATP_EINVAL on
+ * non-monotone row_ptr, unsorted or duplicate columns, or ids out of range.
+ * *rel_id receives the relation id; with ATP_REL_ADD_REVERSE the transpose
+ * gets id *rel_id + 1. */
+atp_status atp_add_relation(atp_ctx *ctx, int32_t src_type, int32_t dst_type,
+                            const int64_t *row_ptr, const int32_t *col, int64_t nnz,
+                            uint32_t flags, int32_t *rel_id);
+
+enum { ATP_I16 = 1, ATP_I32 = 2, ATP_I64 = 3 };
+
+/* Register a node property (Sec. 2, v.prop): one value per node of type_id,
+ * of dtype ATP_I16 / ATP_I32 / ATP_I64, host pointer, copied. */
+atp_status atp_add_property(atp_ctx *ctx, int32_t type_id, const char *name, int32_t dtype,
+                            const void *values, int32_t *prop_id);
+
+/* --- queries (Def. 3, Problem 1) ------------------------------------------ */
+
+enum { ATP_C_RANGE = 1, ATP_C_IDSET = 2 };
+
+/* One constraint c_i of a constrained metapath (Def. 3).  It restricts the
+ * nodes allowed at metapath position `position` (0-based):
+ *   ATP_C_RANGE: lo <= v.prop <= hi (inclusive) on property prop_id, which must
+ *                belong to the node type at that position;
+ *   ATP_C_IDSET: v is one of ids[0..n_ids) (host pointer, any order,
+ *                duplicates allowed, each in range).
+ * Several constraints at one position are ANDed. */
+typedef struct {
+    int32_t position;
+    int32_t kind;
+    int32_t prop_id;
+    int64_t lo, hi;
+    const int32_t *ids;
+    int64_t n_ids;
+} atp_constraint;
+
+/* Evaluate the constrained metapath types[0] .. types[n_types-1] (node type
+ * ids).  rel_ids (n_types-1 entries) names the relation of every step; NULL
+ * means the unique relation registered from types[i] to types[i+1]
+ * (ATP_ESCHEMA if there is none or more than one).  The result is the
+ * count(types[0]) x count(types[n-1]) matrix R in canonical CSR: int64 row
+ * pointers, int32 columns ascending per row, int64 counts >= 1, no stored
+ * zeros; rows excluded by constraints are empty.  If any count is >= 2^63
+ * the call returns ATP_EOVERFLOW and no result.  The result lives in device
+ * memory owned by the library until atp_result_free. */
+atp_status atp_eval(atp_ctx *ctx, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                    const atp_constraint *cons, int32_t n_cons, atp_result **out);
+
+/* As atp_eval, with the multiplication order forced by `plan` instead of the
+ * planner's choice.  `plan` parenthesises the relation indices 0..n_types-2
+ * in order, e.g. "((0,1),(2,3))" or "(((0,1),2),3)"; NULL = planner.  The
+ * result is identical for every plan.  ATP_EINVAL on a malformed plan. */
+atp_status atp_eval_plan(atp_ctx *ctx, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                         const atp_constraint *cons, int32_t n_cons, const char *plan,
+                         atp_result **out);
+
+/* Shape and device arrays of a result.  Pointers stay valid until
+ * atp_result_free; any output pointer argument may be NULL. */
+atp_status atp_result_csr(const atp_result *res, int64_t *n_rows, int64_t *n_cols, int64_t *nnz,
+                          const int64_t **row_ptr, const int32_t **col, const int64_t **val);
+
+/* Copy a result to host arrays of n_rows+1, nnz and nnz entries (synchronous). */
+atp_status atp_result_to_host(const atp_result *res, int64_t *row_ptr, int32_t *col, int64_t *val);
+
+/* Per-query statistics: chosen plan (NUL-terminated, truncated to plan_cap),
+ * multiplications performed, total products (N_op, Sec. 3.2) and nonzeros of
+ * every intermediate and of the result. */
+typedef struct {
+    int32_t n_products;
+    int64_t n_op_total;
+    int64_t nnz_intermediate_total;
+    int64_t nnz_result;
+    int64_t slots_total;         /* sum of per-row upper bounds reserved */
+} atp_eval_stats;
+atp_status atp_result_stats(const atp_result *res, atp_eval_stats *stats, char *plan, size_t plan_cap);
+
+atp_status atp_result_free(atp_result *res);
+
+/* --- planner (host only; usable without a GPU) ----------------------------- */
+
+/* Dynamic-programming chain order (Sec. 3.1, Eq. 1) for p = n_mats matrices
+ * with dims[0..p] (matrix i is dims[i] x dims[i+1]) and per-matrix nonzeros
+ * nnz[0..p) under the sparse cost of Eq. 2 with the uniform E_ac density
+ * estimate (Sec. 3.2): cost = alpha*nnz(X) + beta*N_op + gamma*nnz(Z),
+ * N_op = nnz(X)*nnz(Y)/k for X (m x k), Y (k x l), and
+ * rho_Z = 1 - (1 - rho_X*rho_Y)^k.  With dense != 0 the cost of X*Y is
+ * m*k*l instead (the standard product of Sec. 3.1).  Ties go to the smallest
+ * split.  Writes the parenthesisation (same syntax as atp_eval_plan) and
+ * the optimal total cost. */
+atp_status atp_plan_chain(int32_t n_mats, const int64_t *dims, const int64_t *nnz, double alpha,
+                          double beta, double gamma, int32_t dense, char *plan, size_t plan_cap,
+                          double *cost);
+
+/* --- diagnostics ------------------------------------------------------------ */
+
+/* With ATP_OPT_PROFILE: accumulated device time (ms) and launch count of
+ * every kernel name since the last reset; returns the number of kernels
+ * written (at most cap). */
+int32_t atp_kernel_times(atp_ctx *ctx, const char **names, double *ms, int64_t *launches, int32_t cap);
+void atp_kernel_times_reset(atp_ctx *ctx);
+
+/* Bytes of device memory currently held by the context (pool included). */
+int64_t atp_device_bytes(const atp_ctx *ctx);
+
+const char *atp_status_str(atp_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ATRAPOS_H */

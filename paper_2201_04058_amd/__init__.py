@@ -1,0 +1,304 @@
+"""Python binding of libatrapos.so, the MI355X metapath query engine.
+
+Argument marshalling only: every step of a query runs in the HIP library.
+Names follow the C-ABI in include/atrapos.h.  Importing this package does not
+touch the GPU; loading the library fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libatrapos.so")
+
+ATP_OK, ATP_EINVAL, ATP_ENOMEM, ATP_EOVERFLOW, ATP_ESCHEMA, ATP_EDEVICE, ATP_EBUDGET, ATP_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+ATP_OPT_PROFILE, ATP_OPT_PLAN_EAC = 1, 2
+ATP_REL_DEVICE_PTRS, ATP_REL_ADD_REVERSE = 1, 2
+ATP_I16, ATP_I32, ATP_I64 = 1, 2, 3
+ATP_C_RANGE, ATP_C_IDSET = 1, 2
+
+EXPORTS = [
+    "atp_create", "atp_destroy", "atp_add_node_type", "atp_add_relation", "atp_add_property",
+    "atp_eval", "atp_eval_plan", "atp_result_csr", "atp_result_to_host", "atp_result_stats",
+    "atp_result_free", "atp_plan_chain", "atp_kernel_times", "atp_kernel_times_reset",
+    "atp_device_bytes", "atp_status_str",
+]
+
+
+class AtpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+
+
+class atp_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int),
+                ("hip_stream", ctypes.c_void_p),
+                ("alloc", ctypes.c_void_p),
+                ("free", ctypes.c_void_p),
+                ("alloc_user", ctypes.c_void_p),
+                ("mem_budget_bytes", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
+
+
+class atp_constraint(ctypes.Structure):
+    _fields_ = [("position", ctypes.c_int32),
+                ("kind", ctypes.c_int32),
+                ("prop_id", ctypes.c_int32),
+                ("lo", ctypes.c_int64),
+                ("hi", ctypes.c_int64),
+                ("ids", ctypes.c_void_p),
+                ("n_ids", ctypes.c_int64)]
+
+
+class atp_eval_stats(ctypes.Structure):
+    _fields_ = [("n_products", ctypes.c_int32),
+                ("n_op_total", ctypes.c_int64),
+                ("nnz_intermediate_total", ctypes.c_int64),
+                ("nnz_result", ctypes.c_int64),
+                ("slots_total", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if libatrapos.so was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2201_04058_amd.build` "
+                          "or __graft_entry__.build(); there is no fallback implementation")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    P = ctypes.POINTER
+    sig = {
+        "atp_create": ([vp, P(vp)], i32),
+        "atp_destroy": ([vp], i32),
+        "atp_add_node_type": ([vp, ctypes.c_char_p, i64, P(i32)], i32),
+        "atp_add_relation": ([vp, i32, i32, vp, vp, i64, u32, P(i32)], i32),
+        "atp_add_property": ([vp, i32, ctypes.c_char_p, i32, vp, P(i32)], i32),
+        "atp_eval": ([vp, vp, i32, vp, vp, i32, P(vp)], i32),
+        "atp_eval_plan": ([vp, vp, i32, vp, vp, i32, ctypes.c_char_p, P(vp)], i32),
+        "atp_result_csr": ([vp, P(i64), P(i64), P(i64), P(vp), P(vp), P(vp)], i32),
+        "atp_result_to_host": ([vp, vp, vp, vp], i32),
+        "atp_result_stats": ([vp, P(atp_eval_stats), ctypes.c_char_p, ctypes.c_size_t], i32),
+        "atp_result_free": ([vp], i32),
+        "atp_plan_chain": ([i32, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                            ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_double)], i32),
+        "atp_kernel_times": ([vp, P(ctypes.c_char_p), P(ctypes.c_double), P(i64), i32], i32),
+        "atp_kernel_times_reset": ([vp], None),
+        "atp_device_bytes": ([vp], i64),
+        "atp_status_str": ([i32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def status_str(st: int) -> str:
+    return lib().atp_status_str(st).decode()
+
+
+def _check(st: int, where: str) -> None:
+    if st != ATP_OK:
+        raise AtpError(st, where)
+
+
+def plan_chain(dims, nnz=None, alpha=12.0, beta=12.0, gamma=12.0, dense=False) -> tuple:
+    """Host-only DP planner (Eq. 1) -> (plan string, cost)."""
+    dims = np.ascontiguousarray(dims, dtype=np.int64)
+    p = dims.shape[0] - 1
+    nz = None if nnz is None else np.ascontiguousarray(nnz, dtype=np.int64)
+    buf = ctypes.create_string_buffer(4096)
+    cost = ctypes.c_double()
+    st = lib().atp_plan_chain(p, dims.ctypes.data, None if nz is None else nz.ctypes.data, alpha, beta, gamma,
+                              1 if dense else 0, buf, 4096, ctypes.byref(cost))
+    _check(st, "atp_plan_chain")
+    return buf.value.decode(), cost.value
+
+
+def torch_stream_handle(device: int = 0) -> int | None:
+    """The HIP stream torch currently issues work on (None = default stream)."""
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream or None
+
+
+class Result:
+    def __init__(self, ctx: "Context", handle: int):
+        self._ctx = ctx
+        self._h = ctypes.c_void_p(handle)
+
+    def shape(self) -> tuple:
+        r, c, z = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().atp_result_csr(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(z), None, None, None),
+               "atp_result_csr")
+        return r.value, c.value, z.value
+
+    def device_ptrs(self) -> tuple:
+        rp, col, val = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().atp_result_csr(self._h, None, None, None, ctypes.byref(rp), ctypes.byref(col),
+                                    ctypes.byref(val)), "atp_result_csr")
+        return rp.value, col.value, val.value
+
+    def to_host(self) -> tuple:
+        n_rows, _, nnz = self.shape()
+        rp = np.empty(n_rows + 1, dtype=np.int64)
+        col = np.empty(max(nnz, 0), dtype=np.int32)
+        val = np.empty(max(nnz, 0), dtype=np.int64)
+        _check(lib().atp_result_to_host(self._h, rp.ctypes.data, col.ctypes.data if nnz else None,
+                                        val.ctypes.data if nnz else None), "atp_result_to_host")
+        return rp, col, val
+
+    def stats(self) -> dict:
+        s = atp_eval_stats()
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().atp_result_stats(self._h, ctypes.byref(s), buf, 4096), "atp_result_stats")
+        return {"plan": buf.value.decode(), "n_products": s.n_products, "n_op": s.n_op_total,
+                "nnz_intermediate": s.nnz_intermediate_total, "nnz": s.nnz_result, "slots": s.slots_total}
+
+    def free(self) -> None:
+        if self._h and self._h.value:
+            lib().atp_result_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._ctx._h.value:
+                self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One engine context (device, stream, memory pool, registered network)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None, budget_bytes: int = 0,
+                 profile: bool = False, plan_eac: bool = False):
+        o = atp_options()
+        o.device = device
+        o.hip_stream = stream
+        o.mem_budget_bytes = budget_bytes
+        o.flags = (ATP_OPT_PROFILE if profile else 0) | (ATP_OPT_PLAN_EAC if plan_eac else 0)
+        h = ctypes.c_void_p()
+        _check(lib().atp_create(ctypes.byref(o), ctypes.byref(h)), "atp_create")
+        self._h = h
+        self.type_ids: dict = {}
+        self.prop_ids: dict = {}
+        self.rel_ids: dict = {}
+
+    def close(self) -> None:
+        if self._h.value:
+            lib().atp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- network ---------------------------------------------------------
+    def add_node_type(self, name: str, count: int) -> int:
+        tid = ctypes.c_int32()
+        _check(lib().atp_add_node_type(self._h, name.encode(), int(count), ctypes.byref(tid)), "atp_add_node_type")
+        self.type_ids[name] = tid.value
+        return tid.value
+
+    def add_relation(self, src: int, dst: int, row_ptr, col, reverse: bool = False) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        rid = ctypes.c_int32()
+        flags = ATP_REL_ADD_REVERSE if reverse else 0
+        _check(lib().atp_add_relation(self._h, src, dst, rp.ctypes.data, cl.ctypes.data if cl.size else None,
+                                      cl.shape[0], flags, ctypes.byref(rid)), "atp_add_relation")
+        return rid.value
+
+    def add_property(self, type_id: int, name: str, values) -> int:
+        v = np.ascontiguousarray(values)
+        dt = {np.dtype(np.int16): ATP_I16, np.dtype(np.int32): ATP_I32, np.dtype(np.int64): ATP_I64}[v.dtype]
+        pid = ctypes.c_int32()
+        _check(lib().atp_add_property(self._h, type_id, name.encode(), dt, v.ctypes.data if v.size else None,
+                                      ctypes.byref(pid)), "atp_add_property")
+        return pid.value
+
+    def load_hin(self, hin) -> None:
+        """Register every node type, relation and property of a network object
+        with ``counts``, ``relations`` ((src, dst) -> row_ptr/col) and ``props``."""
+        for name, n in hin.counts.items():
+            self.add_node_type(name, n)
+        for (s, d), r in hin.relations.items():
+            self.rel_ids[(s, d)] = self.add_relation(self.type_ids[s], self.type_ids[d], r.row_ptr, r.col)
+        for (t, p), v in hin.props.items():
+            self.prop_ids[(t, p)] = self.add_property(self.type_ids[t], p, v)
+
+    # --- queries ---------------------------------------------------------
+    def _constraints(self, types, constraints):
+        arr = (atp_constraint * max(1, len(constraints)))()
+        keep = []
+        for z, c in enumerate(constraints):
+            a = arr[z]
+            a.position = c.position
+            if c.kind == "range":
+                a.kind = ATP_C_RANGE
+                a.prop_id = self.prop_ids[(types[c.position], c.prop)]
+                a.lo, a.hi = int(c.lo), int(c.hi)
+            elif c.kind == "idset":
+                ids = np.ascontiguousarray(c.ids, dtype=np.int32)
+                keep.append(ids)
+                a.kind = ATP_C_IDSET
+                a.ids = ids.ctypes.data if ids.size else None
+                a.n_ids = ids.shape[0]
+            else:
+                raise ValueError(c.kind)
+        return arr, keep
+
+    def eval(self, types, constraints=(), plan: str | None = None, rel_ids=None) -> Result:
+        """Evaluate a constrained metapath given by type names (or ids)."""
+        tids = np.array([self.type_ids[t] if isinstance(t, str) else int(t) for t in types], dtype=np.int32)
+        names = [t if isinstance(t, str) else None for t in types]
+        arr, keep = self._constraints(names, list(constraints))
+        rids = None if rel_ids is None else np.ascontiguousarray(rel_ids, dtype=np.int32)
+        h = ctypes.c_void_p()
+        if plan is None:
+            st = lib().atp_eval(self._h, tids.ctypes.data, len(tids), None if rids is None else rids.ctypes.data,
+                                arr, len(constraints), ctypes.byref(h))
+        else:
+            st = lib().atp_eval_plan(self._h, tids.ctypes.data, len(tids),
+                                     None if rids is None else rids.ctypes.data, arr, len(constraints),
+                                     plan.encode(), ctypes.byref(h))
+        del keep
+        _check(st, "atp_eval")
+        return Result(self, h.value)
+
+    def eval_query(self, query, plan: str | None = None) -> Result:
+        return self.eval(query.types, query.constraints, plan=plan)
+
+    # --- diagnostics -----------------------------------------------------
+    def kernel_times(self) -> dict:
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        n = (ctypes.c_int64 * cap)()
+        k = lib().atp_kernel_times(self._h, names, ms, n, cap)
+        return {names[z].decode(): (ms[z], n[z]) for z in range(k)}
+
+    def kernel_times_reset(self) -> None:
+        lib().atp_kernel_times_reset(self._h)
+
+    def device_bytes(self) -> int:
+        return int(lib().atp_device_bytes(self._h))

@@ -1,0 +1,1045 @@
+// Host side of the engine: the C-ABI of atrapos.h, the HIN registry (Def. 1),
+// constraint masks (Def. 3, the diagonal matrices M_c of Sec. 2), the
+// planner call (Sec. 3.1-3.2) and the post-order executor of the plan tree.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <set>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/atrapos.h"
+#include "internal.hpp"
+#include "planner.hpp"
+
+using namespace atp;
+
+// ---------------------------------------------------------------------------
+// kernel timing
+
+namespace atp {
+struct KernelTimer {
+    struct Rec {
+        const char *name;
+        hipEvent_t e0, e1;
+    };
+    std::vector<hipEvent_t> free_events;
+    std::vector<Rec> pending;
+    std::map<std::string, std::pair<double, int64_t>> acc;
+    hipEvent_t take() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void flush() {
+        for (auto &r : pending) {
+            float ms = 0;
+            if (r.e0 && r.e1 && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+                auto &a = acc[r.name];
+                a.first += ms;
+                a.second += 1;
+            }
+            if (r.e0) free_events.push_back(r.e0);
+            if (r.e1) free_events.push_back(r.e1);
+        }
+        pending.clear();
+    }
+    ~KernelTimer() {
+        for (auto &r : pending) {
+            if (r.e0) (void)hipEventDestroy(r.e0);
+            if (r.e1) (void)hipEventDestroy(r.e1);
+        }
+        for (auto e : free_events) (void)hipEventDestroy(e);
+    }
+};
+
+void timer_begin(KernelTimer *t, const char *name, hipStream_t s) {
+    if (!t) return;
+    KernelTimer::Rec r{name, t->take(), t->take()};
+    if (r.e0) (void)hipEventRecord(r.e0, s);
+    t->pending.push_back(r);
+}
+
+void timer_end(KernelTimer *t, hipStream_t s) {
+    if (!t || t->pending.empty()) return;
+    auto &r = t->pending.back();
+    if (r.e1) (void)hipEventRecord(r.e1, s);
+}
+}  // namespace atp
+
+// ---------------------------------------------------------------------------
+// device memory: caching pool (or caller callbacks) with an optional budget
+
+namespace {
+
+struct Pool {
+    void *(*user_alloc)(size_t, void *) = nullptr;
+    void (*user_free)(void *, void *) = nullptr;
+    void *user = nullptr;
+    uint64_t budget = 0;
+    int64_t held = 0;  // bytes obtained from the runtime (in use + cached)
+    std::multimap<size_t, void *> cache;
+    std::map<void *, size_t> live;
+
+    static size_t round(size_t n) {
+        if (n < 256) return 256;
+        size_t r = 256;
+        while (r < n && r < ((size_t)1 << 21)) r <<= 1;
+        if (r >= n) return r;
+        const size_t mb2 = (size_t)1 << 21;
+        return (n + mb2 - 1) / mb2 * mb2;
+    }
+    void release_cache() {
+        for (auto &kv : cache) {
+            (void)hipFree(kv.second);
+            held -= (int64_t)kv.first;
+        }
+        cache.clear();
+    }
+    atp_status alloc(size_t bytes, void **out) {
+        *out = nullptr;
+        if (bytes == 0) bytes = 1;
+        size_t n = round(bytes);
+        if (user_alloc) {
+            if (budget && (uint64_t)(held + n) > budget) return ATP_EBUDGET;
+            void *p = user_alloc(n, user);
+            if (!p) return ATP_ENOMEM;
+            live[p] = n;
+            held += (int64_t)n;
+            *out = p;
+            return ATP_OK;
+        }
+        auto it = cache.lower_bound(n);
+        if (it != cache.end() && it->first <= n + n / 4) {
+            void *p = it->second;
+            size_t sz = it->first;
+            cache.erase(it);
+            live[p] = sz;
+            *out = p;
+            return ATP_OK;
+        }
+        if (budget && (uint64_t)(held + n) > budget) {
+            release_cache();
+            if ((uint64_t)(held + n) > budget) return ATP_EBUDGET;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            release_cache();
+            if (hipMalloc(&p, n) != hipSuccess) {
+                (void)hipGetLastError();
+                return ATP_ENOMEM;
+            }
+        }
+        held += (int64_t)n;
+        live[p] = n;
+        *out = p;
+        return ATP_OK;
+    }
+    void release(void *p) {
+        if (!p) return;
+        auto it = live.find(p);
+        if (it == live.end()) return;
+        size_t n = it->second;
+        live.erase(it);
+        if (user_free) {
+            user_free(p, user);
+            held -= (int64_t)n;
+            return;
+        }
+        cache.emplace(n, p);
+    }
+    void destroy() {
+        release_cache();
+        for (auto &kv : live) {
+            if (user_free)
+                user_free(kv.first, user);
+            else
+                (void)hipFree(kv.first);
+        }
+        live.clear();
+        held = 0;
+    }
+};
+
+// RAII device buffer from the pool
+struct Buf {
+    Pool *pool = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    Buf() = default;
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+    Buf(Buf &&o) noexcept : pool(o.pool), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+    Buf &operator=(Buf &&o) noexcept {
+        reset();
+        pool = o.pool;
+        p = o.p;
+        bytes = o.bytes;
+        o.p = nullptr;
+        return *this;
+    }
+    ~Buf() { reset(); }
+    void reset() {
+        if (p && pool) pool->release(p);
+        p = nullptr;
+    }
+    atp_status alloc(Pool *pl, size_t n) {
+        reset();
+        pool = pl;
+        bytes = n;
+        return pl->alloc(n, &p);
+    }
+    template <typename T>
+    T *as() const {
+        return (T *)p;
+    }
+};
+
+#define TRY(x)                               \
+    do {                                     \
+        atp_status _st = (x);                \
+        if (_st != ATP_OK) return _st;       \
+    } while (0)
+#define HIPTRY(x)                            \
+    do {                                     \
+        if ((x) != hipSuccess) {             \
+            (void)hipGetLastError();         \
+            return ATP_EDEVICE;              \
+        }                                    \
+    } while (0)
+
+struct NodeType {
+    std::string name;
+    int64_t count;
+};
+
+struct Rel {
+    int32_t src, dst;
+    int64_t nnz;
+    Buf rp, col;
+    std::vector<int64_t> h_rp;      // host row pointers (planner statistics)
+    std::vector<int32_t> h_indeg;   // host column counts
+    int64_t nonempty_rows = 0, nonempty_cols = 0;
+};
+
+struct Prop {
+    int32_t type;
+    int32_t dtype;
+    std::string name;
+    Buf values;
+};
+
+}  // namespace
+
+struct atp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    Pool pool;
+    std::vector<NodeType> types;
+    std::vector<std::unique_ptr<Rel>> rels;
+    std::vector<std::unique_ptr<Prop>> props;
+    std::map<std::pair<int, int>, JunctionSketch> sketches;
+    KernelTimer timer;
+    StepHeader *h_hdr = nullptr;  // pinned
+    std::set<atp_result *> results;
+    bool broken = false;
+    KernelTimer *kt() { return (flags & ATP_OPT_PROFILE) ? &timer : nullptr; }
+};
+
+struct atp_result {
+    atp_ctx *ctx;
+    int64_t rows, cols, nnz;
+    Buf rp, col, val;
+    atp_eval_stats stats;
+    std::string plan;
+};
+
+// ---------------------------------------------------------------------------
+
+namespace {
+
+atp_status sync(atp_ctx *c) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    return ATP_OK;
+}
+
+atp_status read_header(atp_ctx *c, const StepHeader *d_hdr) {
+    HIPTRY(hipMemcpyAsync(c->h_hdr, d_hdr, sizeof(StepHeader), hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+// A matrix produced by (or feeding) one plan node.
+struct Mat {
+    bool leaf = false;
+    Operand op;
+    int64_t rows = 0, cols = 0, nnz = 0;
+    Buf rp, col, val;          // owned storage of products
+    Buf active;                // ascending non-empty rows (products used as a left operand)
+    int64_t n_active = -1;     // -1 = no list
+    const int32_t *cand = nullptr;  // leaf: candidate rows from an id-set constraint
+    int64_t n_cand = 0;
+};
+
+struct PosMask {
+    Buf bits;
+    int64_t pop = -1;       // -1 = no constraint at this position
+    Buf ids;                // sorted unique ids of an id-set constraint (smallest set)
+    int64_t n_ids = -1;
+    std::vector<int32_t> h_ids;
+};
+
+struct StepStats {
+    int64_t n_op = 0, nnz = 0, slots = 0;
+};
+
+
+// Z = X * Y, one product of the plan (Sec. 3.2).  ycols_eff bounds the
+// columns that can occur (mask popcount of Y's last position, or Y's width).
+// need_active: Z will be the left operand of a later product.
+atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, bool need_active, Mat &Z,
+                  StepStats &st, bool &saturated) {
+    Pool *pool = &c->pool;
+    hipStream_t s = c->stream;
+    KernelTimer *t = c->kt();
+    Z.leaf = false;
+    Z.rows = X.rows;
+    Z.cols = Y.cols;
+    saturated = false;
+
+    const int32_t *cand = nullptr;
+    int64_t n_cand = X.rows;
+    if (X.leaf && X.cand) {
+        cand = X.cand;
+        n_cand = X.n_cand;
+    } else if (!X.leaf && X.n_active >= 0) {
+        cand = X.active.as<int32_t>();
+        n_cand = X.n_active;
+    }
+    TRY(Z.rp.alloc(pool, sizeof(int64_t) * (Z.rows + 1)));
+    auto finish_empty = [&]() -> atp_status {
+        launch_fill_i64(Z.rp.as<int64_t>(), Z.rows + 1, 0, s, t);
+        Z.nnz = 0;
+        TRY(Z.col.alloc(pool, 4));
+        TRY(Z.val.alloc(pool, 8));
+        if (need_active) {
+            TRY(Z.active.alloc(pool, 4));
+            Z.n_active = 0;
+        }
+        Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
+                       Z.rows, Z.cols, 0};
+        return ATP_OK;
+    };
+    if (n_cand == 0 || ycols_eff == 0) return finish_empty();
+
+    Buf hdr, nop, ub, nseg, bin, long_list, bin_lists, dense_chunks, slot_off, seg_base, task_base, tmp;
+    TRY(hdr.alloc(pool, sizeof(StepHeader)));
+    TRY(nop.alloc(pool, 8 * n_cand));
+    TRY(ub.alloc(pool, 8 * n_cand));
+    TRY(nseg.alloc(pool, 8 * n_cand));
+    TRY(bin.alloc(pool, 4 * n_cand));
+    TRY(long_list.alloc(pool, 4 * n_cand));
+    TRY(bin_lists.alloc(pool, 4 * (size_t)n_cand * BIN_COUNT));
+    TRY(dense_chunks.alloc(pool, 8 * n_cand));
+    TRY(slot_off.alloc(pool, 8 * (n_cand + 1)));
+    TRY(seg_base.alloc(pool, 8 * (n_cand + 1)));
+    TRY(task_base.alloc(pool, 8 * (n_cand + 1)));
+    const int64_t tmp_n = std::max(scan_tmp_elems(n_cand), scan_tmp_elems(Z.rows));
+    TRY(tmp.alloc(pool, 8 * tmp_n));
+
+    StepHeader *d_hdr = hdr.as<StepHeader>();
+    launch_fill_i64((int64_t *)d_hdr, sizeof(StepHeader) / 8, 0, s, t);
+    launch_fill_i64(dense_chunks.as<int64_t>(), n_cand, 0, s, t);
+
+    SymbolicArgs sa;
+    sa.X = X.op;
+    sa.Y = Y.op;
+    sa.cand = cand;
+    sa.n_cand = n_cand;
+    sa.ycols_eff = ycols_eff;
+    sa.nop = nop.as<int64_t>();
+    sa.ub = ub.as<int64_t>();
+    sa.nseg = nseg.as<int64_t>();
+    sa.bin = bin.as<int32_t>();
+    sa.long_list = long_list.as<int32_t>();
+    sa.bin_lists = bin_lists.as<int32_t>();
+    sa.dense_chunks = dense_chunks.as<int64_t>();
+    sa.hdr = d_hdr;
+    launch_symbolic(sa, s, t);
+    launch_bin_rows(sa, s, t);
+    launch_scan_i64(ub.as<int64_t>(), slot_off.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
+    launch_set_header_from_scan(slot_off.as<int64_t>() + n_cand, &d_hdr->slots_total, s);
+    launch_scan_i64(nseg.as<int64_t>(), seg_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
+    launch_set_header_from_scan(seg_base.as<int64_t>() + n_cand, &d_hdr->segs_total, s);
+    launch_scan_i64(dense_chunks.as<int64_t>(), task_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
+    launch_set_header_from_scan(task_base.as<int64_t>() + n_cand, &d_hdr->dense_tasks, s);
+    TRY(read_header(c, d_hdr));
+    const StepHeader h1 = *c->h_hdr;
+    st.n_op += h1.n_op_total;
+    st.slots += h1.slots_total;
+    if (h1.slots_total == 0) return finish_empty();
+
+    Buf slot_col, slot_val, seg_cnt, seg_src, seg_dst, row_cursor, row_nnz;
+    TRY(slot_col.alloc(pool, 4 * (size_t)h1.slots_total));
+    TRY(slot_val.alloc(pool, 8 * (size_t)h1.slots_total));
+    TRY(seg_cnt.alloc(pool, 8 * (size_t)h1.segs_total));
+    TRY(seg_src.alloc(pool, 8 * (size_t)h1.segs_total));
+    TRY(seg_dst.alloc(pool, 8 * ((size_t)h1.segs_total + 1)));
+    TRY(row_cursor.alloc(pool, 8 * n_cand));
+    TRY(row_nnz.alloc(pool, 8 * (size_t)Z.rows));
+    launch_fill_i64(seg_cnt.as<int64_t>(), h1.segs_total, 0, s, t);
+    launch_fill_i64(row_cursor.as<int64_t>(), n_cand, 0, s, t);
+    launch_fill_i64(row_nnz.as<int64_t>(), Z.rows, 0, s, t);
+
+    NumericArgs na;
+    na.X = X.op;
+    na.Y = Y.op;
+    na.cand = cand;
+    na.nop = nop.as<int64_t>();
+    na.slot_off = slot_off.as<int64_t>();
+    na.seg_base = seg_base.as<int64_t>();
+    na.row_cursor = row_cursor.as<int64_t>();
+    na.slot_col = slot_col.as<int32_t>();
+    na.slot_val = slot_val.as<uint64_t>();
+    na.seg_cnt = seg_cnt.as<int64_t>();
+    na.seg_src = seg_src.as<int64_t>();
+    na.row_nnz = row_nnz.as<int64_t>();
+    na.hdr = d_hdr;
+    na.ycols = Y.cols;
+    for (int b = BIN_W64; b <= BIN_B8192; ++b)
+        launch_numeric_hash(b, bin_lists.as<int32_t>() + (int64_t)b * n_cand, h1.bin_count[b], na, s, t);
+    if (h1.bin_count[BIN_DENSE] > 0)
+        launch_numeric_dense(bin_lists.as<int32_t>() + (int64_t)BIN_DENSE * n_cand, h1.bin_count[BIN_DENSE],
+                             task_base.as<int64_t>(), h1.dense_tasks, na, s, t);
+
+    // row pointers over every row of X; segment destinations in (row, tile) order
+    launch_scan_i64(row_nnz.as<int64_t>(), Z.rp.as<int64_t>(), Z.rows, tmp.as<int64_t>(), s, t);
+    launch_set_header_from_scan(Z.rp.as<int64_t>() + Z.rows, &d_hdr->nnz_total, s);
+    Buf tmp_seg;
+    TRY(tmp_seg.alloc(pool, 8 * (size_t)scan_tmp_elems(h1.segs_total)));
+    launch_scan_i64(seg_cnt.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total, tmp_seg.as<int64_t>(), s, t);
+    Buf flags, flags_scan;
+    if (need_active) {
+        TRY(flags.alloc(pool, 8 * n_cand));
+        TRY(flags_scan.alloc(pool, 8 * (n_cand + 1)));
+        launch_active_flags(cand, n_cand, row_nnz.as<int64_t>(), flags.as<int64_t>(), s, t);
+        launch_scan_i64(flags.as<int64_t>(), flags_scan.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
+        launch_set_header_from_scan(flags_scan.as<int64_t>() + n_cand, &d_hdr->n_active, s);
+    }
+    TRY(read_header(c, d_hdr));
+    const StepHeader h2 = *c->h_hdr;
+    saturated = h2.saturated != 0;
+    Z.nnz = h2.nnz_total;
+    st.nnz += Z.nnz;
+    TRY(Z.col.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.nnz, 1)));
+    TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
+    launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
+                         slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
+                         Z.val.as<uint64_t>(), s, t);
+    if (need_active) {
+        Z.n_active = h2.n_active;
+        TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.n_active, 1)));
+        launch_active_scatter(cand, n_cand, flags_scan.as<int64_t>(), Z.active.as<int32_t>(), s, t);
+    }
+    Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
+                   Z.rows, Z.cols, Z.nnz};
+    // temporaries go back to the pool here; later work on the stream is ordered after this step
+    return ATP_OK;
+}
+
+// Build the mask of one metapath position from its constraints (ANDed).
+atp_status build_mask(atp_ctx *c, int pos_type, const atp_constraint *cons, int n_cons, int pos, PosMask &m) {
+    Pool *pool = &c->pool;
+    hipStream_t s = c->stream;
+    KernelTimer *t = c->kt();
+    const int64_t n = c->types[pos_type].count;
+    const int64_t words = (n + 31) / 32;
+    bool first = true;
+    for (int q = 0; q < n_cons; ++q) {
+        const atp_constraint &k = cons[q];
+        if (k.position != pos) continue;
+        if (first) {
+            TRY(m.bits.alloc(pool, 4 * (size_t)std::max<int64_t>(words, 1)));
+        }
+        if (k.kind == ATP_C_RANGE) {
+            const Prop &p = *c->props[k.prop_id];
+            launch_mask_range(p.values.p, p.dtype, n, k.lo, k.hi, m.bits.as<uint32_t>(), first ? 0 : 1, s, t);
+        } else {
+            std::vector<int32_t> ids(k.ids, k.ids + k.n_ids);
+            std::sort(ids.begin(), ids.end());
+            ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+            Buf d_ids;
+            TRY(d_ids.alloc(pool, 4 * std::max<size_t>(ids.size(), 1)));
+            if (!ids.empty()) {
+                HIPTRY(hipMemcpyAsync(d_ids.p, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, s));
+                HIPTRY(hipStreamSynchronize(s));  // `ids` is released at the end of this scope
+            }
+            if (first) {
+                launch_fill_u32(m.bits.as<uint32_t>(), words, 0u, s, t);
+                launch_mask_ids(d_ids.as<int32_t>(), (int64_t)ids.size(), m.bits.as<uint32_t>(), s, t);
+            } else {
+                Buf tmpb;
+                TRY(tmpb.alloc(pool, 4 * (size_t)std::max<int64_t>(words, 1)));
+                launch_fill_u32(tmpb.as<uint32_t>(), words, 0u, s, t);
+                launch_mask_ids(d_ids.as<int32_t>(), (int64_t)ids.size(), tmpb.as<uint32_t>(), s, t);
+                launch_mask_and(m.bits.as<uint32_t>(), tmpb.as<uint32_t>(), words, s, t);
+                HIPTRY(hipStreamSynchronize(s));  // tmpb returns to the pool
+            }
+            if (m.n_ids < 0 || (int64_t)ids.size() < m.n_ids) {
+                m.n_ids = (int64_t)ids.size();
+                m.h_ids = ids;
+                m.ids = std::move(d_ids);
+            }
+        }
+        first = false;
+    }
+    if (!first) m.pop = 0;  // popcount filled in by the caller
+    return ATP_OK;
+}
+
+double est_rows_with_ids(const Rel &r, const std::vector<int32_t> &ids, double *nnz) {
+    double rows = 0, z = 0;
+    for (int32_t u : ids) {
+        int64_t d = r.h_rp[u + 1] - r.h_rp[u];
+        if (d > 0) {
+            rows += 1;
+            z += (double)d;
+        }
+    }
+    *nnz = z;
+    return rows;
+}
+
+const JunctionSketch &sketch_for(atp_ctx *c, int rin, int rout) {
+    auto key = std::make_pair(rin, rout);
+    auto it = c->sketches.find(key);
+    if (it != c->sketches.end()) return it->second;
+    const Rel &a = *c->rels[rin];
+    const Rel &b = *c->rels[rout];
+    JunctionSketch js = make_sketch(a.h_indeg.data(), b.h_rp.data(), (int64_t)b.h_rp.size() - 1);
+    return c->sketches.emplace(key, std::move(js)).first->second;
+}
+
+atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                     const atp_constraint *cons, int32_t n_cons, const char *plan, atp_result **out) {
+    if (out) *out = nullptr;
+    if (!c || !types || !out) return ATP_EINVAL;
+    if (c->broken) return ATP_EDEVICE;
+    if (n_types < 2) return ATP_EINVAL;
+    if (n_cons < 0 || (n_cons > 0 && !cons)) return ATP_EINVAL;
+    const int ntypes_reg = (int)c->types.size();
+    for (int i = 0; i < n_types; ++i)
+        if (types[i] < 0 || types[i] >= ntypes_reg) return ATP_EINVAL;
+    // relations of every step (Def. 2; one matrix per edge type)
+    const int p = n_types - 1;
+    std::vector<int> rel(p);
+    for (int i = 0; i < p; ++i) {
+        if (rel_ids) {
+            int r = rel_ids[i];
+            if (r < 0 || r >= (int)c->rels.size()) return ATP_EINVAL;
+            if (c->rels[r]->src != types[i] || c->rels[r]->dst != types[i + 1]) return ATP_ESCHEMA;
+            rel[i] = r;
+        } else {
+            int found = -1, nfound = 0;
+            for (int r = 0; r < (int)c->rels.size(); ++r)
+                if (c->rels[r]->src == types[i] && c->rels[r]->dst == types[i + 1]) {
+                    found = r;
+                    ++nfound;
+                }
+            if (nfound != 1) return ATP_ESCHEMA;
+            rel[i] = found;
+        }
+    }
+    for (int q = 0; q < n_cons; ++q) {
+        const atp_constraint &k = cons[q];
+        if (k.position < 0 || k.position >= n_types) return ATP_EINVAL;
+        if (k.kind == ATP_C_RANGE) {
+            if (k.prop_id < 0 || k.prop_id >= (int)c->props.size()) return ATP_EINVAL;
+            if (c->props[k.prop_id]->type != types[k.position]) return ATP_EINVAL;
+        } else if (k.kind == ATP_C_IDSET) {
+            if (k.n_ids < 0 || (k.n_ids > 0 && !k.ids)) return ATP_EINVAL;
+            const int64_t n = c->types[types[k.position]].count;
+            for (int64_t z = 0; z < k.n_ids; ++z)
+                if (k.ids[z] < 0 || k.ids[z] >= n) return ATP_EINVAL;
+        } else {
+            return ATP_EINVAL;
+        }
+    }
+    std::vector<PlanTree> forced;
+    int forced_root = -1;
+    if (plan && !parse_plan(plan, p, forced, forced_root)) return ATP_EINVAL;
+
+    hipStream_t s = c->stream;
+    KernelTimer *t = c->kt();
+    // masks M_1..M_n (Def. 3)
+    std::vector<PosMask> masks(n_types);
+    Buf pops;
+    TRY(pops.alloc(&c->pool, 8 * n_types));
+    launch_fill_i64(pops.as<int64_t>(), n_types, 0, s, t);
+    for (int i = 0; i < n_types; ++i) {
+        TRY(build_mask(c, types[i], cons, n_cons, i, masks[i]));
+        if (masks[i].pop >= 0)
+            launch_popcount(masks[i].bits.as<uint32_t>(), (c->types[types[i]].count + 31) / 32,
+                            pops.as<int64_t>() + i, s, t);
+    }
+    std::vector<int64_t> h_pop(n_types, 0);
+    HIPTRY(hipMemcpyAsync(h_pop.data(), pops.p, 8 * n_types, hipMemcpyDeviceToHost, s));
+    TRY(sync(c));
+    for (int i = 0; i < n_types; ++i)
+        if (masks[i].pop >= 0) masks[i].pop = h_pop[i];
+    auto sel_of = [&](int i) {
+        const double n = (double)c->types[types[i]].count;
+        return masks[i].pop >= 0 ? (n > 0 ? masks[i].pop / n : 0.0) : 1.0;
+    };
+
+    // leaves: relation i with masks of positions i and i+1
+    std::vector<Mat> leaves(p);
+    std::vector<ChainStats> lst(p);
+    for (int i = 0; i < p; ++i) {
+        const Rel &r = *c->rels[rel[i]];
+        Mat &L = leaves[i];
+        L.leaf = true;
+        L.rows = c->types[types[i]].count;
+        L.cols = c->types[types[i + 1]].count;
+        L.nnz = r.nnz;
+        L.op = Operand{r.rp.as<int64_t>(), r.col.as<int32_t>(), nullptr,
+                       masks[i].pop >= 0 ? masks[i].bits.as<uint32_t>() : nullptr,
+                       masks[i + 1].pop >= 0 ? masks[i + 1].bits.as<uint32_t>() : nullptr, L.rows, L.cols, r.nnz};
+        if (masks[i].n_ids >= 0) {
+            L.cand = masks[i].ids.as<int32_t>();
+            L.n_cand = masks[i].n_ids;
+        }
+        ChainStats cs;
+        cs.dim_r = (double)L.rows;
+        cs.dim_c = (double)L.cols;
+        const double sr = sel_of(i), sc = sel_of(i + 1);
+        if (masks[i].n_ids >= 0) {
+            double z = 0;
+            // rows of the id list with edges, thinned by any other constraint at the position
+            const double thin = masks[i].n_ids > 0 ? std::min(1.0, sr * L.rows / (double)masks[i].n_ids) : 0.0;
+            cs.rows = est_rows_with_ids(r, masks[i].h_ids, &z) * thin;
+            z *= thin;
+            cs.nnz = z * sc;
+        } else {
+            cs.rows = (double)r.nonempty_rows * sr;
+            cs.nnz = (double)r.nnz * sr * sc;
+        }
+        cs.cols = (double)r.nonempty_cols * sc;
+        lst[i] = cs;
+    }
+    std::string plan_str;
+    if (plan) {
+        plan_str = plan;
+    } else {
+        std::vector<JunctionSketch> js;
+        std::vector<double> jsel;
+        const bool uniform = (c->flags & ATP_OPT_PLAN_EAC) != 0;
+        for (int k = 0; k + 1 < p; ++k) {
+            if (!uniform) js.push_back(sketch_for(c, rel[k], rel[k + 1]));
+            jsel.push_back(sel_of(k + 1));
+        }
+        CostCoeffs cc;
+        PlanResult pr = plan_chain(lst, js, jsel, uniform ? Estimator::Uniform : Estimator::Sketch, cc);
+        plan_str = pr.plan;
+        if (!parse_plan(plan_str.c_str(), p, forced, forced_root)) return ATP_ESTATE;
+    }
+
+    // a single relation: multiply by the identity so the masked relation is
+    // materialised with values by the same kernels
+    Buf ident_rp, ident_col;
+    Mat ident;
+    if (p == 1) {
+        const int64_t n = leaves[0].cols;
+        TRY(ident_rp.alloc(&c->pool, 8 * (n + 1)));
+        TRY(ident_col.alloc(&c->pool, 4 * std::max<int64_t>(n, 1)));
+        std::vector<int64_t> h_rp(n + 1);
+        std::vector<int32_t> h_col(n);
+        for (int64_t z = 0; z <= n; ++z) h_rp[z] = z;
+        for (int64_t z = 0; z < n; ++z) h_col[z] = (int32_t)z;
+        HIPTRY(hipMemcpyAsync(ident_rp.p, h_rp.data(), 8 * (n + 1), hipMemcpyHostToDevice, s));
+        if (n) HIPTRY(hipMemcpyAsync(ident_col.p, h_col.data(), 4 * n, hipMemcpyHostToDevice, s));
+        TRY(sync(c));
+        ident.leaf = true;
+        ident.rows = ident.cols = n;
+        ident.nnz = n;
+        ident.op = Operand{ident_rp.as<int64_t>(), ident_col.as<int32_t>(), nullptr, nullptr, nullptr, n, n, n};
+    }
+
+    StepStats st;
+    int n_products = 0;
+    bool overflow = false;
+    std::vector<PlanTree> &tree = forced;
+    // post-order evaluation; returns the matrix of node `v` into `outm`
+    std::function<atp_status(int, bool, Mat &, int &, int &)> run =
+        [&](int v, bool as_left, Mat &outm, int &lo, int &hi) -> atp_status {
+        const PlanTree &nd = tree[v];
+        if (nd.leaf >= 0) {
+            lo = hi = nd.leaf;
+            outm = Mat();
+            outm.leaf = true;
+            const Mat &L = leaves[nd.leaf];
+            outm.op = L.op;
+            outm.rows = L.rows;
+            outm.cols = L.cols;
+            outm.nnz = L.nnz;
+            outm.cand = L.cand;
+            outm.n_cand = L.n_cand;
+            return ATP_OK;
+        }
+        Mat X, Y;
+        int l0, l1, r0, r1;
+        TRY(run(nd.left, true, X, l0, l1));
+        TRY(run(nd.right, false, Y, r0, r1));
+        lo = l0;
+        hi = r1;
+        const int last_pos = r1 + 1;  // metapath position of Y's last type
+        const int64_t ycols_eff = masks[last_pos].pop >= 0 ? masks[last_pos].pop : Y.cols;
+        bool sat = false;
+        TRY(spgemm(c, X, Y, ycols_eff, as_left, outm, st, sat));
+        ++n_products;
+        if (v == forced_root && sat) overflow = true;
+        return ATP_OK;
+    };
+    Mat R;
+    int lo = 0, hi = 0;
+    atp_status stt;
+    if (p == 1) {
+        const int64_t ycols_eff = masks[1].pop >= 0 ? masks[1].pop : leaves[0].cols;
+        Mat X;
+        X.leaf = true;
+        X.op = leaves[0].op;
+        X.op.cmask = nullptr;  // the column mask is applied through the identity's columns
+        X.rows = leaves[0].rows;
+        X.cols = leaves[0].cols;
+        X.nnz = leaves[0].nnz;
+        X.cand = leaves[0].cand;
+        X.n_cand = leaves[0].n_cand;
+        ident.op.cmask = leaves[0].op.cmask;
+        bool sat = false;
+        stt = spgemm(c, X, ident, ycols_eff, false, R, st, sat);
+        n_products = 1;
+        overflow = sat;
+    } else {
+        stt = run(forced_root, false, R, lo, hi);
+    }
+    if (stt != ATP_OK) {
+        if (stt == ATP_EDEVICE) c->broken = true;
+        (void)hipStreamSynchronize(s);
+        return stt;
+    }
+    HIPTRY(hipStreamSynchronize(s));
+    if (t) t->flush();
+    if (overflow) return ATP_EOVERFLOW;
+    atp_result *res = new atp_result();
+    res->ctx = c;
+    res->rows = R.rows;
+    res->cols = R.cols;
+    res->nnz = R.nnz;
+    res->rp = std::move(R.rp);
+    res->col = std::move(R.col);
+    res->val = std::move(R.val);
+    res->plan = plan_str;
+    res->stats.n_products = n_products;
+    res->stats.n_op_total = st.n_op;
+    res->stats.nnz_result = R.nnz;
+    res->stats.nnz_intermediate_total = st.nnz - R.nnz;
+    res->stats.slots_total = st.slots;
+    c->results.insert(res);
+    *out = res;
+    return ATP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+const char *atp_status_str(atp_status st) {
+    switch (st) {
+        case ATP_OK: return "ok";
+        case ATP_EINVAL: return "invalid argument";
+        case ATP_ENOMEM: return "device out of memory";
+        case ATP_EOVERFLOW: return "path count does not fit int64";
+        case ATP_ESCHEMA: return "metapath does not follow the schema";
+        case ATP_EDEVICE: return "HIP runtime error";
+        case ATP_EBUDGET: return "memory budget exceeded";
+        case ATP_ESTATE: return "invalid state";
+        default: return "unknown status";
+    }
+}
+
+atp_status atp_create(const atp_options *o, atp_ctx **out) {
+    if (!out) return ATP_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return ATP_ESTATE;
+    }
+    atp_options d{};
+    if (o) d = *o;
+    if (d.device < 0 || d.device >= ndev) return ATP_EINVAL;
+    if ((d.alloc == nullptr) != (d.free == nullptr)) return ATP_EINVAL;
+    if (hipSetDevice(d.device) != hipSuccess) return ATP_EDEVICE;
+    atp_ctx *c = new atp_ctx();
+    c->device = d.device;
+    c->stream = (hipStream_t)d.hip_stream;
+    c->flags = d.flags;
+    c->pool.user_alloc = d.alloc;
+    c->pool.user_free = d.free;
+    c->pool.user = d.alloc_user;
+    c->pool.budget = d.mem_budget_bytes;
+    if (hipHostMalloc((void **)&c->h_hdr, sizeof(StepHeader), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return ATP_ENOMEM;
+    }
+    *out = c;
+    return ATP_OK;
+}
+
+atp_status atp_destroy(atp_ctx *c) {
+    if (!c) return ATP_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (atp_result *r : c->results) delete r;
+    c->results.clear();
+    c->rels.clear();
+    c->props.clear();
+    c->timer.flush();
+    c->pool.destroy();
+    if (c->h_hdr) (void)hipHostFree(c->h_hdr);
+    delete c;
+    return ATP_OK;
+}
+
+atp_status atp_add_node_type(atp_ctx *c, const char *name, int64_t count, int32_t *type_id) {
+    if (!c || count < 0 || count >= (int64_t)0x7FFFFFFF) return ATP_EINVAL;
+    c->types.push_back(NodeType{name ? name : "", count});
+    if (type_id) *type_id = (int32_t)c->types.size() - 1;
+    return ATP_OK;
+}
+
+static atp_status add_rel_host(atp_ctx *c, int32_t src, int32_t dst, std::vector<int64_t> &&rp,
+                               std::vector<int32_t> &&col, int32_t *rel_id) {
+    auto r = std::make_unique<Rel>();
+    r->src = src;
+    r->dst = dst;
+    r->nnz = (int64_t)col.size();
+    const int64_t m = c->types[src].count, n = c->types[dst].count;
+    TRY(r->rp.alloc(&c->pool, 8 * (m + 1)));
+    TRY(r->col.alloc(&c->pool, 4 * std::max<int64_t>(r->nnz, 1)));
+    HIPTRY(hipMemcpyAsync(r->rp.p, rp.data(), 8 * (m + 1), hipMemcpyHostToDevice, c->stream));
+    if (r->nnz) HIPTRY(hipMemcpyAsync(r->col.p, col.data(), 4 * r->nnz, hipMemcpyHostToDevice, c->stream));
+    r->h_indeg.assign(n, 0);
+    for (int32_t j : col) r->h_indeg[j]++;
+    for (int64_t i = 0; i < m; ++i) r->nonempty_rows += rp[i + 1] > rp[i];
+    for (int64_t j = 0; j < n; ++j) r->nonempty_cols += r->h_indeg[j] > 0;
+    HIPTRY(hipStreamSynchronize(c->stream));
+    r->h_rp = std::move(rp);
+    c->rels.push_back(std::move(r));
+    if (rel_id) *rel_id = (int32_t)c->rels.size() - 1;
+    return ATP_OK;
+}
+
+atp_status atp_add_relation(atp_ctx *c, int32_t src, int32_t dst, const int64_t *row_ptr, const int32_t *col,
+                            int64_t nnz, uint32_t flags, int32_t *rel_id) {
+    if (!c || !row_ptr || nnz < 0 || (nnz > 0 && !col)) return ATP_EINVAL;
+    if (c->broken) return ATP_EDEVICE;
+    if (src < 0 || dst < 0 || src >= (int)c->types.size() || dst >= (int)c->types.size()) return ATP_EINVAL;
+    const int64_t m = c->types[src].count, n = c->types[dst].count;
+    std::vector<int64_t> rp(m + 1);
+    std::vector<int32_t> cl(nnz);
+    if (flags & ATP_REL_DEVICE_PTRS) {
+        HIPTRY(hipMemcpy(rp.data(), row_ptr, 8 * (m + 1), hipMemcpyDeviceToHost));
+        if (nnz) HIPTRY(hipMemcpy(cl.data(), col, 4 * nnz, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(rp.data(), row_ptr, 8 * (m + 1));
+        if (nnz) std::memcpy(cl.data(), col, 4 * nnz);
+    }
+    // validation: canonical CSR of a 0/1 matrix
+    if (rp[0] != 0 || rp[m] != nnz) return ATP_EINVAL;
+    for (int64_t i = 0; i < m; ++i) {
+        if (rp[i + 1] < rp[i]) return ATP_EINVAL;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (cl[e] < 0 || cl[e] >= n) return ATP_EINVAL;
+            if (e > rp[i] && cl[e] <= cl[e - 1]) return ATP_EINVAL;
+        }
+    }
+    std::vector<int64_t> trp;
+    std::vector<int32_t> tcol;
+    const bool rev = (flags & ATP_REL_ADD_REVERSE) != 0;
+    if (rev) {
+        trp.assign(n + 1, 0);
+        for (int32_t j : cl) trp[j + 1]++;
+        for (int64_t j = 0; j < n; ++j) trp[j + 1] += trp[j];
+        tcol.resize(nnz);
+        std::vector<int64_t> cur(trp.begin(), trp.end() - 1);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) tcol[cur[cl[e]]++] = (int32_t)i;
+    }
+    int32_t id = -1;
+    TRY(add_rel_host(c, src, dst, std::move(rp), std::move(cl), &id));
+    if (rev) {
+        int32_t id2 = -1;
+        TRY(add_rel_host(c, dst, src, std::move(trp), std::move(tcol), &id2));
+    }
+    if (rel_id) *rel_id = id;
+    return ATP_OK;
+}
+
+atp_status atp_add_property(atp_ctx *c, int32_t type_id, const char *name, int32_t dtype, const void *values,
+                            int32_t *prop_id) {
+    if (!c || type_id < 0 || type_id >= (int)c->types.size()) return ATP_EINVAL;
+    if (dtype != ATP_I16 && dtype != ATP_I32 && dtype != ATP_I64) return ATP_EINVAL;
+    const int64_t n = c->types[type_id].count;
+    if (n > 0 && !values) return ATP_EINVAL;
+    if (c->broken) return ATP_EDEVICE;
+    const size_t es = dtype == ATP_I16 ? 2 : dtype == ATP_I32 ? 4 : 8;
+    auto p = std::make_unique<Prop>();
+    p->type = type_id;
+    p->dtype = dtype;
+    p->name = name ? name : "";
+    TRY(p->values.alloc(&c->pool, es * std::max<int64_t>(n, 1)));
+    if (n) HIPTRY(hipMemcpyAsync(p->values.p, values, es * n, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    c->props.push_back(std::move(p));
+    if (prop_id) *prop_id = (int32_t)c->props.size() - 1;
+    return ATP_OK;
+}
+
+atp_status atp_eval(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                    const atp_constraint *cons, int32_t n_cons, atp_result **out) {
+    if (c) (void)hipSetDevice(c->device);
+    return eval_impl(c, types, n_types, rel_ids, cons, n_cons, nullptr, out);
+}
+
+atp_status atp_eval_plan(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                         const atp_constraint *cons, int32_t n_cons, const char *plan, atp_result **out) {
+    if (c) (void)hipSetDevice(c->device);
+    return eval_impl(c, types, n_types, rel_ids, cons, n_cons, plan, out);
+}
+
+atp_status atp_result_csr(const atp_result *r, int64_t *n_rows, int64_t *n_cols, int64_t *nnz,
+                          const int64_t **row_ptr, const int32_t **col, const int64_t **val) {
+    if (!r) return ATP_EINVAL;
+    if (n_rows) *n_rows = r->rows;
+    if (n_cols) *n_cols = r->cols;
+    if (nnz) *nnz = r->nnz;
+    if (row_ptr) *row_ptr = r->rp.as<int64_t>();
+    if (col) *col = r->col.as<int32_t>();
+    if (val) *val = r->val.as<int64_t>();
+    return ATP_OK;
+}
+
+atp_status atp_result_to_host(const atp_result *r, int64_t *row_ptr, int32_t *col, int64_t *val) {
+    if (!r) return ATP_EINVAL;
+    hipStream_t s = r->ctx->stream;
+    if (row_ptr) HIPTRY(hipMemcpyAsync(row_ptr, r->rp.p, 8 * (r->rows + 1), hipMemcpyDeviceToHost, s));
+    if (col && r->nnz) HIPTRY(hipMemcpyAsync(col, r->col.p, 4 * r->nnz, hipMemcpyDeviceToHost, s));
+    if (val && r->nnz) HIPTRY(hipMemcpyAsync(val, r->val.p, 8 * r->nnz, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    return ATP_OK;
+}
+
+atp_status atp_result_stats(const atp_result *r, atp_eval_stats *stats, char *plan, size_t plan_cap) {
+    if (!r) return ATP_EINVAL;
+    if (stats) *stats = r->stats;
+    if (plan && plan_cap) {
+        std::snprintf(plan, plan_cap, "%s", r->plan.c_str());
+    }
+    return ATP_OK;
+}
+
+atp_status atp_result_free(atp_result *r) {
+    if (!r) return ATP_EINVAL;
+    r->ctx->results.erase(r);
+    delete r;
+    return ATP_OK;
+}
+
+atp_status atp_plan_chain(int32_t n_mats, const int64_t *dims, const int64_t *nnz, double alpha, double beta,
+                          double gamma, int32_t dense, char *plan, size_t plan_cap, double *cost) {
+    if (n_mats < 1 || !dims || (!dense && !nnz)) return ATP_EINVAL;
+    const int p = n_mats;
+    if (dense) {
+        // standard product of Sec. 3.1: m*k*l operations per multiplication
+        std::vector<std::vector<double>> C(p, std::vector<double>(p, 0.0));
+        std::vector<std::vector<int>> S(p, std::vector<int>(p, -1));
+        for (int len = 2; len <= p; ++len)
+            for (int i = 0; i + len - 1 < p; ++i) {
+                int j = i + len - 1;
+                C[i][j] = 1e300;
+                for (int k = i; k < j; ++k) {
+                    double v = C[i][k] + C[k + 1][j] + (double)dims[i] * (double)dims[k + 1] * (double)dims[j + 1];
+                    if (v < C[i][j]) {
+                        C[i][j] = v;
+                        S[i][j] = k;
+                    }
+                }
+            }
+        std::function<std::string(int, int)> str = [&](int i, int j) -> std::string {
+            if (i == j) return std::to_string(i);
+            return "(" + str(i, S[i][j]) + "," + str(S[i][j] + 1, j) + ")";
+        };
+        std::string ps = str(0, p - 1);
+        if (plan && plan_cap) std::snprintf(plan, plan_cap, "%s", ps.c_str());
+        if (cost) *cost = C[0][p - 1];
+        return ATP_OK;
+    }
+    std::vector<ChainStats> leaves(p);
+    for (int i = 0; i < p; ++i) {
+        if (dims[i] < 0 || dims[i + 1] < 0 || nnz[i] < 0) return ATP_EINVAL;
+        leaves[i].dim_r = (double)dims[i];
+        leaves[i].dim_c = (double)dims[i + 1];
+        leaves[i].nnz = (double)nnz[i];
+        leaves[i].rows = (double)dims[i];
+        leaves[i].cols = (double)dims[i + 1];
+    }
+    CostCoeffs cc;
+    cc.alpha = alpha;
+    cc.beta = beta;
+    cc.gamma = gamma;
+    cc.delta = 0;
+    PlanResult pr = plan_chain(leaves, {}, {}, Estimator::Uniform, cc);
+    if (plan && plan_cap) std::snprintf(plan, plan_cap, "%s", pr.plan.c_str());
+    if (cost) *cost = pr.cost;
+    return ATP_OK;
+}
+
+int32_t atp_kernel_times(atp_ctx *c, const char **names, double *ms, int64_t *launches, int32_t cap) {
+    if (!c) return 0;
+    c->timer.flush();
+    int32_t n = 0;
+    for (auto &kv : c->timer.acc) {
+        if (n >= cap) break;
+        if (names) names[n] = kv.first.c_str();
+        if (ms) ms[n] = kv.second.first;
+        if (launches) launches[n] = kv.second.second;
+        ++n;
+    }
+    return n;
+}
+
+void atp_kernel_times_reset(atp_ctx *c) {
+    if (!c) return;
+    c->timer.flush();
+    c->timer.acc.clear();
+}
+
+int64_t atp_device_bytes(const atp_ctx *c) { return c ? c->pool.held : 0; }
+
+}  // extern "C"

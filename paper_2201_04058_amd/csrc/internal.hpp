@@ -1,0 +1,125 @@
+// Internal declarations shared by the host engine and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace atp {
+
+constexpr uint64_t kSat = 0x8000000000000000ull;  // saturated count (true value >= 2^63)
+constexpr int32_t kEmptyKey = 0x7FFFFFFF;          // empty hash slot; sorts after every column id
+
+// Dense LDS tile: TW columns of uint64 accumulators plus presence/saturation bitmaps.
+constexpr int kTileW = 8192;
+constexpr int kDenseThreads = 512;
+constexpr int kCursorCap = 512;     // X entries whose cursors fit in LDS (multi-tile chunks)
+constexpr int64_t kTaskOps = 32768; // target products per dense task
+
+// Hash bins: table sizes (slots); wave-level tables for small rows, block-level otherwise.
+enum Bin : int32_t {
+    BIN_NONE = 0,
+    BIN_W64, BIN_W128, BIN_W256, BIN_W512,         // one wavefront per row
+    BIN_B1024, BIN_B2048, BIN_B4096, BIN_B8192,    // one workgroup per row
+    BIN_DENSE,                                     // dense LDS tiles over column ranges
+    BIN_COUNT
+};
+
+// One operand of Z = X * Y.  Leaves are base relations (no values) and carry
+// the masks of their two metapath positions; products carry int64 values and
+// are already masked.
+struct Operand {
+    const int64_t *rp = nullptr;
+    const int32_t *col = nullptr;
+    const uint64_t *val = nullptr;   // nullptr: every stored entry is 1
+    const uint32_t *rmask = nullptr; // row mask bits (leaf X only)
+    const uint32_t *cmask = nullptr; // column mask bits (leaf only)
+    int64_t rows = 0, cols = 0, nnz = 0;
+};
+
+// Per-step device scratch header read back by the host (one small copy).
+struct StepHeader {
+    int64_t slots_total;      // sum of per-row upper bounds
+    int64_t segs_total;       // number of output segments
+    int64_t n_op_total;       // products
+    int64_t n_long;           // rows handed to the long-row symbolic kernel
+    int64_t bin_count[BIN_COUNT];
+    int64_t dense_tasks;      // dense-bin tasks
+    int64_t nnz_total;        // result nonzeros (after numeric)
+    int64_t n_active;         // non-empty result rows
+    int32_t saturated;        // some emitted value is saturated
+    int32_t pad;
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------------
+struct KernelTimer;  // host-side profiler hook (engine.cpp)
+
+void timer_begin(KernelTimer *t, const char *name, hipStream_t s);
+void timer_end(KernelTimer *t, hipStream_t s);
+
+void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s, KernelTimer *t);
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s, KernelTimer *t);
+
+// exclusive scan of n int64 values; out has n+1 entries (out[n] = total);
+// tmp must hold scan_tmp_elems(n) int64.
+int64_t scan_tmp_elems(int64_t n);
+void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s,
+                     KernelTimer *t);
+
+// masks
+void launch_mask_range(const void *prop, int32_t dtype, int64_t n, int64_t lo, int64_t hi,
+                       uint32_t *bits, int and_mode, hipStream_t s, KernelTimer *t);
+void launch_mask_ids(const int32_t *ids, int64_t n_ids, uint32_t *bits, hipStream_t s, KernelTimer *t);
+void launch_mask_and(uint32_t *dst, const uint32_t *src, int64_t words, hipStream_t s, KernelTimer *t);
+void launch_popcount(const uint32_t *bits, int64_t words, int64_t *out, hipStream_t s, KernelTimer *t);
+
+// symbolic: per candidate row the products, the upper bound, bin, segments
+struct SymbolicArgs {
+    Operand X, Y;
+    const int32_t *cand;      // candidate rows (ascending) or nullptr = all rows 0..n_cand-1
+    int64_t n_cand;
+    int64_t ycols_eff;        // columns that can appear (mask popcount or Y cols)
+    int64_t *nop;             // [n_cand]
+    int64_t *ub;              // [n_cand]
+    int64_t *nseg;            // [n_cand]
+    int32_t *bin;             // [n_cand]
+    int32_t *long_list;       // [n_cand] candidates with long X rows
+    int32_t *bin_lists;       // [BIN_COUNT * n_cand]
+    int64_t *dense_chunks;    // [n_cand] tasks per dense candidate (indexed by dense list position)
+    StepHeader *hdr;
+};
+void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t);
+void launch_bin_rows(const SymbolicArgs &a, hipStream_t s, KernelTimer *t);
+
+// numeric
+struct NumericArgs {
+    Operand X, Y;
+    const int32_t *cand;       // nullptr = identity
+    const int64_t *nop;        // [n_cand]
+    const int64_t *slot_off;   // [n_cand + 1]
+    const int64_t *seg_base;   // [n_cand + 1]
+    int64_t *row_cursor;       // [n_cand] (dense rows: reserved slots so far)
+    int32_t *slot_col;         // [slots_total]
+    uint64_t *slot_val;        // [slots_total]
+    int64_t *seg_cnt;          // [segs_total]
+    int64_t *seg_src;          // [segs_total]
+    int64_t *row_nnz;          // [X.rows] (zeroed)
+    StepHeader *hdr;
+    int64_t ycols;
+};
+void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const NumericArgs &a, hipStream_t s,
+                         KernelTimer *t);
+void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *task_base, int64_t n_tasks,
+                          const NumericArgs &a, hipStream_t s, KernelTimer *t);
+
+// compaction
+void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
+                          const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val,
+                          hipStream_t s, KernelTimer *t);
+void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row_nnz, int64_t *flags,
+                         hipStream_t s, KernelTimer *t);
+void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
+                           hipStream_t s, KernelTimer *t);
+void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s);
+
+}  // namespace atp

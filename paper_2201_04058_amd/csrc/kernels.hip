@@ -1,0 +1,843 @@
+// gfx950 kernels of the metapath SpGEMM chain.
+//
+// One sparse product Z = X * Y (paper Sec. 3.2, the sparse product that the
+// planner's Eq. 2 prices) runs as
+//   symbolic  per X row: products N_op (Eq. 2's N_op, exact here) and an upper
+//             bound ub = min(N_op, usable columns) on the row's nonzeros; the
+//             row is binned by ub;
+//   numeric   per bin: small rows accumulate in a wavefront-private LDS hash,
+//             mid rows in a workgroup LDS hash, long rows in dense LDS tiles
+//             over column ranges; hash rows are bitonic-sorted by column;
+//   compact   scan of per-row nonzeros -> row pointers; segments are copied
+//             from the ub-sized slots into exact-size arrays.
+// Constraints (the diagonal masks M_c of Sec. 2) are bitsets tested while the
+// operands are read.  Counts are int64 with saturation at 2^63: a count
+// reaching 2^63 is carried as the value 2^63, so every stored value equals
+// min(true count, 2^63) whatever the multiplication order.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace atp {
+
+namespace {
+
+constexpr int kLongRow = 256;  // X rows longer than this get a workgroup in the symbolic pass
+
+__device__ __forceinline__ bool bit_test(const uint32_t *b, int64_t i) {
+    return (b[i >> 5] >> (i & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b) {
+    if ((a | b) & kSat) return kSat;
+    uint64_t hi = __umul64hi(a, b);
+    uint64_t lo = a * b;
+    return (hi != 0 || (lo & kSat)) ? kSat : lo;
+}
+
+// Add contribution c to accumulator slot `slot` (value v, saturation bitmap
+// satw).  The first addition whose running sum reaches 2^63 sees an old value
+// below 2^63 and a new one at or above it, so the flag is exact.
+__device__ __forceinline__ void acc_add(unsigned long long *v, uint32_t *satw, uint32_t slot, uint64_t c) {
+    if (c & kSat) {
+        atomicOr(&satw[slot >> 5], 1u << (slot & 31));
+        return;
+    }
+    unsigned long long old = atomicAdd(v, (unsigned long long)c);
+    if (old < kSat && old + c >= kSat) atomicOr(&satw[slot >> 5], 1u << (slot & 31));
+}
+
+__device__ __forceinline__ int64_t lower_bound_col(const int32_t *col, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// lanes per X entry: power of two near the average Y-row length, in [1, 64]
+__device__ __forceinline__ int group_size(int64_t avg) {
+    int g = 1;
+    while (g < 64 && (int64_t)g * 2 <= avg + (avg >> 1)) g <<= 1;
+    return g;
+}
+
+__device__ __forceinline__ uint32_t hash_of(int32_t j, int log2s) {
+    return ((uint32_t)j * 0x9E3779B1u) >> (32 - log2s);
+}
+
+template <int S>
+__device__ __forceinline__ uint32_t hash_find(int32_t *keys, int32_t j) {
+    constexpr int L = __builtin_ctz(S);
+    uint32_t h = hash_of(j, L);
+    while (true) {
+        int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == j) return h;
+        if (k == kEmptyKey) {
+            int32_t prev = atomicCAS(&keys[h], kEmptyKey, j);
+            if (prev == kEmptyKey || prev == j) return h;
+        }
+        h = (h + 1) & (S - 1);
+    }
+}
+
+// Accumulate row i of X*Y into an LDS hash table.  Groups of g lanes walk one
+// X entry each; the lanes of a group stride over the Y row.
+template <int S>
+__device__ __forceinline__ void accumulate_hash(const Operand &X, const Operand &Y, int64_t xb, int64_t xe,
+                                                int gid, int ng, int li, int g, int32_t *keys,
+                                                unsigned long long *vals, uint32_t *satw) {
+    for (int64_t e = xb + gid; e < xe; e += ng) {
+        int32_t k = X.col[e];
+        if (X.cmask && !bit_test(X.cmask, k)) continue;
+        uint64_t xv = X.val ? X.val[e] : 1ull;
+        int64_t yb = Y.rp[k], ye = Y.rp[k + 1];
+        for (int64_t f = yb + li; f < ye; f += g) {
+            int32_t j = Y.col[f];
+            if (Y.cmask && !bit_test(Y.cmask, j)) continue;
+            uint64_t c = Y.val ? sat_mul(xv, Y.val[f]) : xv;
+            uint32_t h = hash_find<S>(keys, j);
+            acc_add(&vals[h], satw, h, c);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fills, scans
+
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// inclusive scan across a 256-thread block; returns the inclusive value, *total = block sum
+__device__ int64_t block_inclusive_scan(int64_t x, int64_t *smem_waves, int64_t *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    if (lane == 63) smem_waves[wave] = v;
+    __syncthreads();
+    int64_t pre = 0, tot = 0;
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) {
+        int64_t s = smem_waves[w];
+        if (w < wave) pre += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return v + pre;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int64_t *in, int64_t n, int64_t *tmp) {
+    __shared__ int64_t sw[kScanThreads / 64];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int64_t tot;
+    block_inclusive_scan(s, sw, &tot);
+    if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+}
+
+// exclusive scan of tmp[0..nb) in place, tmp[nb] = total; one block
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *tmp, int64_t nb) {
+    __shared__ int64_t sw[kScanThreads / 64];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        int64_t i = base + threadIdx.x;
+        int64_t x = i < nb ? tmp[i] : 0;
+        int64_t tot;
+        int64_t inc = block_inclusive_scan(x, sw, &tot);
+        if (i < nb) tmp[i] = carry + inc - x;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) tmp[nb] = carry;
+}
+
+// per block: exclusive scan of its tile with offset tmp[block]
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int64_t *in, int64_t *out, int64_t n,
+                                                             const int64_t *tmp, int64_t nb) {
+    __shared__ int64_t sw[kScanThreads / 64];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t x[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        int64_t i = base + r;
+        x[r] = i < n ? in[i] : 0;
+        s += x[r];
+    }
+    int64_t tot;
+    int64_t inc = block_inclusive_scan(s, sw, &tot);
+    int64_t run = tmp[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        int64_t i = base + r;
+        if (i < n) out[i] = run;
+        run += x[r];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tmp[nb];
+}
+
+// ---------------------------------------------------------------------------
+// masks (diagonal M_c as a bitset)
+
+template <typename T>
+__global__ void k_mask_range(const T *prop, int64_t n, int64_t lo, int64_t hi, uint32_t *bits, int64_t words,
+                             int and_mode) {
+    int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool keep = false;
+    if (gid < n) {
+        int64_t v = (int64_t)prop[gid];
+        keep = v >= lo && v <= hi;
+    }
+    uint64_t b = __ballot(keep);
+    if ((threadIdx.x & 63) == 0) {
+        int64_t w = gid >> 5;
+        uint32_t w0 = (uint32_t)b, w1 = (uint32_t)(b >> 32);
+        if (w < words) bits[w] = and_mode ? (bits[w] & w0) : w0;
+        if (w + 1 < words) bits[w + 1] = and_mode ? (bits[w + 1] & w1) : w1;
+    }
+}
+
+__global__ void k_mask_ids(const int32_t *ids, int64_t n, uint32_t *bits) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = ids[i];
+        atomicOr(&bits[v >> 5], 1u << (v & 31));
+    }
+}
+
+__global__ void k_mask_and(uint32_t *dst, const uint32_t *src, int64_t words) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] &= src[i];
+}
+
+__global__ void k_popcount(const uint32_t *bits, int64_t words, int64_t *out) {
+    int64_t s = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        s += __popc(bits[i]);
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)out, (unsigned long long)s);
+}
+
+// ---------------------------------------------------------------------------
+// symbolic pass
+
+__global__ void k_symbolic(SymbolicArgs a) {
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= a.n_cand) return;
+    int64_t i = a.cand ? a.cand[c] : c;
+    int64_t nop = 0;
+    if (!(a.X.rmask && !bit_test(a.X.rmask, i))) {
+        int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
+        if (e - b > kLongRow) {
+            unsigned long long slot = atomicAdd((unsigned long long *)&a.hdr->n_long, 1ull);
+            a.long_list[slot] = (int32_t)c;
+            a.nop[c] = 0;
+            return;
+        }
+        for (int64_t p = b; p < e; ++p) {
+            int32_t k = a.X.col[p];
+            if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
+            nop += a.Y.rp[k + 1] - a.Y.rp[k];
+        }
+    }
+    a.nop[c] = nop;
+}
+
+__global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a) {
+    __shared__ int64_t sw[4];
+    const int64_t n_long = a.hdr->n_long;
+    for (int64_t t = blockIdx.x; t < n_long; t += gridDim.x) {
+        int32_t c = a.long_list[t];
+        int64_t i = a.cand ? a.cand[c] : c;
+        int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
+        int64_t s = 0;
+        for (int64_t p = b + threadIdx.x; p < e; p += blockDim.x) {
+            int32_t k = a.X.col[p];
+            if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
+            s += a.Y.rp[k + 1] - a.Y.rp[k];
+        }
+        int64_t tot;
+        block_inclusive_scan(s, sw, &tot);
+        if (threadIdx.x == 0) a.nop[c] = tot;
+    }
+}
+
+__global__ void k_bin_rows(SymbolicArgs a) {
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= a.n_cand) return;
+    int64_t nop = a.nop[c];
+    int64_t ub = nop < a.ycols_eff ? nop : a.ycols_eff;
+    int32_t bin = BIN_NONE;
+    int64_t nseg = 0;
+    const int64_t ycols = a.Y.cols;
+    const int64_t ntiles = (ycols + kTileW - 1) / kTileW;
+    if (ub > 0) {
+        if (ub > 4096 || (ycols <= kTileW && ycols <= 8 * ub)) {
+            bin = BIN_DENSE;
+            nseg = ntiles;
+        } else {
+            nseg = 1;
+            bin = ub <= 32 ? BIN_W64 : ub <= 64 ? BIN_W128 : ub <= 128 ? BIN_W256 : ub <= 256 ? BIN_W512
+                : ub <= 512 ? BIN_B1024 : ub <= 1024 ? BIN_B2048 : ub <= 2048 ? BIN_B4096 : BIN_B8192;
+        }
+        atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)nop);
+    }
+    a.ub[c] = ub;
+    a.nseg[c] = nseg;
+    a.bin[c] = bin;
+    if (bin != BIN_NONE) {
+        unsigned long long pos = atomicAdd((unsigned long long *)&a.hdr->bin_count[bin], 1ull);
+        a.bin_lists[(int64_t)bin * a.n_cand + (int64_t)pos] = (int32_t)c;
+        if (bin == BIN_DENSE) {
+            int64_t nch = 1;
+            if (ntiles > 1) {
+                int64_t i = a.cand ? a.cand[c] : c;
+                int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
+                if (xlen <= kCursorCap) {
+                    nch = (nop + kTaskOps - 1) / kTaskOps;
+                    nch = nch < 1 ? 1 : (nch > ntiles ? ntiles : nch);
+                    int64_t tpc = (ntiles + nch - 1) / nch;
+                    nch = (ntiles + tpc - 1) / tpc;
+                } else {
+                    nch = ntiles;
+                }
+            }
+            a.dense_chunks[pos] = nch;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric: LDS hash, one wavefront per row
+
+template <int S>
+__device__ void bitonic_sort_wave(int32_t *keys, unsigned long long *vals, int lane) {
+    for (int k = 2; k <= S; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < S / 2; t += 64) {
+                int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                int b = a + j;
+                bool up = (a & k) == 0;
+                int32_t ka = keys[a], kb = keys[b];
+                if ((ka > kb) == up) {
+                    keys[a] = kb;
+                    keys[b] = ka;
+                    unsigned long long va = vals[a];
+                    vals[a] = vals[b];
+                    vals[b] = va;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t n, NumericArgs a) {
+    __shared__ int32_t keys_all[4][S];
+    __shared__ unsigned long long vals_all[4][S];
+    __shared__ uint32_t sat_all[4][(S + 31) / 32];
+    __shared__ int cnt_all[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t *keys = keys_all[wave];
+    unsigned long long *vals = vals_all[wave];
+    uint32_t *satw = sat_all[wave];
+    for (int t = lane; t < S; t += 64) {
+        keys[t] = kEmptyKey;
+        vals[t] = 0;
+    }
+    for (int t = lane; t < (S + 31) / 32; t += 64) satw[t] = 0;
+    if (lane == 0) cnt_all[wave] = 0;
+    wave_sync();
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < n; r += (int64_t)gridDim.x * 4) {
+        const int32_t c = list[r];
+        const int64_t i = a.cand ? a.cand[c] : c;
+        const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
+        const int64_t xlen = xe - xb;
+        const int g = group_size(a.nop[c] / (xlen > 0 ? xlen : 1));
+        accumulate_hash<S>(a.X, a.Y, xb, xe, lane / g, 64 / g, lane % g, g, keys, vals, satw);
+        wave_sync();
+        int local = 0;
+        for (int t = lane; t < S; t += 64) {
+            if (keys[t] != kEmptyKey) {
+                ++local;
+                if ((satw[t >> 5] >> (t & 31)) & 1u) vals[t] = kSat;
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) local += __shfl_xor(local, d, 64);
+        wave_sync();
+        bitonic_sort_wave<S>(keys, vals, lane);
+        const int64_t off = a.slot_off[c];
+        bool sat = false;
+        for (int t = lane; t < local; t += 64) {
+            a.slot_col[off + t] = keys[t];
+            unsigned long long v = vals[t];
+            a.slot_val[off + t] = v;
+            sat |= (v & kSat) != 0;
+            keys[t] = kEmptyKey;
+            vals[t] = 0;
+        }
+        if (__ballot(sat) != 0 && lane == 0) atomicOr(&a.hdr->saturated, 1);
+        for (int t = lane; t < (S + 31) / 32; t += 64) satw[t] = 0;
+        if (lane == 0) {
+            const int64_t sb = a.seg_base[c];
+            a.seg_cnt[sb] = local;
+            a.seg_src[sb] = off;
+            a.row_nnz[i] = local;
+        }
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric: LDS hash, one workgroup per row
+
+template <int S, int NT>
+__device__ void bitonic_sort_block(int32_t *keys, unsigned long long *vals) {
+    for (int k = 2; k <= S; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < S / 2; t += NT) {
+                int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                int b = a + j;
+                bool up = (a & k) == 0;
+                int32_t ka = keys[a], kb = keys[b];
+                if ((ka > kb) == up) {
+                    keys[a] = kb;
+                    keys[b] = ka;
+                    unsigned long long va = vals[a];
+                    vals[a] = vals[b];
+                    vals[b] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int S, int NT>
+__global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t n, NumericArgs a) {
+    __shared__ int32_t keys[S];
+    __shared__ unsigned long long vals[S];
+    __shared__ uint32_t satw[S / 32];
+    __shared__ int cnt;
+    __shared__ int any_sat;
+    for (int t = threadIdx.x; t < S; t += NT) {
+        keys[t] = kEmptyKey;
+        vals[t] = 0;
+    }
+    for (int t = threadIdx.x; t < S / 32; t += NT) satw[t] = 0;
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        any_sat = 0;
+    }
+    __syncthreads();
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const int32_t c = list[r];
+        const int64_t i = a.cand ? a.cand[c] : c;
+        const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
+        const int64_t xlen = xe - xb;
+        const int g = group_size(a.nop[c] / (xlen > 0 ? xlen : 1));
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int gpw = 64 / g;  // groups per wave
+        accumulate_hash<S>(a.X, a.Y, xb, xe, wave * gpw + lane / g, (NT / 64) * gpw, lane % g, g, keys, vals, satw);
+        __syncthreads();
+        int local = 0;
+        for (int t = threadIdx.x; t < S; t += NT) {
+            if (keys[t] != kEmptyKey) {
+                ++local;
+                if ((satw[t >> 5] >> (t & 31)) & 1u) vals[t] = kSat;
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) local += __shfl_xor(local, d, 64);
+        if (lane == 0 && local) atomicAdd(&cnt, local);
+        __syncthreads();
+        bitonic_sort_block<S, NT>(keys, vals);
+        const int total = cnt;
+        const int64_t off = a.slot_off[c];
+        bool sat = false;
+        for (int t = threadIdx.x; t < total; t += NT) {
+            a.slot_col[off + t] = keys[t];
+            unsigned long long v = vals[t];
+            a.slot_val[off + t] = v;
+            sat |= (v & kSat) != 0;
+            keys[t] = kEmptyKey;
+            vals[t] = 0;
+        }
+        if (sat) any_sat = 1;
+        for (int t = threadIdx.x; t < S / 32; t += NT) satw[t] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int64_t sb = a.seg_base[c];
+            a.seg_cnt[sb] = total;
+            a.seg_src[sb] = off;
+            a.row_nnz[i] = total;
+            if (any_sat) atomicOr(&a.hdr->saturated, 1);
+            cnt = 0;
+            any_sat = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// numeric: dense LDS tiles over column ranges
+
+__global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, int64_t n_list, const int64_t *task_base,
+                                                         int64_t n_tasks, NumericArgs a) {
+    constexpr int W = kTileW;
+    constexpr int NW = W / 32;  // bitmap words per tile
+    __shared__ unsigned long long acc[W];
+    __shared__ uint32_t pres[NW];
+    __shared__ uint32_t satw[NW];
+    __shared__ unsigned long long cur[kCursorCap];
+    __shared__ unsigned long long nxt[kCursorCap];
+    __shared__ int64_t sw[kDenseThreads / 64];
+    __shared__ int64_t s_task[4];
+    __shared__ int64_t s_base;
+    __shared__ int s_sat;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < W; t += kDenseThreads) acc[t] = 0;
+    for (int t = tid; t < NW; t += kDenseThreads) {
+        pres[t] = 0;
+        satw[t] = 0;
+    }
+    if (tid == 0) s_sat = 0;
+    __syncthreads();
+    const int64_t ycols = a.ycols;
+    const int64_t ntiles = (ycols + W - 1) / W;
+    for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        if (tid == 0) {
+            int64_t lo = 0, hi = n_list;  // last p with task_base[p] <= task
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) >> 1;
+                if (task_base[mid] <= task)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            s_task[0] = lo;
+            s_task[1] = task - task_base[lo];
+            s_task[2] = task_base[lo + 1] - task_base[lo];
+        }
+        __syncthreads();
+        const int64_t p = s_task[0], q = s_task[1], nch = s_task[2];
+        const int32_t c = list[p];
+        const int64_t i = a.cand ? a.cand[c] : c;
+        const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
+        const int64_t xlen = xe - xb;
+        const int64_t tpc = (ntiles + nch - 1) / nch;
+        const int64_t t0 = q * tpc;
+        const int64_t t1 = (t0 + tpc < ntiles) ? t0 + tpc : ntiles;
+        const bool use_cursor = (t1 - t0) > 1;
+        int64_t avg = a.nop[c] / ((xlen > 0 ? xlen : 1) * (ntiles > 0 ? ntiles : 1));
+        const int g = group_size(avg);
+        const int lane = tid & 63, wave = tid >> 6;
+        const int gpw = 64 / g;
+        const int gid = wave * gpw + lane / g, ng = (kDenseThreads / 64) * gpw, li = lane % g;
+        if (use_cursor) {
+            for (int64_t e = tid; e < xlen; e += kDenseThreads) {
+                int32_t k = a.X.col[xb + e];
+                int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
+                cur[e] = (t0 == 0) ? yb : lower_bound_col(a.Y.col, yb, ye, (int32_t)(t0 * W));
+                nxt[e] = ~0ull;
+            }
+            __syncthreads();
+        }
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t c0 = t * W;
+            const int64_t c1 = (c0 + W < ycols) ? c0 + W : ycols;
+            for (int64_t e = gid; e < xlen; e += ng) {
+                int32_t k = a.X.col[xb + e];
+                if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
+                uint64_t xv = a.X.val ? a.X.val[xb + e] : 1ull;
+                int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
+                int64_t s = use_cursor ? (int64_t)cur[e] : (c0 == 0 ? yb : lower_bound_col(a.Y.col, yb, ye, (int32_t)c0));
+                int64_t brk = ye;
+                for (int64_t f = s + li; f < ye; f += g) {
+                    int32_t j = a.Y.col[f];
+                    if (j >= c1) {
+                        brk = f;
+                        break;
+                    }
+                    if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
+                    uint64_t v = a.Y.val ? sat_mul(xv, a.Y.val[f]) : xv;
+                    uint32_t slot = (uint32_t)(j - c0);
+                    atomicOr(&pres[slot >> 5], 1u << (slot & 31));
+                    acc_add(&acc[slot], satw, slot, v);
+                }
+                if (use_cursor) atomicMin(&nxt[e], (unsigned long long)brk);
+            }
+            __syncthreads();
+            // emit the tile in column order
+            uint32_t word = tid < NW ? pres[tid] : 0u;
+            int64_t cntw = __popc(word);
+            int64_t tot;
+            int64_t inc = block_inclusive_scan(cntw, sw, &tot);
+            if (tid == 0) s_base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c],
+                                                                (unsigned long long)tot)
+                                           : 0;
+            __syncthreads();
+            if (tot > 0) {
+                const int64_t off = a.slot_off[c] + s_base;
+                int64_t pos = off + inc - cntw;
+                bool sat = false;
+                if (tid < NW) {
+                    uint32_t sw_bits = satw[tid];
+                    uint32_t wbits = word;
+                    while (wbits) {
+                        int b = __builtin_ctz(wbits);
+                        wbits &= wbits - 1;
+                        int slot = tid * 32 + b;
+                        unsigned long long v = ((sw_bits >> b) & 1u) ? kSat : acc[slot];
+                        sat |= (v & kSat) != 0;
+                        a.slot_col[pos] = (int32_t)(c0 + slot);
+                        a.slot_val[pos] = v;
+                        ++pos;
+                        acc[slot] = 0;
+                    }
+                    pres[tid] = 0;
+                    satw[tid] = 0;
+                }
+                if (sat) s_sat = 1;
+                if (tid == 0) {
+                    const int64_t sg = a.seg_base[c] + t;
+                    a.seg_cnt[sg] = tot;
+                    a.seg_src[sg] = off;
+                    atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)tot);
+                }
+            }
+            if (use_cursor) {
+                __syncthreads();
+                for (int64_t e = tid; e < xlen; e += kDenseThreads) {
+                    cur[e] = nxt[e];
+                    nxt[e] = ~0ull;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && s_sat) atomicOr(&a.hdr->saturated, 1);
+}
+
+// ---------------------------------------------------------------------------
+// compaction
+
+__global__ void k_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
+                                const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t sgm = wave; sgm < n_segs; sgm += nwaves) {
+        const int64_t n = seg_cnt[sgm];
+        if (n == 0) continue;
+        const int64_t src = seg_src[sgm], dst = seg_dst[sgm];
+        for (int64_t t = lane; t < n; t += 64) {
+            col[dst + t] = slot_col[src + t];
+            val[dst + t] = slot_val[src + t];
+        }
+    }
+}
+
+__global__ void k_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row_nnz, int64_t *flags) {
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n_cand) return;
+    int64_t i = cand ? cand[c] : c;
+    flags[c] = row_nnz[i] > 0 ? 1 : 0;
+}
+
+__global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *scan, int32_t *active) {
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n_cand) return;
+    if (scan[c + 1] != scan[c]) active[scan[c]] = cand ? cand[c] : (int32_t)c;
+}
+
+__global__ void k_copy_i64(const int64_t *src, int64_t *dst) { *dst = *src; }
+
+inline int grid_for(int64_t n, int threads, int64_t cap = 1 << 20) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+
+#define ATP_LAUNCH(name, grid, block, stream, ...)                    \
+    do {                                                              \
+        timer_begin(t, name, stream);                                 \
+        hipLaunchKernelGGL(__VA_ARGS__);                              \
+        timer_end(t, stream);                                         \
+    } while (0)
+
+void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s, KernelTimer *t) {
+    if (n <= 0) return;
+    ATP_LAUNCH("fill", 0, 0, s, k_fill_i64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+}
+
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s, KernelTimer *t) {
+    if (n <= 0) return;
+    ATP_LAUNCH("fill", 0, 0, s, k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 2; }
+
+void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1) nb = 1;
+    ATP_LAUNCH("scan", 0, 0, s, k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, tmp);
+    ATP_LAUNCH("scan", 0, 0, s, k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb);
+    ATP_LAUNCH("scan", 0, 0, s, k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+               (const int64_t *)tmp, nb);
+}
+
+void launch_mask_range(const void *prop, int32_t dtype, int64_t n, int64_t lo, int64_t hi, uint32_t *bits,
+                       int and_mode, hipStream_t s, KernelTimer *t) {
+    int64_t words = (n + 31) / 32;
+    int64_t threads = ((n + 63) / 64) * 64;
+    dim3 g(grid_for(threads, 256)), b(256);
+    if (threads > (int64_t)g.x * 256) return;  // cannot happen below 2^28 nodes
+    if (dtype == 1)
+        ATP_LAUNCH("mask", 0, 0, s, k_mask_range<int16_t>, g, b, 0, s, (const int16_t *)prop, n, lo, hi, bits, words,
+                   and_mode);
+    else if (dtype == 2)
+        ATP_LAUNCH("mask", 0, 0, s, k_mask_range<int32_t>, g, b, 0, s, (const int32_t *)prop, n, lo, hi, bits, words,
+                   and_mode);
+    else
+        ATP_LAUNCH("mask", 0, 0, s, k_mask_range<int64_t>, g, b, 0, s, (const int64_t *)prop, n, lo, hi, bits, words,
+                   and_mode);
+}
+
+void launch_mask_ids(const int32_t *ids, int64_t n_ids, uint32_t *bits, hipStream_t s, KernelTimer *t) {
+    if (n_ids <= 0) return;
+    ATP_LAUNCH("mask", 0, 0, s, k_mask_ids, dim3(grid_for(n_ids, 256, 4096)), dim3(256), 0, s, ids, n_ids, bits);
+}
+
+void launch_mask_and(uint32_t *dst, const uint32_t *src, int64_t words, hipStream_t s, KernelTimer *t) {
+    if (words <= 0) return;
+    ATP_LAUNCH("mask", 0, 0, s, k_mask_and, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s, dst, src, words);
+}
+
+void launch_popcount(const uint32_t *bits, int64_t words, int64_t *out, hipStream_t s, KernelTimer *t) {
+    if (words <= 0) return;
+    ATP_LAUNCH("mask", 0, 0, s, k_popcount, dim3(grid_for(words, 256, 2048)), dim3(256), 0, s, bits, words, out);
+}
+
+void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
+    if (a.n_cand <= 0) return;
+    if ((a.n_cand + 255) / 256 > 0x7FFFFFFF) return;
+    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic, dim3((unsigned)((a.n_cand + 255) / 256)), dim3(256), 0, s, a);
+    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic_long, dim3(device_cus() * 4), dim3(256), 0, s, a);
+}
+
+void launch_bin_rows(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
+    if (a.n_cand <= 0) return;
+    ATP_LAUNCH("binning", 0, 0, s, k_bin_rows, dim3((unsigned)((a.n_cand + 255) / 256)), dim3(256), 0, s, a);
+}
+
+void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const NumericArgs &a, hipStream_t s,
+                         KernelTimer *t) {
+    if (n <= 0) return;
+    const int cus = device_cus();
+    auto waves = [&](int per_block) { return dim3((unsigned)grid_for(n, per_block, (int64_t)cus * 16)); };
+    switch (bin) {
+        case BIN_W64: ATP_LAUNCH("hash_wave", 0, 0, s, k_hash_wave<64>, waves(4), dim3(256), 0, s, list, n, a); break;
+        case BIN_W128: ATP_LAUNCH("hash_wave", 0, 0, s, k_hash_wave<128>, waves(4), dim3(256), 0, s, list, n, a); break;
+        case BIN_W256: ATP_LAUNCH("hash_wave", 0, 0, s, k_hash_wave<256>, waves(4), dim3(256), 0, s, list, n, a); break;
+        case BIN_W512: ATP_LAUNCH("hash_wave", 0, 0, s, k_hash_wave<512>, waves(4), dim3(256), 0, s, list, n, a); break;
+        case BIN_B1024:
+            ATP_LAUNCH("hash_block", 0, 0, s, (k_hash_block<1024, 256>), waves(1), dim3(256), 0, s, list, n, a);
+            break;
+        case BIN_B2048:
+            ATP_LAUNCH("hash_block", 0, 0, s, (k_hash_block<2048, 256>), waves(1), dim3(256), 0, s, list, n, a);
+            break;
+        case BIN_B4096:
+            ATP_LAUNCH("hash_block", 0, 0, s, (k_hash_block<4096, 512>), waves(1), dim3(512), 0, s, list, n, a);
+            break;
+        case BIN_B8192:
+            ATP_LAUNCH("hash_block", 0, 0, s, (k_hash_block<8192, 512>), waves(1), dim3(512), 0, s, list, n, a);
+            break;
+        default: break;
+    }
+}
+
+void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *task_base, int64_t n_tasks,
+                          const NumericArgs &a, hipStream_t s, KernelTimer *t) {
+    if (n_tasks <= 0) return;
+    const int cus = device_cus();
+    int64_t g = n_tasks < (int64_t)cus * 2 ? n_tasks : (int64_t)cus * 2;
+    ATP_LAUNCH("dense", 0, 0, s, k_dense, dim3((unsigned)g), dim3(kDenseThreads), 0, s, list, n_list, task_base,
+               n_tasks, a);
+}
+
+void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
+                          const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val,
+                          hipStream_t s, KernelTimer *t) {
+    if (n_segs <= 0) return;
+    const int cus = device_cus();
+    ATP_LAUNCH("copy", 0, 0, s, k_copy_segments, dim3(grid_for(n_segs * 64, 256, (int64_t)cus * 8)), dim3(256), 0, s,
+               seg_cnt, seg_src, seg_dst, n_segs, slot_col, slot_val, col, val);
+}
+
+void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row_nnz, int64_t *flags,
+                         hipStream_t s, KernelTimer *t) {
+    if (n_cand <= 0) return;
+    ATP_LAUNCH("active", 0, 0, s, k_active_flags, dim3((unsigned)((n_cand + 255) / 256)), dim3(256), 0, s, cand,
+               n_cand, row_nnz, flags);
+}
+
+void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
+                           hipStream_t s, KernelTimer *t) {
+    if (n_cand <= 0) return;
+    ATP_LAUNCH("active", 0, 0, s, k_active_scatter, dim3((unsigned)((n_cand + 255) / 256)), dim3(256), 0, s, cand,
+               n_cand, flags_scan, active);
+}
+
+void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, scan_total, dst);
+}
+
+}  // namespace atp

@@ -1,0 +1,223 @@
+// Chain-order planner: the dynamic program of Sec. 3.1 (Eq. 1) over the
+// sparse product cost of Sec. 3.2 (Eq. 2),
+//     c(X*Y) = alpha*nnz(X) + beta*N_op + gamma*nnz(Z)  (+ delta per product),
+// with two estimators for N_op and nnz(Z):
+//   Uniform  the paper's average-case E_ac: nonzeros spread uniformly, so
+//            N_op = nnz(X)*nnz(Y)/k and rho_Z = 1 - (1 - rho_X*rho_Y)^k;
+//   Sketch   degree-aware: the columns of X follow the in-degree of the
+//            junction type under the last relation of X, the rows of Y follow
+//            the out-degree under the first relation of Y (joint log2 buckets
+//            of both degrees), each capped by the other operand's extent; the
+//            result density is E_ac applied to the N_op products over the
+//            active block.  This is exact for N_op when X and Y are single
+//            relations and catches the hub rows that the uniform estimate
+//            misses.
+// The order never changes the result (associativity), only its cost.
+#include "planner.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <map>
+
+namespace atp {
+
+double eac_density(double rx, double ry, double k) {
+    double r = rx * ry;
+    if (r <= 0 || k <= 0) return 0.0;
+    if (r >= 1) return 1.0;
+    double d = -std::expm1(k * std::log1p(-r));
+    return d < 0 ? 0 : (d > 1 ? 1 : d);
+}
+
+static double sat_fill(double n_op, double cells) {
+    // expected occupied cells after n_op uniform throws into `cells` cells
+    if (cells <= 0 || n_op <= 0) return 0;
+    return cells * -std::expm1(-n_op / cells);
+}
+
+ChainStats estimate_product(const ChainStats &x, const ChainStats &y, const JunctionSketch *j, double sel,
+                            Estimator est, double *n_op_out) {
+    ChainStats z;
+    z.dim_r = x.dim_r;
+    z.dim_c = y.dim_c;
+    double n_op;
+    const bool uniform = est == Estimator::Uniform || j == nullptr || j->sum_in <= 0 || j->sum_out <= 0;
+    if (uniform) {
+        const double k = x.dim_c;
+        const double rx = (x.dim_r * k) > 0 ? x.nnz / (x.dim_r * k) : 0;
+        const double ry = (k * y.dim_c) > 0 ? y.nnz / (k * y.dim_c) : 0;
+        n_op = k > 0 ? x.nnz * y.nnz / k : 0;
+        const double rz = eac_density(rx, ry, k);
+        z.nnz = x.dim_r * y.dim_c * rz;
+        z.rows = x.rows;
+        z.cols = y.cols;
+        if (n_op_out) *n_op_out = n_op;
+        return z;
+    }
+    {
+        const double sin = j->sum_in * sel, sout = j->sum_out * sel;
+        const double ax = sin > 0 ? x.nnz / sin : 0;
+        const double ay = sout > 0 ? y.nnz / sout : 0;
+        double s = 0;
+        for (const auto &b : j->buckets) {
+            double cx = std::min(ax * b.in, x.rows);
+            double ry = std::min(ay * b.out, y.cols);
+            s += b.n * cx * ry;
+        }
+        n_op = s * sel;
+        z.rows = x.rows * -std::expm1(-(x.rows > 0 ? n_op / x.rows : 0));
+        z.cols = y.cols * -std::expm1(-(y.cols > 0 ? n_op / y.cols : 0));
+        z.nnz = std::min(n_op, sat_fill(n_op, z.rows * z.cols));
+    }
+    if (n_op_out) *n_op_out = n_op;
+    return z;
+}
+
+PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<JunctionSketch> &junctions,
+                      const std::vector<double> &junction_sel, Estimator est, const CostCoeffs &cc) {
+    const int p = (int)leaves.size();
+    PlanResult out;
+    if (p == 0) return out;
+    std::vector<std::vector<double>> C(p, std::vector<double>(p, 0.0));
+    std::vector<std::vector<int>> S(p, std::vector<int>(p, -1));
+    std::vector<std::vector<ChainStats>> D(p, std::vector<ChainStats>(p));
+    for (int i = 0; i < p; ++i) D[i][i] = leaves[i];
+    for (int len = 2; len <= p; ++len) {
+        for (int i = 0; i + len - 1 < p; ++i) {
+            const int j = i + len - 1;
+            double best = std::numeric_limits<double>::infinity();
+            for (int k = i; k < j; ++k) {
+                const JunctionSketch *js = k < (int)junctions.size() ? &junctions[k] : nullptr;
+                const double sel = k < (int)junction_sel.size() ? junction_sel[k] : 1.0;
+                double n_op = 0;
+                ChainStats z = estimate_product(D[i][k], D[k + 1][j], js, sel, est, &n_op);
+                double c = C[i][k] + C[k + 1][j] + cc.alpha * D[i][k].nnz + cc.beta * n_op + cc.gamma * z.nnz +
+                           cc.delta;
+                if (c < best) {  // strict: ties keep the smallest split
+                    best = c;
+                    S[i][j] = k;
+                    D[i][j] = z;
+                }
+            }
+            C[i][j] = best;
+        }
+    }
+    std::function<std::string(int, int)> str = [&](int i, int j) -> std::string {
+        if (i == j) {
+            out.node_stats.push_back(D[i][i]);
+            return std::to_string(i);
+        }
+        const int k = S[i][j];
+        std::string l = str(i, k), r = str(k + 1, j);
+        out.node_stats.push_back(D[i][j]);
+        return "(" + l + "," + r + ")";
+    };
+    out.plan = str(0, p - 1);
+    out.cost = C[0][p - 1];
+    return out;
+}
+
+JunctionSketch make_sketch(const int32_t *in_deg, const int64_t *out_row_ptr, int64_t n) {
+    JunctionSketch js;
+    std::map<int, JunctionSketch::Bucket> acc;
+    auto lg = [](int64_t d) {
+        int b = 0;
+        while ((d >> b) > 1) ++b;
+        return d > 0 ? b + 1 : 0;
+    };
+    for (int64_t b = 0; b < n; ++b) {
+        const int64_t di = in_deg[b];
+        const int64_t dout = out_row_ptr[b + 1] - out_row_ptr[b];
+        js.sum_in += (double)di;
+        js.sum_out += (double)dout;
+        if (di == 0 || dout == 0) continue;
+        auto &bk = acc[lg(di) * 64 + lg(dout)];
+        bk.n += 1;
+        bk.in += (double)di;
+        bk.out += (double)dout;
+    }
+    for (auto &kv : acc) {
+        auto b = kv.second;
+        b.in /= b.n;
+        b.out /= b.n;
+        js.buckets.push_back(b);
+    }
+    return js;
+}
+
+// ---- plan strings ----------------------------------------------------------
+
+namespace {
+struct Parser {
+    const char *s;
+    size_t pos = 0;
+    int p;
+    int next_leaf = 0;
+    std::vector<PlanTree> &nodes;
+    bool ok = true;
+    Parser(const char *str, int p_, std::vector<PlanTree> &n) : s(str), p(p_), nodes(n) {}
+    void ws() {
+        while (s[pos] == ' ' || s[pos] == '\t' || s[pos] == '\n') ++pos;
+    }
+    int node() {
+        ws();
+        if (s[pos] == '(') {
+            ++pos;
+            int l = node();
+            ws();
+            if (!ok || s[pos] != ',') {
+                ok = false;
+                return -1;
+            }
+            ++pos;
+            int r = node();
+            ws();
+            if (!ok || s[pos] != ')') {
+                ok = false;
+                return -1;
+            }
+            ++pos;
+            PlanTree t;
+            t.left = l;
+            t.right = r;
+            nodes.push_back(t);
+            return (int)nodes.size() - 1;
+        }
+        if (s[pos] >= '0' && s[pos] <= '9') {
+            long v = 0;
+            while (s[pos] >= '0' && s[pos] <= '9') {
+                v = v * 10 + (s[pos] - '0');
+                if (v > 1000000) {
+                    ok = false;
+                    return -1;
+                }
+                ++pos;
+            }
+            if (v != next_leaf || v >= p) {  // leaves must appear once each, in chain order
+                ok = false;
+                return -1;
+            }
+            ++next_leaf;
+            PlanTree t;
+            t.leaf = (int)v;
+            nodes.push_back(t);
+            return (int)nodes.size() - 1;
+        }
+        ok = false;
+        return -1;
+    }
+};
+}  // namespace
+
+bool parse_plan(const char *s, int p, std::vector<PlanTree> &nodes, int &root) {
+    nodes.clear();
+    if (!s) return false;
+    Parser ps(s, p, nodes);
+    root = ps.node();
+    ps.ws();
+    return ps.ok && s[ps.pos] == '\0' && ps.next_leaf == p;
+}
+
+}  // namespace atp

@@ -1,0 +1,68 @@
+// Chain-order planner (host only).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace atp {
+
+// Estimated shape of a (sub)chain product.
+struct ChainStats {
+    double rows = 0;   // non-empty rows
+    double cols = 0;   // non-empty columns
+    double nnz = 0;
+    double dim_r = 0;  // full dimensions
+    double dim_c = 0;
+};
+
+// Joint degree sketch of a junction node type between relation k (into the
+// type) and relation k+1 (out of it): nodes grouped by (log2 in-degree,
+// log2 out-degree) with their count and mean degrees.
+struct JunctionSketch {
+    struct Bucket {
+        double n, in, out;
+    };
+    std::vector<Bucket> buckets;
+    double sum_in = 0, sum_out = 0;  // over all nodes of the type
+};
+
+struct CostCoeffs {
+    double alpha = 12.0;   // per nonzero of the left operand
+    double beta = 12.0;    // per product (N_op)
+    double gamma = 24.0;   // per nonzero of the result
+    double delta = 2.0e5;  // fixed cost of one product (launches and synchronisation)
+};
+
+enum class Estimator { Uniform, Sketch };
+
+struct PlanResult {
+    std::string plan;
+    double cost = 0;
+    std::vector<ChainStats> node_stats;  // estimate of the root and every product, post-order
+};
+
+// Dynamic program of Eq. 1 over p = leaves.size() matrices.  junctions[k]
+// (k < p-1) describes the node type between leaf k and k+1, and
+// junction_sel[k] the fraction of its nodes kept by that position's mask.
+PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<JunctionSketch> &junctions,
+                      const std::vector<double> &junction_sel, Estimator est, const CostCoeffs &cc);
+
+// Product estimate for X * Y meeting at a junction (exposed for tests).
+ChainStats estimate_product(const ChainStats &x, const ChainStats &y, const JunctionSketch *junction, double sel,
+                            Estimator est, double *n_op);
+
+// The paper's E_ac density estimate: 1 - (1 - rx*ry)^k, computed stably.
+double eac_density(double rx, double ry, double k);
+
+// Build a junction sketch from per-node in-degrees and out-degrees.
+JunctionSketch make_sketch(const int32_t *in_deg, const int64_t *out_row_ptr, int64_t n);
+
+// Plan strings: "3" for a single leaf, "(L,R)" for a product.
+struct PlanTree {
+    int leaf = -1;
+    int left = -1, right = -1;  // node indices
+};
+bool parse_plan(const char *s, int p, std::vector<PlanTree> &nodes, int &root);
+
+}  // namespace atp
