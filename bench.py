@@ -1,0 +1,220 @@
+"""Benchmark of the metapath SpGEMM-chain path on one MI355X.
+
+A step evaluates every query of the workload once (scholarly: A-P-V-P-A,
+A-P-T-P-A, V-P-T-P-V, T-P-A-P-T on the 4M-author / 6M-paper network, each with
+a seeded 1,000-node start set and P.year >= 2015).  The network is resident in
+HBM before timing; each query's result stays in device memory (freed after the
+query).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scholarly|news]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2201_04058_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, workload: str, launches_per_step: float) -> float | None:
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("kernel_source") != kernel_source_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(hin, queries, rows_per_query: int, threads: int) -> dict:
+    """The CPU oracle timed on a bounded sample: ``rows_per_query`` random start
+    rows of each query, scaled to whole queries (time x |S| / sample)."""
+    import oracle
+    oracle.build(force=False)
+    rng = np.random.default_rng(1234)
+    est_total = 0.0
+    for q in queries:
+        ids = [c for c in q.constraints if c.kind == "idset" and c.position == 0][0].ids
+        k = min(rows_per_query, len(ids))
+        rows = np.sort(rng.choice(ids, size=k, replace=False)).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.eval_rows(hin, q, rows, nthreads=threads)
+        dt = time.perf_counter() - t0
+        est_total += dt * len(ids) / k
+        log(f"cpu oracle {q.name}: {k} rows in {dt:.2f} s -> {dt * len(ids) / k:.1f} s per query")
+    return {"value": len(queries) / est_total, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows_per_query} random start rows per query of {len(queries)} "
+                      f"(of {len(ids)}), scaled by |start set| / sample"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="scholarly", choices=["scholarly", "news", "tiny"])
+    ap.add_argument("--cpu-rows", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan-eac", action="store_true", help="paper's uniform E_ac planner")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}), flush=True)
+        return 0
+
+    import paper_2201_04058_amd as atp
+    from synth import configs
+
+    t0 = time.perf_counter()
+    hin, queries = configs.load(args.workload)
+    log(f"workload {args.workload}: {len(queries)} queries, network ready in {time.perf_counter() - t0:.1f} s")
+    stream = None
+    try:
+        import torch
+        torch.cuda.init()
+        stream = atp.torch_stream_handle(0)
+    except Exception:
+        pass
+    ctx = atp.Context(device=0, stream=stream, plan_eac=args.plan_eac)
+    ctx.load_hin(hin)
+    log(f"network registered: {ctx.device_bytes() / 2**30:.2f} GiB on the device")
+
+    # plans and shapes (one untimed pass, also warms the pool)
+    plans = {}
+    for q in queries:
+        r = ctx.eval_query(q)
+        plans[q.name] = r.stats()
+        r.free()
+        log(f"  {q.name}: {plans[q.name]}")
+
+    # algorithmic bytes per kernel for one step (counting mode, untimed)
+    ctx.set_flags(count_bytes=True, plan_eac=args.plan_eac)
+    ctx.kernel_times_reset()
+    for q in queries:
+        ctx.eval_query(q).free()
+    bytes_per_step = {k: v[2] for k, v in ctx.kernel_times().items()}
+    ctx.set_flags(plan_eac=args.plan_eac)
+
+    for _ in range(args.warmup):
+        for q in queries:
+            ctx.eval_query(q).free()
+
+    # timed region: kernel events on the engine's stream
+    ctx.set_flags(profile=True, plan_eac=args.plan_eac)
+    ctx.kernel_times_reset()
+    lat = []
+    if stream is not None:
+        torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        for q in queries:
+            tq = time.perf_counter()
+            r = ctx.eval_query(q)
+            lat.append(time.perf_counter() - tq)
+            r.free()
+    if stream is not None:
+        torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kt = ctx.kernel_times()
+    ctx.set_flags(plan_eac=args.plan_eac)
+    n_q = len(queries) * args.steps
+    qps = n_q / elapsed
+    lat_ms = np.array(lat) * 1e3
+
+    # dominant kernel and its roofline (HBM-bound integer work)
+    timed = {k: v for k, v in kt.items() if v[1] > 0}
+    dom = max(timed, key=lambda k: timed[k][0])
+    ms_total, launches, _ = timed[dom]
+    alg_bytes = bytes_per_step.get(dom, 0.0) * args.steps
+    achieved = alg_bytes / (ms_total * 1e-3) / 1e9 if ms_total > 0 else 0.0
+    launches_per_step = launches / args.steps
+    traffic = traffic_for(dom, args.workload, launches_per_step)
+    kernel_ms = sum(v[0] for v in timed.values())
+    per_kernel = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps,
+                      "alg_GBps": round(bytes_per_step.get(k, 0.0) / (v[0] / args.steps * 1e-3) / 1e9, 1)
+                      if v[0] > 0 and bytes_per_step.get(k) else None}
+                  for k, v in sorted(timed.items(), key=lambda kv: -kv[1][0])}
+
+    out = {
+        "metric": "metapath queries/s",
+        "value": round(qps, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": args.workload,
+                   "queries": [q.name for q in queries],
+                   "start_set": int(len([c for c in queries[0].constraints if c.kind == "idset"][0].ids)),
+                   "network": {t: int(n) for t, n in hin.counts.items()},
+                   "edges": int(sum(r.nnz for r in hin.relations.values())),
+                   "parallelism": "single-gpu"},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3),
+                       "per_query_median": {q.name: round(float(np.median(lat_ms[i::len(queries)])), 3)
+                                            for i, q in enumerate(queries)}},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": round(alg_bytes / launches, 1) if launches else None,
+                     "avg_launch_ms": round(ms_total / launches, 5) if launches else None},
+        "kernels": per_kernel,
+        "kernel_ms_per_step": round(kernel_ms / args.steps, 3),
+        "plans": {k: v["plan"] for k, v in plans.items()},
+        "n_op_per_step": int(sum(v["n_op"] for v in plans.values())),
+        "nnz_result_per_step": int(sum(v["nnz"] for v in plans.values())),
+    }
+    if not args.no_cpu_baseline:
+        threads = len(os.sched_getaffinity(0))
+        threads = min(threads, 16)
+        out["cpu_baseline"] = cpu_baseline(hin, queries, args.cpu_rows, threads)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

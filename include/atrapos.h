@@ -57,6 +57,7 @@ typedef struct atp_result atp_result;
 /* flags of atp_options.flags */
 #define ATP_OPT_PROFILE (1u << 0)   /* time every kernel launch with HIP events (atp_kernel_times) */
 #define ATP_OPT_PLAN_EAC (1u << 1)  /* planner uses the paper's uniform E_ac estimate (Sec. 3.2) */
+#define ATP_OPT_COUNT_BYTES (1u << 2) /* count algorithmic bytes per kernel (extra passes; not for timing) */
 
 typedef struct {
     int device;                 /* HIP device ordinal */
@@ -179,10 +180,18 @@ atp_status atp_plan_chain(int32_t n_mats, const int64_t *dims, const int64_t *nn
 
 /* --- diagnostics ------------------------------------------------------------ */
 
-/* With ATP_OPT_PROFILE: accumulated device time (ms) and launch count of
- * every kernel name since the last reset; returns the number of kernels
- * written (at most cap). */
-int32_t atp_kernel_times(atp_ctx *ctx, const char **names, double *ms, int64_t *launches, int32_t cap);
+/* Replace the context's ATP_OPT_* flags (between queries). */
+atp_status atp_set_flags(atp_ctx *ctx, uint32_t flags);
+
+/* Per kernel name since the last reset: accumulated device time in ms and
+ * launch count (ATP_OPT_PROFILE, HIP events on the context's stream), and
+ * algorithmic bytes (ATP_OPT_COUNT_BYTES): operands read once and results
+ * written once, i.e. for a numeric launch 16 B per row pointer pair,
+ * (4 + 8 if valued) B per left-operand entry, 16 + (4 + 8 if valued) B per
+ * distinct right-operand row and its entries, 12 B per result entry.  Any
+ * output array may be NULL; returns the number of kernels written (<= cap). */
+int32_t atp_kernel_times(atp_ctx *ctx, const char **names, double *ms, int64_t *launches, double *bytes,
+                         int32_t cap);
 void atp_kernel_times_reset(atp_ctx *ctx);
 
 /* Bytes of device memory currently held by the context (pool included). */

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libatrapos.so")
 
 ATP_OK, ATP_EINVAL, ATP_ENOMEM, ATP_EOVERFLOW, ATP_ESCHEMA, ATP_EDEVICE, ATP_EBUDGET, ATP_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
-ATP_OPT_PROFILE, ATP_OPT_PLAN_EAC = 1, 2
+ATP_OPT_PROFILE, ATP_OPT_PLAN_EAC, ATP_OPT_COUNT_BYTES = 1, 2, 4
 ATP_REL_DEVICE_PTRS, ATP_REL_ADD_REVERSE = 1, 2
 ATP_I16, ATP_I32, ATP_I64 = 1, 2, 3
 ATP_C_RANGE, ATP_C_IDSET = 1, 2
@@ -24,7 +24,7 @@ ATP_C_RANGE, ATP_C_IDSET = 1, 2
 EXPORTS = [
     "atp_create", "atp_destroy", "atp_add_node_type", "atp_add_relation", "atp_add_property",
     "atp_eval", "atp_eval_plan", "atp_result_csr", "atp_result_to_host", "atp_result_stats",
-    "atp_result_free", "atp_plan_chain", "atp_kernel_times", "atp_kernel_times_reset",
+    "atp_result_free", "atp_plan_chain", "atp_set_flags", "atp_kernel_times", "atp_kernel_times_reset",
     "atp_device_bytes", "atp_status_str",
 ]
 
@@ -91,7 +91,8 @@ def lib() -> ctypes.CDLL:
         "atp_result_free": ([vp], i32),
         "atp_plan_chain": ([i32, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
                             ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_double)], i32),
-        "atp_kernel_times": ([vp, P(ctypes.c_char_p), P(ctypes.c_double), P(i64), i32], i32),
+        "atp_set_flags": ([vp, u32], i32),
+        "atp_kernel_times": ([vp, P(ctypes.c_char_p), P(ctypes.c_double), P(i64), P(ctypes.c_double), i32], i32),
         "atp_kernel_times_reset": ([vp], None),
         "atp_device_bytes": ([vp], i64),
         "atp_status_str": ([i32], ctypes.c_char_p),
@@ -289,13 +290,20 @@ class Context:
         return self.eval(query.types, query.constraints, plan=plan)
 
     # --- diagnostics -----------------------------------------------------
+    def set_flags(self, profile: bool = False, plan_eac: bool = False, count_bytes: bool = False) -> None:
+        f = (ATP_OPT_PROFILE if profile else 0) | (ATP_OPT_PLAN_EAC if plan_eac else 0) | \
+            (ATP_OPT_COUNT_BYTES if count_bytes else 0)
+        _check(lib().atp_set_flags(self._h, f), "atp_set_flags")
+
     def kernel_times(self) -> dict:
+        """kernel name -> (total ms, launches, algorithmic bytes) since the last reset"""
         cap = 64
         names = (ctypes.c_char_p * cap)()
         ms = (ctypes.c_double * cap)()
         n = (ctypes.c_int64 * cap)()
-        k = lib().atp_kernel_times(self._h, names, ms, n, cap)
-        return {names[z].decode(): (ms[z], n[z]) for z in range(k)}
+        b = (ctypes.c_double * cap)()
+        k = lib().atp_kernel_times(self._h, names, ms, n, b, cap)
+        return {names[z].decode(): (ms[z], n[z], b[z]) for z in range(k)}
 
     def kernel_times_reset(self) -> None:
         lib().atp_kernel_times_reset(self._h)

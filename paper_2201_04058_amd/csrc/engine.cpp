@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -25,12 +26,14 @@ using namespace atp;
 namespace atp {
 struct KernelTimer {
     struct Rec {
-        const char *name;
+        std::string name;
         hipEvent_t e0, e1;
     };
+    std::string suffix;  // appended to kernel names (per-product breakdown)
     std::vector<hipEvent_t> free_events;
     std::vector<Rec> pending;
     std::map<std::string, std::pair<double, int64_t>> acc;
+    std::map<std::string, double> bytes;
     hipEvent_t take() {
         if (!free_events.empty()) {
             hipEvent_t e = free_events.back();
@@ -65,7 +68,7 @@ struct KernelTimer {
 
 void timer_begin(KernelTimer *t, const char *name, hipStream_t s) {
     if (!t) return;
-    KernelTimer::Rec r{name, t->take(), t->take()};
+    KernelTimer::Rec r{std::string(name) + t->suffix, t->take(), t->take()};
     if (r.e0) (void)hipEventRecord(r.e0, s);
     t->pending.push_back(r);
 }
@@ -255,6 +258,7 @@ struct atp_ctx {
     StepHeader *h_hdr = nullptr;  // pinned
     std::set<atp_result *> results;
     bool broken = false;
+    bool step_names = std::getenv("ATP_PROFILE_STEPS") != nullptr;  // diagnostics: kernel names per product
     KernelTimer *kt() { return (flags & ATP_OPT_PROFILE) ? &timer : nullptr; }
 };
 
@@ -305,6 +309,39 @@ struct StepStats {
 };
 
 
+// Counting mode: algorithmic bytes of the numeric launches of one product,
+// by kernel name (operands read once, results written once).
+atp_status count_bytes(atp_ctx *c, const Mat &X, const Mat &Y, const int32_t *cand, const int32_t *bin_lists,
+                       int64_t n_cand, const StepHeader &h1, const int64_t *row_nnz) {
+    struct Group {
+        const char *name;
+        int b0, b1;
+    } groups[] = {{"hash_wave", BIN_W64, BIN_W512}, {"hash_block", BIN_B1024, BIN_B8192}, {"dense", BIN_DENSE, BIN_DENSE},
+                  {"bucket", BIN_BUCKET, BIN_BUCKET}};
+    hipStream_t s = c->stream;
+    const double vx = X.op.val ? 8.0 : 0.0, vy = Y.op.val ? 8.0 : 0.0;
+    for (const Group &g : groups) {
+        int64_t rows_in_group = 0;
+        for (int b = g.b0; b <= g.b1; ++b) rows_in_group += h1.bin_count[b];
+        if (!rows_in_group) continue;
+        Buf ymark, acc;
+        const int64_t words = (Y.rows + 31) / 32;
+        TRY(ymark.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(words, 1)));
+        TRY(acc.alloc(&c->pool, 8 * 5));
+        launch_fill_u32(ymark.as<uint32_t>(), words, 0u, s, nullptr);
+        launch_fill_i64(acc.as<int64_t>(), 5, 0, s, nullptr);
+        for (int b = g.b0; b <= g.b1; ++b)
+            launch_bin_stats(bin_lists + (int64_t)b * n_cand, h1.bin_count[b], X.op, cand, row_nnz,
+                             ymark.as<uint32_t>(), acc.as<int64_t>(), s);
+        launch_mark_bytes(ymark.as<uint32_t>(), Y.op.rp, Y.rows, acc.as<int64_t>(), s);
+        int64_t h[5];
+        HIPTRY(hipMemcpyAsync(h, acc.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        TRY(sync(c));
+        c->timer.bytes[g.name] += 16.0 * h[0] + (4.0 + vx) * h[1] + 12.0 * h[2] + 16.0 * h[3] + (4.0 + vy) * h[4];
+    }
+    return ATP_OK;
+}
+
 // Z = X * Y, one product of the plan (Sec. 3.2).  ycols_eff bounds the
 // columns that can occur (mask popcount of Y's last position, or Y's width).
 // need_active: Z will be the left operand of a later product.
@@ -344,6 +381,7 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     if (n_cand == 0 || ycols_eff == 0) return finish_empty();
 
     Buf hdr, nop, ub, nseg, bin, long_list, bin_lists, dense_chunks, slot_off, seg_base, task_base, tmp;
+    Buf bucket_chunks, bucket_nop, chunk_base, prod_base;
     TRY(hdr.alloc(pool, sizeof(StepHeader)));
     TRY(nop.alloc(pool, 8 * n_cand));
     TRY(ub.alloc(pool, 8 * n_cand));
@@ -355,12 +393,18 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     TRY(slot_off.alloc(pool, 8 * (n_cand + 1)));
     TRY(seg_base.alloc(pool, 8 * (n_cand + 1)));
     TRY(task_base.alloc(pool, 8 * (n_cand + 1)));
+    TRY(bucket_chunks.alloc(pool, 8 * n_cand));
+    TRY(bucket_nop.alloc(pool, 8 * n_cand));
+    TRY(chunk_base.alloc(pool, 8 * (n_cand + 1)));
+    TRY(prod_base.alloc(pool, 8 * (n_cand + 1)));
     const int64_t tmp_n = std::max(scan_tmp_elems(n_cand), scan_tmp_elems(Z.rows));
     TRY(tmp.alloc(pool, 8 * tmp_n));
 
     StepHeader *d_hdr = hdr.as<StepHeader>();
     launch_fill_i64((int64_t *)d_hdr, sizeof(StepHeader) / 8, 0, s, t);
     launch_fill_i64(dense_chunks.as<int64_t>(), n_cand, 0, s, t);
+    launch_fill_i64(bucket_chunks.as<int64_t>(), n_cand, 0, s, t);
+    launch_fill_i64(bucket_nop.as<int64_t>(), n_cand, 0, s, t);
 
     SymbolicArgs sa;
     sa.X = X.op;
@@ -375,6 +419,8 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     sa.long_list = long_list.as<int32_t>();
     sa.bin_lists = bin_lists.as<int32_t>();
     sa.dense_chunks = dense_chunks.as<int64_t>();
+    sa.bucket_chunks = bucket_chunks.as<int64_t>();
+    sa.bucket_nop = bucket_nop.as<int64_t>();
     sa.hdr = d_hdr;
     launch_symbolic(sa, s, t);
     launch_bin_rows(sa, s, t);
@@ -384,6 +430,10 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     launch_set_header_from_scan(seg_base.as<int64_t>() + n_cand, &d_hdr->segs_total, s);
     launch_scan_i64(dense_chunks.as<int64_t>(), task_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
     launch_set_header_from_scan(task_base.as<int64_t>() + n_cand, &d_hdr->dense_tasks, s);
+    launch_scan_i64(bucket_chunks.as<int64_t>(), chunk_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
+    launch_set_header_from_scan(chunk_base.as<int64_t>() + n_cand, &d_hdr->bucket_chunks, s);
+    launch_scan_i64(bucket_nop.as<int64_t>(), prod_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
+    launch_set_header_from_scan(prod_base.as<int64_t>() + n_cand, &d_hdr->bucket_products, s);
     TRY(read_header(c, d_hdr));
     const StepHeader h1 = *c->h_hdr;
     st.n_op += h1.n_op_total;
@@ -422,6 +472,24 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     if (h1.bin_count[BIN_DENSE] > 0)
         launch_numeric_dense(bin_lists.as<int32_t>() + (int64_t)BIN_DENSE * n_cand, h1.bin_count[BIN_DENSE],
                              task_base.as<int64_t>(), h1.dense_tasks, na, s, t);
+    Buf tile_cnt, tile_off, prod_col, prod_val;
+    if (h1.bin_count[BIN_BUCKET] > 0) {
+        const int64_t nb = h1.bin_count[BIN_BUCKET];
+        const int64_t ntiles = (Y.cols + kTileW - 1) / kTileW;
+        TRY(tile_cnt.alloc(pool, 8 * (size_t)nb * (ntiles + 1)));
+        TRY(tile_off.alloc(pool, 8 * (size_t)nb * (ntiles + 1)));
+        TRY(prod_col.alloc(pool, 4 * (size_t)std::max<int64_t>(h1.bucket_products, 1)));
+        const bool valued = X.op.val || Y.op.val;
+        if (valued) TRY(prod_val.alloc(pool, 8 * (size_t)std::max<int64_t>(h1.bucket_products, 1)));
+        launch_fill_i64(tile_cnt.as<int64_t>(), nb * (ntiles + 1), 0, s, t);
+        launch_numeric_bucket(bin_lists.as<int32_t>() + (int64_t)BIN_BUCKET * n_cand, nb, chunk_base.as<int64_t>(),
+                              h1.bucket_chunks, prod_base.as<int64_t>(), ntiles, tile_cnt.as<int64_t>(),
+                              tile_off.as<int64_t>(), prod_col.as<int32_t>(),
+                              valued ? prod_val.as<uint64_t>() : nullptr, na, s, t);
+    }
+
+    if (c->flags & ATP_OPT_COUNT_BYTES) TRY(count_bytes(c, X, Y, cand, bin_lists.as<int32_t>(), n_cand, h1,
+                                                       row_nnz.as<int64_t>()));
 
     // row pointers over every row of X; segment destinations in (row, tile) order
     launch_scan_i64(row_nnz.as<int64_t>(), Z.rp.as<int64_t>(), Z.rows, tmp.as<int64_t>(), s, t);
@@ -454,6 +522,7 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     }
     Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
                    Z.rows, Z.cols, Z.nnz};
+    if (c->flags & ATP_OPT_COUNT_BYTES) c->timer.bytes["copy"] += 24.0 * (double)Z.nnz + 24.0 * (double)h1.segs_total;
     // temporaries go back to the pool here; later work on the stream is ordered after this step
     return ATP_OK;
 }
@@ -706,7 +775,9 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         const int last_pos = r1 + 1;  // metapath position of Y's last type
         const int64_t ycols_eff = masks[last_pos].pop >= 0 ? masks[last_pos].pop : Y.cols;
         bool sat = false;
+        if (c->step_names) c->timer.suffix = "#" + std::to_string(n_products);
         TRY(spgemm(c, X, Y, ycols_eff, as_left, outm, st, sat));
+        c->timer.suffix.clear();
         ++n_products;
         if (v == forced_root && sat) overflow = true;
         return ATP_OK;
@@ -1020,15 +1091,27 @@ atp_status atp_plan_chain(int32_t n_mats, const int64_t *dims, const int64_t *nn
     return ATP_OK;
 }
 
-int32_t atp_kernel_times(atp_ctx *c, const char **names, double *ms, int64_t *launches, int32_t cap) {
+atp_status atp_set_flags(atp_ctx *c, uint32_t flags) {
+    if (!c) return ATP_EINVAL;
+    c->flags = flags;
+    return ATP_OK;
+}
+
+int32_t atp_kernel_times(atp_ctx *c, const char **names, double *ms, int64_t *launches, double *bytes, int32_t cap) {
     if (!c) return 0;
     c->timer.flush();
+    std::map<std::string, int> keys;
+    for (auto &kv : c->timer.acc) keys[kv.first] = 1;
+    for (auto &kv : c->timer.bytes) keys[kv.first] = 1;
     int32_t n = 0;
-    for (auto &kv : c->timer.acc) {
+    for (auto &kv : keys) {
         if (n >= cap) break;
-        if (names) names[n] = kv.first.c_str();
-        if (ms) ms[n] = kv.second.first;
-        if (launches) launches[n] = kv.second.second;
+        auto it = c->timer.acc.find(kv.first);
+        auto ib = c->timer.bytes.find(kv.first);
+        if (names) names[n] = kv.first == "" ? "" : (it != c->timer.acc.end() ? it->first.c_str() : ib->first.c_str());
+        if (ms) ms[n] = it != c->timer.acc.end() ? it->second.first : 0.0;
+        if (launches) launches[n] = it != c->timer.acc.end() ? it->second.second : 0;
+        if (bytes) bytes[n] = ib != c->timer.bytes.end() ? ib->second : 0.0;
         ++n;
     }
     return n;
@@ -1038,6 +1121,7 @@ void atp_kernel_times_reset(atp_ctx *c) {
     if (!c) return;
     c->timer.flush();
     c->timer.acc.clear();
+    c->timer.bytes.clear();
 }
 
 int64_t atp_device_bytes(const atp_ctx *c) { return c ? c->pool.held : 0; }

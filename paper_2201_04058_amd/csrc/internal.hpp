@@ -11,10 +11,14 @@ constexpr uint64_t kSat = 0x8000000000000000ull;  // saturated count (true value
 constexpr int32_t kEmptyKey = 0x7FFFFFFF;          // empty hash slot; sorts after every column id
 
 // Dense LDS tile: TW columns of uint64 accumulators plus presence/saturation bitmaps.
-constexpr int kTileW = 8192;
+constexpr int kTileShift = 13;
+constexpr int kTileW = 1 << kTileShift;
 constexpr int kDenseThreads = 512;
 constexpr int kCursorCap = 512;     // X entries whose cursors fit in LDS (multi-tile chunks)
 constexpr int64_t kTaskOps = 32768; // target products per dense task
+constexpr int kMaxBucketTiles = 4096;  // column tiles a bucketed row may span
+constexpr int64_t kBucketChunk = 8192; // left-operand entries per bucketing work item
+constexpr int kBucketThreads = 512;
 
 // Hash bins: table sizes (slots); wave-level tables for small rows, block-level otherwise.
 enum Bin : int32_t {
@@ -22,6 +26,7 @@ enum Bin : int32_t {
     BIN_W64, BIN_W128, BIN_W256, BIN_W512,         // one wavefront per row
     BIN_B1024, BIN_B2048, BIN_B4096, BIN_B8192,    // one workgroup per row
     BIN_DENSE,                                     // dense LDS tiles over column ranges
+    BIN_BUCKET,                                    // products bucketed by column tile, then dense tiles
     BIN_COUNT
 };
 
@@ -43,8 +48,11 @@ struct StepHeader {
     int64_t segs_total;       // number of output segments
     int64_t n_op_total;       // products
     int64_t n_long;           // rows handed to the long-row symbolic kernel
+    int64_t n_huge;           // rows split across the whole grid in the symbolic pass
     int64_t bin_count[BIN_COUNT];
     int64_t dense_tasks;      // dense-bin tasks
+    int64_t bucket_chunks;    // bucket-bin work items
+    int64_t bucket_products;  // products buffered by the bucket bin
     int64_t nnz_total;        // result nonzeros (after numeric)
     int64_t n_active;         // non-empty result rows
     int32_t saturated;        // some emitted value is saturated
@@ -83,9 +91,11 @@ struct SymbolicArgs {
     int64_t *ub;              // [n_cand]
     int64_t *nseg;            // [n_cand]
     int32_t *bin;             // [n_cand]
-    int32_t *long_list;       // [n_cand] candidates with long X rows
+    int32_t *long_list;       // [n_cand] long X rows from the front, huge rows from the back
     int32_t *bin_lists;       // [BIN_COUNT * n_cand]
     int64_t *dense_chunks;    // [n_cand] tasks per dense candidate (indexed by dense list position)
+    int64_t *bucket_chunks;   // [n_cand] work items per bucket candidate (indexed by bucket list position)
+    int64_t *bucket_nop;      // [n_cand] products per bucket candidate (indexed by bucket list position)
     StepHeader *hdr;
 };
 void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t);
@@ -112,6 +122,11 @@ void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const Nume
 void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *task_base, int64_t n_tasks,
                           const NumericArgs &a, hipStream_t s, KernelTimer *t);
 
+void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *chunk_base, int64_t n_chunks,
+                           const int64_t *prod_base, int64_t ntiles, int64_t *tile_cnt, int64_t *tile_off,
+                           int32_t *prod_col, uint64_t *prod_val, const NumericArgs &a, hipStream_t s,
+                           KernelTimer *t);
+
 // compaction
 void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
                           const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val,
@@ -121,5 +136,11 @@ void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row
 void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
                            hipStream_t s, KernelTimer *t);
 void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s);
+
+// algorithmic-byte accounting: acc[5] = rows, left entries, result entries,
+// distinct right rows, their entries
+void launch_bin_stats(const int32_t *list, int64_t n, const Operand &X, const int32_t *cand, const int64_t *row_nnz,
+                      uint32_t *ymark, int64_t *acc, hipStream_t s);
+void launch_mark_bytes(const uint32_t *ymark, const int64_t *yrp, int64_t yrows, int64_t *acc, hipStream_t s);
 
 }  // namespace atp

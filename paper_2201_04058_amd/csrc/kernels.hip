@@ -24,7 +24,8 @@ namespace atp {
 
 namespace {
 
-constexpr int kLongRow = 256;  // X rows longer than this get a workgroup in the symbolic pass
+constexpr int kLongRow = 256;     // X rows longer than this get a workgroup in the symbolic pass
+constexpr int kHugeRow = 32768;   // ... and longer than this are split across the whole grid
 
 __device__ __forceinline__ bool bit_test(const uint32_t *b, int64_t i) {
     return (b[i >> 5] >> (i & 31)) & 1u;
@@ -258,6 +259,12 @@ __global__ void k_symbolic(SymbolicArgs a) {
     int64_t nop = 0;
     if (!(a.X.rmask && !bit_test(a.X.rmask, i))) {
         int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
+        if (e - b > kHugeRow) {
+            unsigned long long slot = atomicAdd((unsigned long long *)&a.hdr->n_huge, 1ull);
+            a.long_list[a.n_cand - 1 - (int64_t)slot] = (int32_t)c;
+            a.nop[c] = 0;
+            return;
+        }
         if (e - b > kLongRow) {
             unsigned long long slot = atomicAdd((unsigned long long *)&a.hdr->n_long, 1ull);
             a.long_list[slot] = (int32_t)c;
@@ -292,47 +299,96 @@ __global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a) {
     }
 }
 
+// rows longer than kHugeRow: every block takes a slice of each row
+__global__ __launch_bounds__(256) void k_symbolic_huge(SymbolicArgs a) {
+    __shared__ int64_t sw[4];
+    const int64_t n_huge = a.hdr->n_huge;
+    for (int64_t t = 0; t < n_huge; ++t) {
+        int32_t c = a.long_list[a.n_cand - 1 - t];
+        int64_t i = a.cand ? a.cand[c] : c;
+        int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
+        int64_t chunk = (e - b + gridDim.x - 1) / gridDim.x;
+        int64_t lo = b + chunk * blockIdx.x, hi = lo + chunk < e ? lo + chunk : e;
+        int64_t s = 0;
+        for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+            int32_t k = a.X.col[p];
+            if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
+            s += a.Y.rp[k + 1] - a.Y.rp[k];
+        }
+        int64_t tot;
+        block_inclusive_scan(s, sw, &tot);
+        if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&a.nop[c], (unsigned long long)tot);
+    }
+}
+
 __global__ void k_bin_rows(SymbolicArgs a) {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= a.n_cand) return;
-    int64_t nop = a.nop[c];
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool live = c < a.n_cand;
+    const int lane = threadIdx.x & 63;
+    int64_t nop = live ? a.nop[c] : 0;
     int64_t ub = nop < a.ycols_eff ? nop : a.ycols_eff;
     int32_t bin = BIN_NONE;
     int64_t nseg = 0;
     const int64_t ycols = a.Y.cols;
     const int64_t ntiles = (ycols + kTileW - 1) / kTileW;
-    if (ub > 0) {
+    if (live && ub > 0) {
         if (ub > 4096 || (ycols <= kTileW && ycols <= 8 * ub)) {
             bin = BIN_DENSE;
             nseg = ntiles;
+            if (ntiles > 1 && ntiles <= kMaxBucketTiles) {
+                const int64_t i = a.cand ? a.cand[c] : c;
+                const int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
+                if (xlen > kCursorCap && xlen * ntiles > 4 * nop) bin = BIN_BUCKET;
+            }
         } else {
             nseg = 1;
             bin = ub <= 32 ? BIN_W64 : ub <= 64 ? BIN_W128 : ub <= 128 ? BIN_W256 : ub <= 256 ? BIN_W512
                 : ub <= 512 ? BIN_B1024 : ub <= 1024 ? BIN_B2048 : ub <= 2048 ? BIN_B4096 : BIN_B8192;
         }
-        atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)nop);
     }
-    a.ub[c] = ub;
-    a.nseg[c] = nseg;
-    a.bin[c] = bin;
-    if (bin != BIN_NONE) {
-        unsigned long long pos = atomicAdd((unsigned long long *)&a.hdr->bin_count[bin], 1ull);
-        a.bin_lists[(int64_t)bin * a.n_cand + (int64_t)pos] = (int32_t)c;
-        if (bin == BIN_DENSE) {
-            int64_t nch = 1;
-            if (ntiles > 1) {
+    if (live) {
+        a.ub[c] = ub;
+        a.nseg[c] = nseg;
+        a.bin[c] = bin;
+    }
+    // products: one atomic per wavefront
+    int64_t wsum = bin != BIN_NONE ? nop : 0;
+    for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
+    if (lane == 0 && wsum) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)wsum);
+    // bin lists: one atomic per (wavefront, bin)
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int b = BIN_W64; b < BIN_COUNT; ++b) {
+        const uint64_t m = __ballot(bin == b);
+        if (m == 0) continue;
+        const int leader = __builtin_ctzll(m);
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd((unsigned long long *)&a.hdr->bin_count[b], (unsigned long long)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if (bin == b) {
+            const int64_t pos = (int64_t)base + __popcll(m & lt);
+            a.bin_lists[(int64_t)b * a.n_cand + pos] = (int32_t)c;
+            if (b == BIN_BUCKET) {
                 int64_t i = a.cand ? a.cand[c] : c;
                 int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
-                if (xlen <= kCursorCap) {
-                    nch = (nop + kTaskOps - 1) / kTaskOps;
-                    nch = nch < 1 ? 1 : (nch > ntiles ? ntiles : nch);
-                    int64_t tpc = (ntiles + nch - 1) / nch;
-                    nch = (ntiles + tpc - 1) / tpc;
-                } else {
-                    nch = ntiles;
-                }
+                a.bucket_chunks[pos] = (xlen + kBucketChunk - 1) / kBucketChunk;
+                a.bucket_nop[pos] = nop;
             }
-            a.dense_chunks[pos] = nch;
+            if (b == BIN_DENSE) {
+                int64_t nch = 1;
+                if (ntiles > 1) {
+                    int64_t i = a.cand ? a.cand[c] : c;
+                    int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
+                    if (xlen <= kCursorCap) {
+                        nch = (nop + kTaskOps - 1) / kTaskOps;
+                        nch = nch < 1 ? 1 : (nch > ntiles ? ntiles : nch);
+                        int64_t tpc = (ntiles + nch - 1) / nch;
+                        nch = (ntiles + tpc - 1) / tpc;
+                    } else {
+                        nch = ntiles;
+                    }
+                }
+                a.dense_chunks[pos] = nch;
+            }
         }
     }
 }
@@ -512,22 +568,76 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
 // ---------------------------------------------------------------------------
 // numeric: dense LDS tiles over column ranges
 
+// Write one dense LDS tile (columns c0 .. c0+kTileW) of row i in column order
+// into the row's slots, then clear the tile.  Every thread of the block calls it.
+__device__ void emit_dense_tile(const NumericArgs &a, int32_t c, int64_t i, int64_t t, int64_t c0,
+                                unsigned long long *acc, uint32_t *pres, uint32_t *satw, int64_t *sw,
+                                int64_t *s_base, int *s_sat) {
+    constexpr int NW = kTileW / 32;
+    const int tid = threadIdx.x;
+    uint32_t word = tid < NW ? pres[tid] : 0u;
+    int64_t cntw = __popc(word);
+    int64_t tot;
+    int64_t inc = block_inclusive_scan(cntw, sw, &tot);
+    if (tid == 0)
+        *s_base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)tot) : 0;
+    __syncthreads();
+    if (tot > 0) {
+        const int64_t off = a.slot_off[c] + *s_base;
+        int64_t pos = off + inc - cntw;
+        bool sat = false;
+        if (tid < NW) {
+            uint32_t sw_bits = satw[tid];
+            uint32_t wbits = word;
+            while (wbits) {
+                int b = __builtin_ctz(wbits);
+                wbits &= wbits - 1;
+                int slot = tid * 32 + b;
+                unsigned long long v = ((sw_bits >> b) & 1u) ? kSat : acc[slot];
+                sat |= (v & kSat) != 0;
+                a.slot_col[pos] = (int32_t)(c0 + slot);
+                a.slot_val[pos] = v;
+                ++pos;
+                acc[slot] = 0;
+            }
+            pres[tid] = 0;
+            satw[tid] = 0;
+        }
+        if (sat) *s_sat = 1;
+        if (tid == 0) {
+            const int64_t sg = a.seg_base[c] + t;
+            a.seg_cnt[sg] = tot;
+            a.seg_src[sg] = off;
+            atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)tot);
+        }
+    }
+}
+
+// One task = one row and a chunk of consecutive column tiles.  Per tile, every
+// left entry's segment of its right row inside the tile is located (a cursor
+// carried from the previous tile, or a binary search), the segment lengths are
+// block-scanned, and the flattened products are shared evenly by all threads
+// (each thread walks 4 consecutive products).  Left entries are taken in
+// batches of kDenseThreads.
 __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, int64_t n_list, const int64_t *task_base,
                                                          int64_t n_tasks, NumericArgs a) {
     constexpr int W = kTileW;
-    constexpr int NW = W / 32;  // bitmap words per tile
+    constexpr int NW = W / 32;
+    constexpr int NT = kDenseThreads;
+    constexpr int RUN = 4;
     __shared__ unsigned long long acc[W];
     __shared__ uint32_t pres[NW];
     __shared__ uint32_t satw[NW];
-    __shared__ unsigned long long cur[kCursorCap];
-    __shared__ unsigned long long nxt[kCursorCap];
-    __shared__ int64_t sw[kDenseThreads / 64];
+    __shared__ int64_t cur[kCursorCap];  // next segment start per entry (multi-tile chunks)
+    __shared__ int64_t seg_s[NT];        // segment start of each entry of the batch
+    __shared__ int32_t seg_o[NT + 1];    // exclusive scan of segment lengths
+    __shared__ int64_t sw[NT / 64];
     __shared__ int64_t s_task[4];
     __shared__ int64_t s_base;
     __shared__ int s_sat;
     const int tid = threadIdx.x;
-    for (int t = tid; t < W; t += kDenseThreads) acc[t] = 0;
-    for (int t = tid; t < NW; t += kDenseThreads) {
+    for (int t = tid; t < W; t += NT) acc[t] = 0;
+    for (int t = tid; t < NW; t += NT) {
         pres[t] = 0;
         satw[t] = 0;
     }
@@ -558,93 +668,238 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
         const int64_t tpc = (ntiles + nch - 1) / nch;
         const int64_t t0 = q * tpc;
         const int64_t t1 = (t0 + tpc < ntiles) ? t0 + tpc : ntiles;
-        const bool use_cursor = (t1 - t0) > 1;
-        int64_t avg = a.nop[c] / ((xlen > 0 ? xlen : 1) * (ntiles > 0 ? ntiles : 1));
-        const int g = group_size(avg);
-        const int lane = tid & 63, wave = tid >> 6;
-        const int gpw = 64 / g;
-        const int gid = wave * gpw + lane / g, ng = (kDenseThreads / 64) * gpw, li = lane % g;
+        const bool use_cursor = (t1 - t0) > 1;  // implies xlen <= kCursorCap
         if (use_cursor) {
-            for (int64_t e = tid; e < xlen; e += kDenseThreads) {
+            for (int64_t e = tid; e < xlen; e += NT) {
                 int32_t k = a.X.col[xb + e];
                 int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
                 cur[e] = (t0 == 0) ? yb : lower_bound_col(a.Y.col, yb, ye, (int32_t)(t0 * W));
-                nxt[e] = ~0ull;
             }
             __syncthreads();
         }
         for (int64_t t = t0; t < t1; ++t) {
             const int64_t c0 = t * W;
             const int64_t c1 = (c0 + W < ycols) ? c0 + W : ycols;
-            for (int64_t e = gid; e < xlen; e += ng) {
-                int32_t k = a.X.col[xb + e];
-                if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
-                uint64_t xv = a.X.val ? a.X.val[xb + e] : 1ull;
-                int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
-                int64_t s = use_cursor ? (int64_t)cur[e] : (c0 == 0 ? yb : lower_bound_col(a.Y.col, yb, ye, (int32_t)c0));
-                int64_t brk = ye;
-                for (int64_t f = s + li; f < ye; f += g) {
-                    int32_t j = a.Y.col[f];
-                    if (j >= c1) {
-                        brk = f;
-                        break;
+            for (int64_t eb = 0; eb < xlen; eb += NT) {
+                const int64_t e = eb + tid;
+                int64_t len = 0;
+                if (e < xlen) {
+                    const int32_t k = a.X.col[xb + e];
+                    if (!(a.X.cmask && !bit_test(a.X.cmask, k))) {
+                        const int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
+                        const int64_t s0 = use_cursor ? cur[e] : (c0 == 0 ? yb : lower_bound_col(a.Y.col, yb, ye, (int32_t)c0));
+                        const int64_t s1 = (c1 >= ycols) ? ye : lower_bound_col(a.Y.col, s0, ye, (int32_t)c1);
+                        len = s1 - s0;
+                        seg_s[tid] = s0;
+                        if (use_cursor) cur[e] = s1;
                     }
-                    if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
-                    uint64_t v = a.Y.val ? sat_mul(xv, a.Y.val[f]) : xv;
-                    uint32_t slot = (uint32_t)(j - c0);
-                    atomicOr(&pres[slot >> 5], 1u << (slot & 31));
-                    acc_add(&acc[slot], satw, slot, v);
                 }
-                if (use_cursor) atomicMin(&nxt[e], (unsigned long long)brk);
-            }
-            __syncthreads();
-            // emit the tile in column order
-            uint32_t word = tid < NW ? pres[tid] : 0u;
-            int64_t cntw = __popc(word);
-            int64_t tot;
-            int64_t inc = block_inclusive_scan(cntw, sw, &tot);
-            if (tid == 0) s_base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c],
-                                                                (unsigned long long)tot)
-                                           : 0;
-            __syncthreads();
-            if (tot > 0) {
-                const int64_t off = a.slot_off[c] + s_base;
-                int64_t pos = off + inc - cntw;
-                bool sat = false;
-                if (tid < NW) {
-                    uint32_t sw_bits = satw[tid];
-                    uint32_t wbits = word;
-                    while (wbits) {
-                        int b = __builtin_ctz(wbits);
-                        wbits &= wbits - 1;
-                        int slot = tid * 32 + b;
-                        unsigned long long v = ((sw_bits >> b) & 1u) ? kSat : acc[slot];
-                        sat |= (v & kSat) != 0;
-                        a.slot_col[pos] = (int32_t)(c0 + slot);
-                        a.slot_val[pos] = v;
-                        ++pos;
-                        acc[slot] = 0;
-                    }
-                    pres[tid] = 0;
-                    satw[tid] = 0;
-                }
-                if (sat) s_sat = 1;
-                if (tid == 0) {
-                    const int64_t sg = a.seg_base[c] + t;
-                    a.seg_cnt[sg] = tot;
-                    a.seg_src[sg] = off;
-                    atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)tot);
-                }
-            }
-            if (use_cursor) {
+                int64_t tot;
+                const int64_t inc = block_inclusive_scan(len, sw, &tot);
+                seg_o[tid] = (int32_t)(inc - len);
+                if (tid == NT - 1) seg_o[NT] = (int32_t)inc;
                 __syncthreads();
-                for (int64_t e = tid; e < xlen; e += kDenseThreads) {
-                    cur[e] = nxt[e];
-                    nxt[e] = ~0ull;
+                const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
+                for (int64_t r0 = 0; r0 < tot; r0 += (int64_t)NT * RUN) {
+                    const int64_t first = r0 + (int64_t)tid * RUN;
+                    if (first >= tot) continue;
+                    int lo = 0, hi = NT;  // last entry with seg_o <= first
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (seg_o[mid] <= first)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    int ent = lo;
+#pragma unroll
+                    for (int r = 0; r < RUN; ++r) {
+                        const int64_t item = first + r;
+                        if (item >= tot) break;
+                        while (seg_o[ent + 1] <= item) ++ent;
+                        const int64_t f = seg_s[ent] + (item - seg_o[ent]);
+                        const int32_t j = a.Y.col[f];
+                        if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
+                        const uint64_t xv = xval ? xval[ent] : 1ull;
+                        const uint64_t v = a.Y.val ? sat_mul(xv, a.Y.val[f]) : xv;
+                        const uint32_t slot = (uint32_t)(j - c0);
+                        atomicOr(&pres[slot >> 5], 1u << (slot & 31));
+                        acc_add(&acc[slot], satw, slot, v);
+                    }
                 }
+                __syncthreads();
             }
+            emit_dense_tile(a, c, i, t, c0, acc, pres, satw, sw, &s_base, &s_sat);
             __syncthreads();
         }
+    }
+    __syncthreads();
+    if (tid == 0 && s_sat) atomicOr(&a.hdr->saturated, 1);
+}
+
+// ---------------------------------------------------------------------------
+// numeric: tile buckets for rows with very many left-operand entries and many
+// column tiles.  Their products are generated once, counting-sorted into
+// column-tile buckets, and each bucket is accumulated in a dense LDS tile.
+
+// chunk id -> (bucket list position, chunk index)
+__device__ __forceinline__ void bucket_chunk(const int64_t *chunk_base, int64_t n_list, int64_t id, int64_t *p,
+                                             int64_t *q) {
+    int64_t lo = 0, hi = n_list;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (chunk_base[mid] <= id)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *p = lo;
+    *q = id - chunk_base[lo];
+}
+
+// Products of X entries [e0, e1) of row i; f(tile, col, value) for each.
+template <typename F>
+__device__ __forceinline__ void for_products(const Operand &X, const Operand &Y, int64_t e0, int64_t e1, F f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int g = 8;  // lanes per X entry
+    const int gid = wave * (64 / g) + lane / g, ng = (blockDim.x / 64) * (64 / g), li = lane % g;
+    for (int64_t e = e0 + gid; e < e1; e += ng) {
+        int32_t k = X.col[e];
+        if (X.cmask && !bit_test(X.cmask, k)) continue;
+        uint64_t xv = X.val ? X.val[e] : 1ull;
+        int64_t yb = Y.rp[k], ye = Y.rp[k + 1];
+        for (int64_t fpos = yb + li; fpos < ye; fpos += g) {
+            int32_t j = Y.col[fpos];
+            if (Y.cmask && !bit_test(Y.cmask, j)) continue;
+            uint64_t v = Y.val ? sat_mul(xv, Y.val[fpos]) : xv;
+            f(j >> kTileShift, j, v);
+        }
+    }
+}
+
+struct BucketArgs {
+    const int32_t *list;        // bucket rows (candidate indices)
+    int64_t n_list;
+    const int64_t *chunk_base;  // [n_list + 1] X-entry chunks per row
+    int64_t n_chunks;
+    const int64_t *prod_base;   // [n_list + 1] products per row
+    int64_t ntiles;
+    int64_t *tile_cnt;          // [n_list * (ntiles + 1)] counts, then cursors
+    int64_t *tile_off;          // [n_list * (ntiles + 1)] absolute bucket offsets
+    int32_t *prod_col;
+    uint64_t *prod_val;
+};
+
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, NumericArgs a) {
+    __shared__ int32_t hist[kMaxBucketTiles];
+    for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
+        int64_t p, q;
+        bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
+        const int32_t c = b.list[p];
+        const int64_t i = a.cand ? a.cand[c] : c;
+        const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
+        const int64_t e0 = xb + q * kBucketChunk, e1 = e0 + kBucketChunk < xe ? e0 + kBucketChunk : xe;
+        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
+        __syncthreads();
+        for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+        __syncthreads();
+        int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
+        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x)
+            if (hist[t]) atomicAdd((unsigned long long *)&cnt[t], (unsigned long long)hist[t]);
+        __syncthreads();
+    }
+}
+
+// per bucket row: tile_off = prod_base + exclusive scan of the tile counts; counts become cursors
+__global__ __launch_bounds__(256) void k_bucket_scan(BucketArgs b) {
+    __shared__ int64_t sw[4];
+    for (int64_t p = blockIdx.x; p < b.n_list; p += gridDim.x) {
+        int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
+        int64_t *off = b.tile_off + p * (b.ntiles + 1);
+        int64_t carry = b.prod_base[p];
+        for (int64_t base = 0; base < b.ntiles; base += blockDim.x) {
+            int64_t t = base + threadIdx.x;
+            int64_t x = t < b.ntiles ? cnt[t] : 0;
+            int64_t tot;
+            int64_t inc = block_inclusive_scan(x, sw, &tot);
+            if (t < b.ntiles) {
+                off[t] = carry + inc - x;
+                cnt[t] = carry + inc - x;
+            }
+            carry += tot;
+        }
+        if (threadIdx.x == 0) off[b.ntiles] = carry;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b, NumericArgs a) {
+    __shared__ int32_t hist[kMaxBucketTiles];
+    __shared__ int64_t base[kMaxBucketTiles];
+    for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
+        int64_t p, q;
+        bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
+        const int32_t c = b.list[p];
+        const int64_t i = a.cand ? a.cand[c] : c;
+        const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
+        const int64_t e0 = xb + q * kBucketChunk, e1 = e0 + kBucketChunk < xe ? e0 + kBucketChunk : xe;
+        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
+        __syncthreads();
+        for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+        __syncthreads();
+        int64_t *cur = b.tile_cnt + p * (b.ntiles + 1);
+        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
+            int32_t h = hist[t];
+            base[t] = h ? (int64_t)atomicAdd((unsigned long long *)&cur[t], (unsigned long long)h) : 0;
+            hist[t] = 0;
+        }
+        __syncthreads();
+        const bool valued = b.prod_val != nullptr;
+        for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t j, uint64_t v) {
+            int64_t pos = base[tile] + atomicAdd(&hist[tile], 1);
+            b.prod_col[pos] = j;
+            if (valued) b.prod_val[pos] = v;
+        });
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs b, NumericArgs a) {
+    constexpr int W = kTileW;
+    constexpr int NW = W / 32;
+    __shared__ unsigned long long acc[W];
+    __shared__ uint32_t pres[NW];
+    __shared__ uint32_t satw[NW];
+    __shared__ int64_t sw[kDenseThreads / 64];
+    __shared__ int64_t s_base;
+    __shared__ int s_sat;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < W; t += kDenseThreads) acc[t] = 0;
+    for (int t = tid; t < NW; t += kDenseThreads) {
+        pres[t] = 0;
+        satw[t] = 0;
+    }
+    if (tid == 0) s_sat = 0;
+    __syncthreads();
+    const int64_t n_tasks = b.n_list * b.ntiles;
+    for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        const int64_t p = task / b.ntiles, t = task % b.ntiles;
+        const int64_t *off = b.tile_off + p * (b.ntiles + 1);
+        const int64_t lo = off[t], hi = off[t + 1];
+        if (lo == hi) continue;  // uniform across the block
+        const int32_t c = b.list[p];
+        const int64_t i = a.cand ? a.cand[c] : c;
+        const int64_t c0 = t * W;
+        const bool valued = b.prod_val != nullptr;
+        for (int64_t e = lo + tid; e < hi; e += kDenseThreads) {
+            const uint32_t slot = (uint32_t)(b.prod_col[e] - c0);
+            const uint64_t v = valued ? b.prod_val[e] : 1ull;
+            atomicOr(&pres[slot >> 5], 1u << (slot & 31));
+            acc_add(&acc[slot], satw, slot, v);
+        }
+        __syncthreads();
+        emit_dense_tile(a, c, i, t, c0, acc, pres, satw, sw, &s_base, &s_sat);
+        __syncthreads();
     }
     __syncthreads();
     if (tid == 0 && s_sat) atomicOr(&a.hdr->saturated, 1);
@@ -683,6 +938,49 @@ __global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int6
 }
 
 __global__ void k_copy_i64(const int64_t *src, int64_t *dst) { *dst = *src; }
+
+// ---------------------------------------------------------------------------
+// algorithmic-byte accounting (counting mode only, never on the timed path)
+
+// acc[0] rows, acc[1] left-operand entries, acc[2] result entries; marks the
+// right-operand rows the bin reads.
+__global__ void k_bin_stats(const int32_t *list, int64_t n, Operand X, const int32_t *cand, const int64_t *row_nnz,
+                            uint32_t *ymark, unsigned long long *acc) {
+    unsigned long long rows = 0, xent = 0, outn = 0;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = list[r];
+        const int64_t i = cand ? cand[c] : c;
+        const int64_t xb = X.rp[i], xe = X.rp[i + 1];
+        rows += 1;
+        xent += (unsigned long long)(xe - xb);
+        outn += (unsigned long long)row_nnz[i];
+        for (int64_t p = xb; p < xe; ++p) {
+            int32_t k = X.col[p];
+            if (X.cmask && !bit_test(X.cmask, k)) continue;
+            atomicOr(&ymark[k >> 5], 1u << (k & 31));
+        }
+    }
+    if (rows) {
+        atomicAdd(&acc[0], rows);
+        atomicAdd(&acc[1], xent);
+        atomicAdd(&acc[2], outn);
+    }
+}
+
+// acc[3] distinct right-operand rows, acc[4] their entries
+__global__ void k_mark_bytes(const uint32_t *ymark, const int64_t *yrp, int64_t yrows, unsigned long long *acc) {
+    unsigned long long rows = 0, ent = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < yrows; k += (int64_t)gridDim.x * blockDim.x) {
+        if (bit_test(ymark, k)) {
+            rows += 1;
+            ent += (unsigned long long)(yrp[k + 1] - yrp[k]);
+        }
+    }
+    if (rows) {
+        atomicAdd(&acc[3], rows);
+        atomicAdd(&acc[4], ent);
+    }
+}
 
 inline int grid_for(int64_t n, int threads, int64_t cap = 1 << 20) {
     int64_t g = (n + threads - 1) / threads;
@@ -771,6 +1069,7 @@ void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
     if ((a.n_cand + 255) / 256 > 0x7FFFFFFF) return;
     ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic, dim3((unsigned)((a.n_cand + 255) / 256)), dim3(256), 0, s, a);
     ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic_long, dim3(device_cus() * 4), dim3(256), 0, s, a);
+    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic_huge, dim3(device_cus() * 4), dim3(256), 0, s, a);
 }
 
 void launch_bin_rows(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
@@ -813,6 +1112,22 @@ void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *ta
                n_tasks, a);
 }
 
+void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *chunk_base, int64_t n_chunks,
+                           const int64_t *prod_base, int64_t ntiles, int64_t *tile_cnt, int64_t *tile_off,
+                           int32_t *prod_col, uint64_t *prod_val, const NumericArgs &a, hipStream_t s,
+                           KernelTimer *t) {
+    if (n_list <= 0 || n_chunks <= 0) return;
+    BucketArgs b{list, n_list, chunk_base, n_chunks, prod_base, ntiles, tile_cnt, tile_off, prod_col, prod_val};
+    const int cus = device_cus();
+    const int64_t gc = n_chunks < (int64_t)cus * 4 ? n_chunks : (int64_t)cus * 4;
+    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_count, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);
+    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scan, dim3((unsigned)(n_list < 1024 ? n_list : 1024)), dim3(256), 0, s, b);
+    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scatter, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);
+    const int64_t n_tasks = n_list * ntiles;
+    const int64_t ga = n_tasks < (int64_t)cus * 2 ? n_tasks : (int64_t)cus * 2;
+    ATP_LAUNCH("bucket_acc", 0, 0, s, k_bucket_accumulate, dim3((unsigned)ga), dim3(kDenseThreads), 0, s, b, a);
+}
+
 void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
                           const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val,
                           hipStream_t s, KernelTimer *t) {
@@ -834,6 +1149,19 @@ void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *f
     if (n_cand <= 0) return;
     ATP_LAUNCH("active", 0, 0, s, k_active_scatter, dim3((unsigned)((n_cand + 255) / 256)), dim3(256), 0, s, cand,
                n_cand, flags_scan, active);
+}
+
+void launch_bin_stats(const int32_t *list, int64_t n, const Operand &X, const int32_t *cand, const int64_t *row_nnz,
+                      uint32_t *ymark, int64_t *acc, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_bin_stats, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, list, n, X, cand, row_nnz, ymark,
+                       (unsigned long long *)acc);
+}
+
+void launch_mark_bytes(const uint32_t *ymark, const int64_t *yrp, int64_t yrows, int64_t *acc, hipStream_t s) {
+    if (yrows <= 0) return;
+    hipLaunchKernelGGL(k_mark_bytes, dim3(grid_for(yrows, 256, 4096)), dim3(256), 0, s, ymark, yrp, yrows,
+                       (unsigned long long *)acc);
 }
 
 void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s) {

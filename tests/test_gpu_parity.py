@@ -142,6 +142,31 @@ def test_row_size_at_every_bin_threshold(atp, oracle_mod, n_out, ncols):
     ctx.close()
 
 
+@pytest.mark.parametrize("ncols", [100_000, 8193, 1 << 24])
+def test_hub_rows_bucketed_by_tile(atp, oracle_mod, ncols):
+    """A left-operand row with 20k entries, each expanding to 1-3 products over
+    many column tiles (the tile-bucket path), pattern-only and valued."""
+    rng = np.random.default_rng(ncols)
+    nb = 20_000
+    hin = HIN(counts={"Z": 2, "A": 3, "B": nb, "C": ncols})
+    _csr_rel(hin, "Z", "A", [[0, 1, 2], [1]])
+    _csr_rel(hin, "A", "B", [list(range(nb)), list(range(0, nb, 7)), [3]])
+    rows = []
+    for b in range(nb):
+        k = int(rng.integers(1, 4))
+        rows.append(np.sort(rng.choice(ncols, size=k, replace=False)))
+    _csr_rel(hin, "B", "C", rows)
+    ctx = make_ctx(atp, hin)
+    for q, plans in [(Query("A-B-C", ["A", "B", "C"], []), [None]),
+                     (Query("Z-A-B-C", ["Z", "A", "B", "C"], []), [None, "((0,1),2)", "(0,(1,2))"]),
+                     (Query("A-B-C", ["A", "B", "C"], [Constraint(1, "idset", ids=np.arange(0, nb, 3, dtype=np.int32))]),
+                      [None])]:
+        ref = oracle_mod.eval_full(hin, q)
+        for plan in plans:
+            assert_same(ctx.eval_query(q, plan=plan), ref, f"{q.name} {plan}")
+    ctx.close()
+
+
 def test_colliding_hash_keys(atp, oracle_mod):
     """Columns that share low bits and hash-step patterns (multiples of 2^k)."""
     hin = HIN(counts={"A": 4, "B": 64, "C": 1 << 22})
