@@ -245,6 +245,28 @@ struct Prop {
 
 }  // namespace
 
+static Tuning tuning_from_env() {
+    Tuning t;
+    auto get = [](const char *name, int64_t &v) {
+        if (const char *e = std::getenv(name)) v = std::atoll(e);
+    };
+    get("ATP_PART_TARGET", t.part_target);
+    get("ATP_PART_HASH_CAP", t.part_hash_cap);
+    get("ATP_TASK_OPS", t.task_ops);
+    get("ATP_BUCKET_RATIO", t.bucket_ratio);
+    get("ATP_SPLIT_OPS", t.split_ops);
+    if (t.split_ops < 1024) t.split_ops = 1024;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        t.wg_slots = 2 * (int64_t)cus;
+    (void)hipGetLastError();
+    if (t.part_hash_cap > 2048) t.part_hash_cap = 2048;  // the hash overlays one 8192-column tile
+    if (t.part_target < 1) t.part_target = 1;
+    if (t.task_ops < 1) t.task_ops = 1;
+    return t;
+}
+
 struct atp_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -254,11 +276,13 @@ struct atp_ctx {
     std::vector<std::unique_ptr<Rel>> rels;
     std::vector<std::unique_ptr<Prop>> props;
     std::map<std::pair<int, int>, JunctionSketch> sketches;
+    std::map<int, ColumnHist> col_hists;
     KernelTimer timer;
     StepHeader *h_hdr = nullptr;  // pinned
     std::set<atp_result *> results;
     bool broken = false;
     bool step_names = std::getenv("ATP_PROFILE_STEPS") != nullptr;  // diagnostics: kernel names per product
+    Tuning tune = tuning_from_env();
     KernelTimer *kt() { return (flags & ATP_OPT_PROFILE) ? &timer : nullptr; }
 };
 
@@ -381,7 +405,7 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     if (n_cand == 0 || ycols_eff == 0) return finish_empty();
 
     Buf hdr, nop, ub, nseg, bin, long_list, bin_lists, dense_chunks, slot_off, seg_base, task_base, tmp;
-    Buf bucket_chunks, bucket_nop, chunk_base, prod_base;
+    Buf bucket_chunks, bucket_nop, chunk_base, prod_base, dense_split;
     TRY(hdr.alloc(pool, sizeof(StepHeader)));
     TRY(nop.alloc(pool, 8 * n_cand));
     TRY(ub.alloc(pool, 8 * n_cand));
@@ -394,6 +418,7 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     TRY(seg_base.alloc(pool, 8 * (n_cand + 1)));
     TRY(task_base.alloc(pool, 8 * (n_cand + 1)));
     TRY(bucket_chunks.alloc(pool, 8 * n_cand));
+    TRY(dense_split.alloc(pool, 8 * n_cand));
     TRY(bucket_nop.alloc(pool, 8 * n_cand));
     TRY(chunk_base.alloc(pool, 8 * (n_cand + 1)));
     TRY(prod_base.alloc(pool, 8 * (n_cand + 1)));
@@ -420,8 +445,10 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     sa.bin_lists = bin_lists.as<int32_t>();
     sa.dense_chunks = dense_chunks.as<int64_t>();
     sa.bucket_chunks = bucket_chunks.as<int64_t>();
+    sa.dense_split = dense_split.as<int64_t>();
     sa.bucket_nop = bucket_nop.as<int64_t>();
     sa.hdr = d_hdr;
+    sa.tune = c->tune;
     launch_symbolic(sa, s, t);
     launch_bin_rows(sa, s, t);
     launch_scan_i64(ub.as<int64_t>(), slot_off.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
@@ -467,6 +494,22 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     na.row_nnz = row_nnz.as<int64_t>();
     na.hdr = d_hdr;
     na.ycols = Y.cols;
+    na.tune = c->tune;
+    na.dense_split = dense_split.as<int64_t>();
+    Buf split_acc, split_sat, split_done;
+    if (h1.n_split > 0) {
+        const int64_t ntiles = (Y.cols + kTileW - 1) / kTileW;
+        const int64_t nt = h1.n_split * ntiles;
+        TRY(split_acc.alloc(pool, 8 * (size_t)nt * kTileW));
+        TRY(split_sat.alloc(pool, 4 * (size_t)nt * (kTileW / 32)));
+        TRY(split_done.alloc(pool, 4 * (size_t)nt));
+        launch_fill_i64(split_acc.as<int64_t>(), nt * kTileW, 0, s, t);
+        launch_fill_u32(split_sat.as<uint32_t>(), nt * (kTileW / 32), 0u, s, t);
+        launch_fill_u32((uint32_t *)split_done.as<int32_t>(), nt, 0u, s, t);
+        na.split_acc = split_acc.as<unsigned long long>();
+        na.split_sat = split_sat.as<uint32_t>();
+        na.split_done = split_done.as<int32_t>();
+    }
     for (int b = BIN_W64; b <= BIN_B8192; ++b)
         launch_numeric_hash(b, bin_lists.as<int32_t>() + (int64_t)b * n_cand, h1.bin_count[b], na, s, t);
     if (h1.bin_count[BIN_DENSE] > 0)
@@ -712,14 +755,24 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         plan_str = plan;
     } else {
         std::vector<JunctionSketch> js;
-        std::vector<double> jsel;
+        std::vector<double> jsel, csel;
+        std::vector<ColumnHist> ch;
         const bool uniform = (c->flags & ATP_OPT_PLAN_EAC) != 0;
         for (int k = 0; k + 1 < p; ++k) {
             if (!uniform) js.push_back(sketch_for(c, rel[k], rel[k + 1]));
             jsel.push_back(sel_of(k + 1));
         }
+        for (int k = 0; k < p && !uniform; ++k) {
+            auto it = c->col_hists.find(rel[k]);
+            if (it == c->col_hists.end()) {
+                const Rel &r = *c->rels[rel[k]];
+                it = c->col_hists.emplace(rel[k], make_column_hist(r.h_indeg.data(), (int64_t)r.h_indeg.size())).first;
+            }
+            ch.push_back(it->second);
+            csel.push_back(sel_of(k + 1));
+        }
         CostCoeffs cc;
-        PlanResult pr = plan_chain(lst, js, jsel, uniform ? Estimator::Uniform : Estimator::Sketch, cc);
+        PlanResult pr = plan_chain(lst, js, jsel, ch, csel, uniform ? Estimator::Uniform : Estimator::Sketch, cc);
         plan_str = pr.plan;
         if (!parse_plan(plan_str.c_str(), p, forced, forced_root)) return ATP_ESTATE;
     }
@@ -1085,7 +1138,7 @@ atp_status atp_plan_chain(int32_t n_mats, const int64_t *dims, const int64_t *nn
     cc.beta = beta;
     cc.gamma = gamma;
     cc.delta = 0;
-    PlanResult pr = plan_chain(leaves, {}, {}, Estimator::Uniform, cc);
+    PlanResult pr = plan_chain(leaves, {}, {}, {}, {}, Estimator::Uniform, cc);
     if (plan && plan_cap) std::snprintf(plan, plan_cap, "%s", pr.plan.c_str());
     if (cost) *cost = pr.cost;
     return ATP_OK;

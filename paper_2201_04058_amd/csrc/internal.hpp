@@ -16,6 +16,11 @@ constexpr int kTileW = 1 << kTileShift;
 constexpr int kDenseThreads = 512;
 constexpr int kCursorCap = 512;     // X entries whose cursors fit in LDS (multi-tile chunks)
 constexpr int64_t kTaskOps = 32768; // target products per dense task
+constexpr int64_t kPartTarget = 1200;  // expected products per part of a sparse long row
+constexpr int64_t kPartHashCap = 2048; // a part with at most this many products uses an LDS hash
+constexpr int kPartMaxTiles = 16;      // ... if it spans at most this many tiles (its presence bitmap)
+constexpr int64_t kSplitOps = 65536;   // products per (row, tile) beyond which the row's entries are split
+constexpr int kMaxSplit = 64;
 constexpr int kMaxBucketTiles = 4096;  // column tiles a bucketed row may span
 constexpr int64_t kBucketChunk = 8192; // left-operand entries per bucketing work item
 constexpr int kBucketThreads = 512;
@@ -42,6 +47,16 @@ struct Operand {
     int64_t rows = 0, cols = 0, nnz = 0;
 };
 
+// Runtime tunables of the binning and numeric kernels (defaults above).
+struct Tuning {
+    int64_t part_target = kPartTarget;
+    int64_t part_hash_cap = kPartHashCap;
+    int64_t task_ops = kTaskOps;
+    int64_t bucket_ratio = 4;  // bucket a row when left entries x tiles > ratio x products
+    int64_t split_ops = kSplitOps;
+    int64_t wg_slots = 512;    // resident dense workgroups (2 per compute unit)
+};
+
 // Per-step device scratch header read back by the host (one small copy).
 struct StepHeader {
     int64_t slots_total;      // sum of per-row upper bounds
@@ -52,6 +67,7 @@ struct StepHeader {
     int64_t bin_count[BIN_COUNT];
     int64_t dense_tasks;      // dense-bin tasks
     int64_t bucket_chunks;    // bucket-bin work items
+    int64_t n_split;          // dense rows whose entries are split over several workgroups
     int64_t bucket_products;  // products buffered by the bucket bin
     int64_t nnz_total;        // result nonzeros (after numeric)
     int64_t n_active;         // non-empty result rows
@@ -94,9 +110,11 @@ struct SymbolicArgs {
     int32_t *long_list;       // [n_cand] long X rows from the front, huge rows from the back
     int32_t *bin_lists;       // [BIN_COUNT * n_cand]
     int64_t *dense_chunks;    // [n_cand] tasks per dense candidate (indexed by dense list position)
+    int64_t *dense_split;     // [n_cand] split slot * 256 + split factor per dense candidate
     int64_t *bucket_chunks;   // [n_cand] work items per bucket candidate (indexed by bucket list position)
     int64_t *bucket_nop;      // [n_cand] products per bucket candidate (indexed by bucket list position)
     StepHeader *hdr;
+    Tuning tune;
 };
 void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t);
 void launch_bin_rows(const SymbolicArgs &a, hipStream_t s, KernelTimer *t);
@@ -116,6 +134,11 @@ struct NumericArgs {
     int64_t *row_nnz;          // [X.rows] (zeroed)
     StepHeader *hdr;
     int64_t ycols;
+    const int64_t *dense_split;        // [n_dense] split slot * 256 + split factor
+    unsigned long long *split_acc;     // [n_split * ntiles * kTileW] (zeroed)
+    uint32_t *split_sat;               // [n_split * ntiles * kTileW / 32] (zeroed)
+    int32_t *split_done;               // [n_split * ntiles] (zeroed)
+    Tuning tune;
 };
 void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const NumericArgs &a, hipStream_t s,
                          KernelTimer *t);

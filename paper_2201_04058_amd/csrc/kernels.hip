@@ -61,6 +61,34 @@ __device__ __forceinline__ int64_t lower_bound_col(const int32_t *col, int64_t l
     return lo;
 }
 
+// Lower bound of `key` in the ascending arr[lo, hi), searched by a group of g
+// lanes of one wavefront (g a power of two <= 64, li = lane within the group,
+// gmask = the group's lanes in the wavefront).  Each round probes g evenly
+// spaced positions and keeps the gap that holds the answer, so a range of n
+// entries takes about log(n)/log(g+1) dependent loads.
+template <typename T, typename K>
+__device__ __forceinline__ int64_t group_lower_bound(const T *arr, int64_t lo, int64_t hi, K key, int g, int li,
+                                                     uint64_t gmask) {
+    while (hi - lo > g) {
+        const int64_t span = hi - lo;
+        const int64_t pos = lo + span * (li + 1) / (g + 1);
+        const bool pred = arr[pos] < key;
+        const int cnt = __popcll(__ballot(pred) & gmask);
+        const int64_t nlo = cnt > 0 ? lo + span * cnt / (g + 1) + 1 : lo;
+        const int64_t nhi = cnt < g ? lo + span * (cnt + 1) / (g + 1) : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    const bool pred = (lo + li < hi) && arr[lo + li] < key;
+    return lo + __popcll(__ballot(pred) & gmask);
+}
+
+__device__ __forceinline__ uint64_t group_mask(int g) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t base = g == 64 ? ~0ull : ((1ull << g) - 1ull);
+    return base << (lane & ~(g - 1));
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -278,6 +306,7 @@ __global__ void k_symbolic(SymbolicArgs a) {
         }
     }
     a.nop[c] = nop;
+    if (nop) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)nop);
 }
 
 __global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a) {
@@ -295,7 +324,10 @@ __global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a) {
         }
         int64_t tot;
         block_inclusive_scan(s, sw, &tot);
-        if (threadIdx.x == 0) a.nop[c] = tot;
+        if (threadIdx.x == 0) {
+            a.nop[c] = tot;
+            if (tot) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)tot);
+        }
     }
 }
 
@@ -317,7 +349,10 @@ __global__ __launch_bounds__(256) void k_symbolic_huge(SymbolicArgs a) {
         }
         int64_t tot;
         block_inclusive_scan(s, sw, &tot);
-        if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&a.nop[c], (unsigned long long)tot);
+        if (threadIdx.x == 0 && tot) {
+            atomicAdd((unsigned long long *)&a.nop[c], (unsigned long long)tot);
+            atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)tot);
+        }
     }
 }
 
@@ -338,7 +373,7 @@ __global__ void k_bin_rows(SymbolicArgs a) {
             if (ntiles > 1 && ntiles <= kMaxBucketTiles) {
                 const int64_t i = a.cand ? a.cand[c] : c;
                 const int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
-                if (xlen > kCursorCap && xlen * ntiles > 4 * nop) bin = BIN_BUCKET;
+                if (xlen > kCursorCap && xlen * ntiles > a.tune.bucket_ratio * nop) bin = BIN_BUCKET;
             }
         } else {
             nseg = 1;
@@ -351,10 +386,6 @@ __global__ void k_bin_rows(SymbolicArgs a) {
         a.nseg[c] = nseg;
         a.bin[c] = bin;
     }
-    // products: one atomic per wavefront
-    int64_t wsum = bin != BIN_NONE ? nop : 0;
-    for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
-    if (lane == 0 && wsum) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)wsum);
     // bin lists: one atomic per (wavefront, bin)
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int b = BIN_W64; b < BIN_COUNT; ++b) {
@@ -378,14 +409,40 @@ __global__ void k_bin_rows(SymbolicArgs a) {
                 if (ntiles > 1) {
                     int64_t i = a.cand ? a.cand[c] : c;
                     int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
-                    if (xlen <= kCursorCap) {
-                        nch = (nop + kTaskOps - 1) / kTaskOps;
-                        nch = nch < 1 ? 1 : (nch > ntiles ? ntiles : nch);
-                        int64_t tpc = (ntiles + nch - 1) / nch;
-                        nch = (ntiles + tpc - 1) / tpc;
-                    } else {
-                        nch = ntiles;
+                    const int64_t per_tile = nop / ntiles;
+                    int64_t m = 1;  // tiles per part
+                    if (per_tile < a.tune.part_target) {
+                        m = a.tune.part_target / (per_tile > 0 ? per_tile : 1);
+                        m = m > kPartMaxTiles ? kPartMaxTiles : m;
+                    } else if (xlen <= kCursorCap) {
+                        int64_t chunks = (nop + a.tune.task_ops - 1) / a.tune.task_ops;
+                        chunks = chunks < 1 ? 1 : chunks;
+                        m = (ntiles + chunks - 1) / chunks;
                     }
+                    m = m < 1 ? 1 : (m > ntiles ? ntiles : m);
+                    nch = (ntiles + m - 1) / m;
+                }
+                // heavy rows: split the left entries over several workgroups per tile
+                int64_t ks = 1;
+                {
+                    const int64_t i = a.cand ? a.cand[c] : c;
+                    const int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
+                    const int64_t per_tile = nop / ntiles;
+                    // a straggler holds more than the step's work per resident workgroup
+                    int64_t thr = a.hdr->n_op_total / (2 * a.tune.wg_slots);
+                    thr = thr > a.tune.split_ops ? thr : a.tune.split_ops;
+                    if (per_tile > thr) {
+                        ks = (per_tile + thr - 1) / thr;
+                        const int64_t cap = xlen / 8 < kMaxSplit ? xlen / 8 : kMaxSplit;
+                        ks = ks > cap ? cap : ks;
+                    }
+                }
+                if (ks > 1) {
+                    nch = ntiles * ks;  // one part per tile
+                    const unsigned long long slot = atomicAdd((unsigned long long *)&a.hdr->n_split, 1ull);
+                    a.dense_split[pos] = (int64_t)slot * 256 + ks;
+                } else {
+                    a.dense_split[pos] = 1;
                 }
                 a.dense_chunks[pos] = nch;
             }
@@ -569,16 +626,76 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
 // numeric: dense LDS tiles over column ranges
 
 // Write one dense LDS tile (columns c0 .. c0+kTileW) of row i in column order
-// into the row's slots, then clear the tile.  Every thread of the block calls it.
+// into the row's slots, then clear it.  A slot is present when its
+// accumulator is non-zero or its saturation bit is set (every contribution is
+// at least 1; a saturated one only sets the bit).  Each wavefront handles
+// groups of 64 consecutive slots, one slot per lane: a ballot gives the
+// group's presence mask, a block scan of the group counts gives positions,
+// and lanes write consecutive outputs.  gcnt holds kTileW/64 int32.  Every
+// thread of the block calls it.
 __device__ void emit_dense_tile(const NumericArgs &a, int32_t c, int64_t i, int64_t t, int64_t c0,
-                                unsigned long long *acc, uint32_t *pres, uint32_t *satw, int64_t *sw,
+                                unsigned long long *acc, uint32_t *satw, int32_t *gcnt, int64_t *sw,
                                 int64_t *s_base, int *s_sat) {
+    constexpr int NG = kTileW / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nwaves = blockDim.x >> 6;
+    for (int g = wave; g < NG; g += nwaves) {
+        const int slot = g * 64 + lane;
+        const bool pr = acc[slot] != 0 || ((satw[slot >> 5] >> (slot & 31)) & 1u);
+        const uint64_t m = __ballot(pr);
+        if (lane == 0) gcnt[g] = __popcll(m);
+    }
+    __syncthreads();
+    int64_t x = 0;
+    for (int g = tid; g < NG; g += blockDim.x) x += gcnt[g];  // NG <= blockDim: one group per thread
+    int64_t tot;
+    const int64_t inc = block_inclusive_scan(x, sw, &tot);
+    if (tid < NG) gcnt[tid] = (int32_t)(inc - x);
+    if (tid == 0)
+        *s_base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)tot) : 0;
+    __syncthreads();
+    if (tot > 0) {
+        const int64_t off = a.slot_off[c] + *s_base;
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        bool sat = false;
+        for (int g = wave; g < NG; g += nwaves) {
+            const int slot = g * 64 + lane;
+            const unsigned long long v = acc[slot];
+            const bool sb = (satw[slot >> 5] >> (slot & 31)) & 1u;
+            const bool pr = v != 0 || sb;
+            const uint64_t m = __ballot(pr);
+            if (pr) {
+                const int64_t pos = off + gcnt[g] + __popcll(m & lt);
+                const unsigned long long out = sb ? kSat : v;
+                sat |= sb;
+                a.slot_col[pos] = (int32_t)(c0 + slot);
+                a.slot_val[pos] = out;
+                acc[slot] = 0;
+            }
+        }
+        for (int w = tid; w < kTileW / 32; w += blockDim.x) satw[w] = 0;
+        if (sat) *s_sat = 1;
+        if (tid == 0) {
+            const int64_t sg = a.seg_base[c] + t;
+            a.seg_cnt[sg] = tot;
+            a.seg_src[sg] = off;
+            atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)tot);
+        }
+    }
+}
+
+// As emit_dense_tile, for a sparse tile whose present slots are marked in the
+// bitmap pres (one bit per column): one thread per bitmap word, the word's
+// entries written in column order; pres is cleared.
+__device__ void emit_sparse_tile(const NumericArgs &a, int32_t c, int64_t i, int64_t t, int64_t c0,
+                                 unsigned long long *acc, uint32_t *pres, uint32_t *satw, int64_t *sw,
+                                 int64_t *s_base, int *s_sat) {
     constexpr int NW = kTileW / 32;
     const int tid = threadIdx.x;
-    uint32_t word = tid < NW ? pres[tid] : 0u;
-    int64_t cntw = __popc(word);
+    const uint32_t word = tid < NW ? pres[tid] : 0u;
+    const int64_t cntw = __popc(word);
     int64_t tot;
-    int64_t inc = block_inclusive_scan(cntw, sw, &tot);
+    const int64_t inc = block_inclusive_scan(cntw, sw, &tot);
     if (tid == 0)
         *s_base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)tot) : 0;
     __syncthreads();
@@ -587,16 +704,16 @@ __device__ void emit_dense_tile(const NumericArgs &a, int32_t c, int64_t i, int6
         int64_t pos = off + inc - cntw;
         bool sat = false;
         if (tid < NW) {
-            uint32_t sw_bits = satw[tid];
+            const uint32_t sbits = satw[tid];
             uint32_t wbits = word;
             while (wbits) {
-                int b = __builtin_ctz(wbits);
+                const int b = __builtin_ctz(wbits);
                 wbits &= wbits - 1;
-                int slot = tid * 32 + b;
-                unsigned long long v = ((sw_bits >> b) & 1u) ? kSat : acc[slot];
-                sat |= (v & kSat) != 0;
+                const int slot = tid * 32 + b;
+                const bool sb = (sbits >> b) & 1u;
+                sat |= sb;
                 a.slot_col[pos] = (int32_t)(c0 + slot);
-                a.slot_val[pos] = v;
+                a.slot_val[pos] = sb ? kSat : acc[slot];
                 ++pos;
                 acc[slot] = 0;
             }
@@ -613,123 +730,391 @@ __device__ void emit_dense_tile(const NumericArgs &a, int32_t c, int64_t i, int6
     }
 }
 
-// One task = one row and a chunk of consecutive column tiles.  Per tile, every
-// left entry's segment of its right row inside the tile is located (a cursor
-// carried from the previous tile, or a binary search), the segment lengths are
-// block-scanned, and the flattened products are shared evenly by all threads
-// (each thread walks 4 consecutive products).  Left entries are taken in
-// batches of kDenseThreads.
+// Split rows: add this workgroup's partial tile into the tile's global
+// accumulator (device-scope atomics; a partial is exact below 2^63, so the
+// first crossing of 2^63 is seen by the adding workgroup, as in acc_add),
+// clear the LDS tile, and let the last of the ks workgroups emit the tile in
+// column order from the global accumulator.
+__device__ void flush_split_tile(const NumericArgs &a, int64_t gt, int64_t ks, int32_t c, int64_t i, int64_t t,
+                                 int64_t c0, unsigned long long *acc, uint32_t *satw, int32_t *gcnt, int64_t *sw,
+                                 int64_t *s_base, int *s_sat, int *s_last) {
+    constexpr int NG = kTileW / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nwaves = blockDim.x >> 6;
+    unsigned long long *gacc = a.split_acc + gt * kTileW;
+    uint32_t *gsat = a.split_sat + gt * (kTileW / 32);
+    for (int g = wave; g < NG; g += nwaves) {
+        const int slot = g * 64 + lane;
+        const unsigned long long v = acc[slot];
+        const bool sb = (satw[slot >> 5] >> (slot & 31)) & 1u;
+        if (sb) {
+            atomicOr(&gsat[slot >> 5], 1u << (slot & 31));
+        } else if (v) {
+            const unsigned long long old = atomicAdd(&gacc[slot], v);
+            if (old < kSat && old + v >= kSat) atomicOr(&gsat[slot >> 5], 1u << (slot & 31));
+        }
+        acc[slot] = 0;
+    }
+    for (int w = tid; w < kTileW / 32; w += blockDim.x) satw[w] = 0;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const int done = atomicAdd(&a.split_done[gt], 1);
+        *s_last = (done == ks - 1);
+    }
+    __syncthreads();
+    if (!*s_last) return;
+    __threadfence();
+    // last workgroup: emit from the global accumulator
+    for (int g = wave; g < NG; g += nwaves) {
+        const int slot = g * 64 + lane;
+        const unsigned long long v = __hip_atomic_load(&gacc[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t sw32 = __hip_atomic_load(&gsat[slot >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool pr = v != 0 || ((sw32 >> (slot & 31)) & 1u);
+        const uint64_t m = __ballot(pr);
+        if (lane == 0) gcnt[g] = __popcll(m);
+    }
+    __syncthreads();
+    const int64_t x = tid < NG ? gcnt[tid] : 0;
+    int64_t tot;
+    const int64_t inc = block_inclusive_scan(x, sw, &tot);
+    if (tid < NG) gcnt[tid] = (int32_t)(inc - x);
+    if (tid == 0)
+        *s_base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)tot) : 0;
+    __syncthreads();
+    if (tot > 0) {
+        const int64_t off = a.slot_off[c] + *s_base;
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        bool sat = false;
+        for (int g = wave; g < NG; g += nwaves) {
+            const int slot = g * 64 + lane;
+            const unsigned long long v = __hip_atomic_load(&gacc[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t sw32 = __hip_atomic_load(&gsat[slot >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool sb = (sw32 >> (slot & 31)) & 1u;
+            const bool pr = v != 0 || sb;
+            const uint64_t m = __ballot(pr);
+            if (pr) {
+                const int64_t pos = off + gcnt[g] + __popcll(m & lt);
+                sat |= sb;
+                a.slot_col[pos] = (int32_t)(c0 + slot);
+                a.slot_val[pos] = sb ? kSat : v;
+            }
+        }
+        if (sat) *s_sat = 1;
+        if (tid == 0) {
+            const int64_t sg = a.seg_base[c] + t;
+            a.seg_cnt[sg] = tot;
+            a.seg_src[sg] = off;
+            atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)tot);
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t hash_find_rt(int32_t *keys, int32_t j, int log2s) {
+    const uint32_t mask = (1u << log2s) - 1u;
+    uint32_t h = hash_of(j, log2s);
+    while (true) {
+        int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == j) return h;
+        if (k == kEmptyKey) {
+            int32_t prev = atomicCAS(&keys[h], kEmptyKey, j);
+            if (prev == kEmptyKey || prev == j) return h;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Block-wide bitonic sort of n (power of two) key/value pairs in LDS.
+__device__ void bitonic_sort_rt(int32_t *keys, unsigned long long *vals, int n) {
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                int b = a + j;
+                bool up = (a & k) == 0;
+                int32_t ka = keys[a], kb = keys[b];
+                if ((ka > kb) == up) {
+                    keys[a] = kb;
+                    keys[b] = ka;
+                    unsigned long long va = vals[a];
+                    vals[a] = vals[b];
+                    vals[b] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// One task = one row and a part of m consecutive column tiles.  Each left
+// entry's segment of its right row inside the part is located (binary search,
+// or the row start), the segment lengths are block-scanned, and:
+//  * a part with at most kPartHashCap products is accumulated in an LDS hash
+//    overlaid on the tile memory, bitonic-sorted, and emitted as one segment;
+//  * otherwise the part is walked tile by tile: per tile the segments are
+//    found again (cursors carried between tiles when the row's entries fit one
+//    batch), and the flattened products are shared evenly by the threads
+//    (each walks 4 consecutive products) into a dense LDS tile.
+// Left entries are taken in batches of kDenseThreads.
 __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, int64_t n_list, const int64_t *task_base,
                                                          int64_t n_tasks, NumericArgs a) {
     constexpr int W = kTileW;
     constexpr int NW = W / 32;
     constexpr int NT = kDenseThreads;
-    constexpr int RUN = 4;
     __shared__ unsigned long long acc[W];
-    __shared__ uint32_t pres[NW];
     __shared__ uint32_t satw[NW];
-    __shared__ int64_t cur[kCursorCap];  // next segment start per entry (multi-tile chunks)
+    __shared__ int64_t cur[kCursorCap];  // next segment start per entry (single-batch rows)
     __shared__ int64_t seg_s[NT];        // segment start of each entry of the batch
+    __shared__ int32_t seg_l[NT];        // segment length (first: remaining row length)
     __shared__ int32_t seg_o[NT + 1];    // exclusive scan of segment lengths
     __shared__ int64_t sw[NT / 64];
     __shared__ int64_t s_task[4];
     __shared__ int64_t s_base;
     __shared__ int s_sat;
+    __shared__ int s_last;
     const int tid = threadIdx.x;
     for (int t = tid; t < W; t += NT) acc[t] = 0;
-    for (int t = tid; t < NW; t += NT) {
-        pres[t] = 0;
-        satw[t] = 0;
-    }
+    for (int t = tid; t < NW; t += NT) satw[t] = 0;
     if (tid == 0) s_sat = 0;
     __syncthreads();
     const int64_t ycols = a.ycols;
     const int64_t ntiles = (ycols + W - 1) / W;
-    for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
-        if (tid == 0) {
-            int64_t lo = 0, hi = n_list;  // last p with task_base[p] <= task
-            while (hi - lo > 1) {
-                int64_t mid = (lo + hi) >> 1;
-                if (task_base[mid] <= task)
-                    lo = mid;
-                else
-                    hi = mid;
+
+    // segments of the batch starting at eb over columns [c0, c1); start from
+    // cur[] when from_cursor.  The bound searches are shared out to groups of
+    // lanes (all 512 threads on few entries, one thread per entry on many).
+    // Returns the batch's product count (block-uniform).
+    auto segments = [&](int64_t xb, int64_t xlen, int64_t eb, int64_t c0, int64_t c1, bool from_cursor,
+                        bool keep_cursor) -> int64_t {
+        const int64_t nb = (xlen - eb < NT) ? xlen - eb : NT;
+        if (tid < nb) {
+            const int64_t e = eb + tid;
+            const int32_t k = a.X.col[xb + e];
+            if (a.X.cmask && !bit_test(a.X.cmask, k)) {
+                seg_s[tid] = 0;
+                seg_l[tid] = 0;
+            } else {
+                const int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
+                const int64_t s0 = from_cursor ? cur[e] : yb;
+                seg_s[tid] = s0;
+                seg_l[tid] = (int32_t)(ye - s0);
             }
-            s_task[0] = lo;
-            s_task[1] = task - task_base[lo];
-            s_task[2] = task_base[lo + 1] - task_base[lo];
         }
         __syncthreads();
-        const int64_t p = s_task[0], q = s_task[1], nch = s_task[2];
-        const int32_t c = list[p];
-        const int64_t i = a.cand ? a.cand[c] : c;
-        const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
-        const int64_t xlen = xe - xb;
-        const int64_t tpc = (ntiles + nch - 1) / nch;
-        const int64_t t0 = q * tpc;
-        const int64_t t1 = (t0 + tpc < ntiles) ? t0 + tpc : ntiles;
-        const bool use_cursor = (t1 - t0) > 1;  // implies xlen <= kCursorCap
-        if (use_cursor) {
-            for (int64_t e = tid; e < xlen; e += NT) {
-                int32_t k = a.X.col[xb + e];
-                int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
-                cur[e] = (t0 == 0) ? yb : lower_bound_col(a.Y.col, yb, ye, (int32_t)(t0 * W));
+        int g = 64;
+        while (g > 1 && (int64_t)(NT / g) < nb) g >>= 1;
+        const int li = tid & (g - 1);
+        const int64_t ngroups = NT / g;
+        const uint64_t gm = group_mask(g);
+        if (!from_cursor && c0 > 0) {
+            for (int64_t x = tid / g; x < nb; x += ngroups) {
+                const int64_t lo = seg_s[x], hi = lo + seg_l[x];
+                const int64_t r = group_lower_bound(a.Y.col, lo, hi, (int32_t)c0, g, li, gm);
+                if (li == 0) {
+                    seg_s[x] = r;
+                    seg_l[x] = (int32_t)(hi - r);
+                }
             }
             __syncthreads();
+        }
+        if (c1 < ycols) {
+            for (int64_t x = tid / g; x < nb; x += ngroups) {
+                const int64_t lo = seg_s[x], hi = lo + seg_l[x];
+                const int64_t r = group_lower_bound(a.Y.col, lo, hi, (int32_t)c1, g, li, gm);
+                if (li == 0) seg_l[x] = (int32_t)(r - lo);
+            }
+            __syncthreads();
+        }
+        const int64_t len = tid < nb ? seg_l[tid] : 0;
+        if (keep_cursor && tid < nb) cur[eb + tid] = seg_s[tid] + len;
+        int64_t tot;
+        const int64_t inc = block_inclusive_scan(len, sw, &tot);
+        seg_o[tid] = (int32_t)(inc - len);
+        if (tid == NT - 1) seg_o[NT] = (int32_t)inc;
+        __syncthreads();
+        return tot;
+    };
+    // visit the flattened products of the current batch: f(column, value).
+    // Each wavefront takes a contiguous chunk of items, one item per lane per
+    // step (unit stride), and tracks its entry with a forward walk.
+    auto products = [&](int64_t tot, const uint64_t *xval, auto f) {
+        const int lane = tid & 63, wave = tid >> 6;
+        constexpr int NWV = NT / 64;
+        const int64_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~int64_t(63);
+        const int64_t beg = wave * chunk;
+        const int64_t end = (beg + chunk < tot) ? beg + chunk : tot;
+        if (beg >= end) return;
+        int64_t item = beg + lane;
+        const int64_t first = item < end ? item : end - 1;
+        int lo = 0, hi = NT;  // last entry with seg_o <= first
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (seg_o[mid] <= first)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        int ent = lo;
+        int64_t o0 = seg_o[ent], o1 = seg_o[ent + 1], s0 = seg_s[ent];
+        uint64_t xv = xval ? xval[ent] : 1ull;
+        for (; item < end; item += 64) {
+            while (item >= o1) {
+                ++ent;
+                o0 = o1;
+                o1 = seg_o[ent + 1];
+                s0 = seg_s[ent];
+                if (xval) xv = xval[ent];
+            }
+            const int64_t fpos = s0 + (item - o0);
+            const int32_t j = a.Y.col[fpos];
+            if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
+            f(j, a.Y.val ? sat_mul(xv, a.Y.val[fpos]) : xv);
+        }
+    };
+
+    for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        if (tid < 64) {  // last p with task_base[p] <= task, by the first wavefront
+            const int64_t pp = group_lower_bound(task_base, 0, n_list, task + 1, 64, tid, ~0ull) - 1;
+            if (tid == 0) {
+                s_task[0] = pp;
+                s_task[1] = task - task_base[pp];
+                s_task[2] = task_base[pp + 1] - task_base[pp];
+            }
+        }
+        __syncthreads();
+        const int64_t p = s_task[0], qq = s_task[1];
+        const int64_t sp = a.dense_split[p];
+        const int64_t ks = sp & 255, sslot = sp >> 8;
+        const int64_t nparts = s_task[2] / ks;
+        const int64_t q = qq / ks, r = qq % ks;  // part, split
+        const int32_t c = list[p];
+        const int64_t i = a.cand ? a.cand[c] : c;
+        int64_t xb = a.X.rp[i], xlen = a.X.rp[i + 1] - xb;
+        if (ks > 1) {  // this workgroup's share of the left entries
+            const int64_t per = (xlen + ks - 1) / ks;
+            const int64_t e0 = r * per, e1 = (e0 + per < xlen) ? e0 + per : xlen;
+            xb += e0 < xlen ? e0 : xlen;
+            xlen = e1 > e0 ? e1 - e0 : 0;
+        }
+        const int64_t m = (ntiles + nparts - 1) / nparts;
+        const int64_t t0 = q * m;
+        const int64_t t1 = (t0 + m < ntiles) ? t0 + m : ntiles;
+        if (t0 >= t1) continue;  // block-uniform
+        const int64_t c0p = t0 * W, c1p = (t1 * W < ycols) ? t1 * W : ycols;
+        const bool single = xlen <= NT;
+
+        // part-level product count
+        int64_t ltot = 0;
+        if (ks == 1) {
+            for (int64_t eb = 0; eb < xlen; eb += NT) ltot += segments(xb, xlen, eb, c0p, c1p, false, false);
+            if (ltot == 0) continue;
+        }
+
+        if (ks == 1 && ltot <= a.tune.part_hash_cap && (c1p - c0p) <= (int64_t)kPartMaxTiles * W) {
+            // sparse part: values in an LDS hash, presence in a bitmap over the
+            // part's columns (both overlaid on the tile memory); emission walks
+            // the bitmap in column order and looks each column up.
+            int log2s = 6;
+            while ((int64_t(1) << log2s) < 2 * ltot) ++log2s;
+            const int S = 1 << log2s;
+            int32_t *keys = reinterpret_cast<int32_t *>(acc);
+            unsigned long long *vals = acc + S / 2;
+            uint32_t *bm = reinterpret_cast<uint32_t *>(acc + S / 2 + S);
+            const int nwords = (int)((c1p - c0p + 31) / 32);
+            for (int t = tid; t < S; t += NT) keys[t] = kEmptyKey;  // vals and bm are already zero
+            __syncthreads();
+            for (int64_t eb = 0; eb < xlen; eb += NT) {
+                const int64_t tot = single ? ltot : segments(xb, xlen, eb, c0p, c1p, false, false);
+                const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
+                products(tot, xval, [&](int32_t j, uint64_t v) {
+                    const uint32_t h = hash_find_rt(keys, j, log2s);
+                    acc_add(&vals[h], satw, h, v);
+                    const int64_t r = j - c0p;
+                    atomicOr(&bm[r >> 5], 1u << (r & 31));
+                });
+                __syncthreads();
+            }
+            const int wpt = (nwords + NT - 1) / NT;  // words per thread, contiguous
+            const int w0 = tid * wpt, w1 = (w0 + wpt < nwords) ? w0 + wpt : nwords;
+            int64_t local = 0;
+            for (int w = w0; w < w1; ++w) local += __popc(bm[w]);
+            int64_t cnt;
+            const int64_t incl = block_inclusive_scan(local, sw, &cnt);
+            if (tid == 0) s_base = (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)cnt);
+            __syncthreads();
+            const int64_t off = a.slot_off[c] + s_base;
+            int64_t pos = off + incl - local;
+            bool sat = false;
+            const uint32_t hmask = (uint32_t)S - 1u;
+            for (int w = w0; w < w1; ++w) {
+                uint32_t bits = bm[w];
+                while (bits) {
+                    const int b = __builtin_ctz(bits);
+                    bits &= bits - 1;
+                    const int32_t col = (int32_t)(c0p + (int64_t)w * 32 + b);
+                    uint32_t h = hash_of(col, log2s);
+                    while (keys[h] != col) h = (h + 1) & hmask;
+                    const bool sb = (satw[h >> 5] >> (h & 31)) & 1u;
+                    sat |= sb;
+                    a.slot_col[pos] = col;
+                    a.slot_val[pos] = sb ? kSat : vals[h];
+                    ++pos;
+                }
+            }
+            if (sat) s_sat = 1;
+            if (tid == 0) {
+                const int64_t sg = a.seg_base[c] + t0;
+                a.seg_cnt[sg] = cnt;
+                a.seg_src[sg] = off;
+                atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)cnt);
+            }
+            __syncthreads();
+            // restore the all-zero tile memory and bitmaps
+            const int zero_words = S / 2 + S + (nwords + 1) / 2;
+            for (int t = tid; t < zero_words; t += NT) acc[t] = 0;
+            for (int t = tid; t < (S + 31) / 32; t += NT) satw[t] = 0;
+            __syncthreads();
+            continue;
+        }
+
+        // dense part: tile by tile
+        if (single) {  // cursors at the part start
+            for (int64_t e = tid; e < xlen; e += NT) {
+                int32_t k = a.X.col[xb + e];
+                cur[e] = a.Y.rp[k];
+            }
+            __syncthreads();
+            if (c0p > 0) {
+                int g = 64;
+                while (g > 1 && (int64_t)(NT / g) < xlen) g >>= 1;
+                const int li = tid & (g - 1);
+                const uint64_t gm = group_mask(g);
+                for (int64_t x = tid / g; x < xlen; x += NT / g) {
+                    const int32_t k = a.X.col[xb + x];
+                    const int64_t r = group_lower_bound(a.Y.col, a.Y.rp[k], a.Y.rp[k + 1], (int32_t)c0p, g, li, gm);
+                    if (li == 0) cur[x] = r;
+                }
+                __syncthreads();
+            }
         }
         for (int64_t t = t0; t < t1; ++t) {
             const int64_t c0 = t * W;
             const int64_t c1 = (c0 + W < ycols) ? c0 + W : ycols;
             for (int64_t eb = 0; eb < xlen; eb += NT) {
-                const int64_t e = eb + tid;
-                int64_t len = 0;
-                if (e < xlen) {
-                    const int32_t k = a.X.col[xb + e];
-                    if (!(a.X.cmask && !bit_test(a.X.cmask, k))) {
-                        const int64_t yb = a.Y.rp[k], ye = a.Y.rp[k + 1];
-                        const int64_t s0 = use_cursor ? cur[e] : (c0 == 0 ? yb : lower_bound_col(a.Y.col, yb, ye, (int32_t)c0));
-                        const int64_t s1 = (c1 >= ycols) ? ye : lower_bound_col(a.Y.col, s0, ye, (int32_t)c1);
-                        len = s1 - s0;
-                        seg_s[tid] = s0;
-                        if (use_cursor) cur[e] = s1;
-                    }
-                }
-                int64_t tot;
-                const int64_t inc = block_inclusive_scan(len, sw, &tot);
-                seg_o[tid] = (int32_t)(inc - len);
-                if (tid == NT - 1) seg_o[NT] = (int32_t)inc;
-                __syncthreads();
+                const int64_t tot = segments(xb, xlen, eb, c0, c1, single, single);
                 const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
-                for (int64_t r0 = 0; r0 < tot; r0 += (int64_t)NT * RUN) {
-                    const int64_t first = r0 + (int64_t)tid * RUN;
-                    if (first >= tot) continue;
-                    int lo = 0, hi = NT;  // last entry with seg_o <= first
-                    while (hi - lo > 1) {
-                        int mid = (lo + hi) >> 1;
-                        if (seg_o[mid] <= first)
-                            lo = mid;
-                        else
-                            hi = mid;
-                    }
-                    int ent = lo;
-#pragma unroll
-                    for (int r = 0; r < RUN; ++r) {
-                        const int64_t item = first + r;
-                        if (item >= tot) break;
-                        while (seg_o[ent + 1] <= item) ++ent;
-                        const int64_t f = seg_s[ent] + (item - seg_o[ent]);
-                        const int32_t j = a.Y.col[f];
-                        if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
-                        const uint64_t xv = xval ? xval[ent] : 1ull;
-                        const uint64_t v = a.Y.val ? sat_mul(xv, a.Y.val[f]) : xv;
-                        const uint32_t slot = (uint32_t)(j - c0);
-                        atomicOr(&pres[slot >> 5], 1u << (slot & 31));
-                        acc_add(&acc[slot], satw, slot, v);
-                    }
-                }
+                products(tot, xval, [&](int32_t j, uint64_t v) {
+                    const uint32_t slot = (uint32_t)(j - c0);
+                    acc_add(&acc[slot], satw, slot, v);
+                });
                 __syncthreads();
             }
-            emit_dense_tile(a, c, i, t, c0, acc, pres, satw, sw, &s_base, &s_sat);
+            if (ks == 1) {
+                emit_dense_tile(a, c, i, t, c0, acc, satw, seg_o, sw, &s_base, &s_sat);
+            } else {
+                const int64_t gt = sslot * ntiles + t;
+                flush_split_tile(a, gt, ks, c, i, t, c0, acc, satw, seg_o, sw, &s_base, &s_sat, &s_last);
+            }
             __syncthreads();
         }
     }
@@ -868,16 +1253,17 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
     constexpr int W = kTileW;
     constexpr int NW = W / 32;
     __shared__ unsigned long long acc[W];
-    __shared__ uint32_t pres[NW];
     __shared__ uint32_t satw[NW];
+    __shared__ uint32_t pres[NW];
+    __shared__ int32_t gcnt[W / 64];
     __shared__ int64_t sw[kDenseThreads / 64];
     __shared__ int64_t s_base;
     __shared__ int s_sat;
     const int tid = threadIdx.x;
     for (int t = tid; t < W; t += kDenseThreads) acc[t] = 0;
     for (int t = tid; t < NW; t += kDenseThreads) {
-        pres[t] = 0;
         satw[t] = 0;
+        pres[t] = 0;
     }
     if (tid == 0) s_sat = 0;
     __syncthreads();
@@ -891,14 +1277,18 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
         const int64_t i = a.cand ? a.cand[c] : c;
         const int64_t c0 = t * W;
         const bool valued = b.prod_val != nullptr;
+        const bool sparse = (hi - lo) < (int64_t)(W / 4);  // block-uniform
         for (int64_t e = lo + tid; e < hi; e += kDenseThreads) {
             const uint32_t slot = (uint32_t)(b.prod_col[e] - c0);
             const uint64_t v = valued ? b.prod_val[e] : 1ull;
-            atomicOr(&pres[slot >> 5], 1u << (slot & 31));
+            if (sparse) atomicOr(&pres[slot >> 5], 1u << (slot & 31));
             acc_add(&acc[slot], satw, slot, v);
         }
         __syncthreads();
-        emit_dense_tile(a, c, i, t, c0, acc, pres, satw, sw, &s_base, &s_sat);
+        if (sparse)
+            emit_sparse_tile(a, c, i, t, c0, acc, pres, satw, sw, &s_base, &s_sat);
+        else
+            emit_dense_tile(a, c, i, t, c0, acc, satw, gcnt, sw, &s_base, &s_sat);
         __syncthreads();
     }
     __syncthreads();

@@ -7,10 +7,13 @@
 //   Sketch   degree-aware: the columns of X follow the in-degree of the
 //            junction type under the last relation of X, the rows of Y follow
 //            the out-degree under the first relation of Y (joint log2 buckets
-//            of both degrees), each capped by the other operand's extent; the
-//            result density is E_ac applied to the N_op products over the
-//            active block.  This is exact for N_op when X and Y are single
-//            relations and catches the hub rows that the uniform estimate
+//            of both degrees), each capped by the other operand's extent.
+//            The result's nonzeros are the distinct cells hit when each row's
+//            products fall on columns with probability proportional to their
+//            in-degree under Y's last relation (log2 buckets): a column of
+//            weight w is hit with probability 1 - exp(-n w) by n products.
+//            This is exact for N_op when X and Y are single relations and
+//            catches the hub rows and hub columns that the uniform estimate
 //            misses.
 // The order never changes the result (associativity), only its cost.
 #include "planner.hpp"
@@ -37,8 +40,33 @@ static double sat_fill(double n_op, double cells) {
     return cells * -std::expm1(-n_op / cells);
 }
 
+// expected distinct columns hit by n products spread by column popularity
+static double fill_columns(const ColumnHist &h, double sel, double n) {
+    if (h.total <= 0 || n <= 0 || sel <= 0) return 0;
+    double s = 0;
+    for (const auto &b : h.buckets) s += b.n * sel * -std::expm1(-n * b.deg / (h.total * sel));
+    return s;
+}
+
+ColumnHist make_column_hist(const int32_t *in_deg, int64_t n) {
+    ColumnHist h;
+    std::map<int, ColumnHist::Bucket> acc;
+    for (int64_t b = 0; b < n; ++b) {
+        const int64_t d = in_deg[b];
+        if (d <= 0) continue;
+        int lg = 0;
+        while ((d >> lg) > 1) ++lg;
+        auto &bk = acc[lg];
+        bk.n += 1;
+        bk.deg += (double)d;
+        h.total += (double)d;
+    }
+    for (auto &kv : acc) h.buckets.push_back({kv.second.n, kv.second.deg / kv.second.n});
+    return h;
+}
+
 ChainStats estimate_product(const ChainStats &x, const ChainStats &y, const JunctionSketch *j, double sel,
-                            Estimator est, double *n_op_out) {
+                            const ColumnHist *ycols, double ycol_sel, Estimator est, double *n_op_out) {
     ChainStats z;
     z.dim_r = x.dim_r;
     z.dim_c = y.dim_c;
@@ -68,15 +96,22 @@ ChainStats estimate_product(const ChainStats &x, const ChainStats &y, const Junc
         }
         n_op = s * sel;
         z.rows = x.rows * -std::expm1(-(x.rows > 0 ? n_op / x.rows : 0));
-        z.cols = y.cols * -std::expm1(-(y.cols > 0 ? n_op / y.cols : 0));
-        z.nnz = std::min(n_op, sat_fill(n_op, z.rows * z.cols));
+        if (ycols && ycols->total > 0) {
+            const double per_row = z.rows > 0 ? n_op / z.rows : 0;
+            z.nnz = std::min(n_op, z.rows * fill_columns(*ycols, ycol_sel, per_row));
+            z.cols = std::min(y.cols, fill_columns(*ycols, ycol_sel, n_op));
+        } else {
+            z.cols = y.cols * -std::expm1(-(y.cols > 0 ? n_op / y.cols : 0));
+            z.nnz = std::min(n_op, sat_fill(n_op, z.rows * z.cols));
+        }
     }
     if (n_op_out) *n_op_out = n_op;
     return z;
 }
 
 PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<JunctionSketch> &junctions,
-                      const std::vector<double> &junction_sel, Estimator est, const CostCoeffs &cc) {
+                      const std::vector<double> &junction_sel, const std::vector<ColumnHist> &col_hists,
+                      const std::vector<double> &col_sel, Estimator est, const CostCoeffs &cc) {
     const int p = (int)leaves.size();
     PlanResult out;
     if (p == 0) return out;
@@ -92,7 +127,9 @@ PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<J
                 const JunctionSketch *js = k < (int)junctions.size() ? &junctions[k] : nullptr;
                 const double sel = k < (int)junction_sel.size() ? junction_sel[k] : 1.0;
                 double n_op = 0;
-                ChainStats z = estimate_product(D[i][k], D[k + 1][j], js, sel, est, &n_op);
+                const ColumnHist *yc = j < (int)col_hists.size() ? &col_hists[j] : nullptr;
+                const double ycs = j < (int)col_sel.size() ? col_sel[j] : 1.0;
+                ChainStats z = estimate_product(D[i][k], D[k + 1][j], js, sel, yc, ycs, est, &n_op);
                 double c = C[i][k] + C[k + 1][j] + cc.alpha * D[i][k].nnz + cc.beta * n_op + cc.gamma * z.nnz +
                            cc.delta;
                 if (c < best) {  // strict: ties keep the smallest split

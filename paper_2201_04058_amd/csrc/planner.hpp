@@ -27,6 +27,15 @@ struct JunctionSketch {
     double sum_in = 0, sum_out = 0;  // over all nodes of the type
 };
 
+// Column popularity of a relation: its columns grouped by log2 in-degree.
+struct ColumnHist {
+    struct Bucket {
+        double n, deg;
+    };
+    std::vector<Bucket> buckets;
+    double total = 0;  // sum of in-degrees
+};
+
 struct CostCoeffs {
     double alpha = 12.0;   // per nonzero of the left operand
     double beta = 12.0;    // per product (N_op)
@@ -45,12 +54,18 @@ struct PlanResult {
 // Dynamic program of Eq. 1 over p = leaves.size() matrices.  junctions[k]
 // (k < p-1) describes the node type between leaf k and k+1, and
 // junction_sel[k] the fraction of its nodes kept by that position's mask.
+// col_hists[i] / col_sel[i] describe the columns of leaf i (used by Sketch to
+// estimate how many distinct cells the products of a product hit).
 PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<JunctionSketch> &junctions,
-                      const std::vector<double> &junction_sel, Estimator est, const CostCoeffs &cc);
+                      const std::vector<double> &junction_sel, const std::vector<ColumnHist> &col_hists,
+                      const std::vector<double> &col_sel, Estimator est, const CostCoeffs &cc);
 
-// Product estimate for X * Y meeting at a junction (exposed for tests).
+// Product estimate for X * Y meeting at a junction; ycols describes the
+// columns of Y's last relation (exposed for tests).
 ChainStats estimate_product(const ChainStats &x, const ChainStats &y, const JunctionSketch *junction, double sel,
-                            Estimator est, double *n_op);
+                            const ColumnHist *ycols, double ycol_sel, Estimator est, double *n_op);
+
+ColumnHist make_column_hist(const int32_t *in_deg, int64_t n);
 
 // The paper's E_ac density estimate: 1 - (1 - rx*ry)^k, computed stably.
 double eac_density(double rx, double ry, double k);

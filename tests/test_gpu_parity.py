@@ -342,3 +342,27 @@ def test_memory_budget(atp, oracle_mod, tiny_cfg):
     ctx.load_hin(hin)
     assert_same(ctx.eval_query(q), ref)
     ctx.close()
+
+
+@pytest.mark.parametrize("tune", [{"ATP_SPLIT_OPS": "1024"}, {"ATP_PART_HASH_CAP": "0"}, {"ATP_PART_TARGET": "1"},
+                                  {"ATP_PART_TARGET": "100000", "ATP_TASK_OPS": "1"}, {"ATP_BUCKET_RATIO": "0"},
+                                  {"ATP_SPLIT_OPS": "1024", "ATP_PART_TARGET": "64", "ATP_BUCKET_RATIO": "1"}])
+def test_every_kernel_path_under_forced_tunings(atp, oracle_mod, tune, monkeypatch):
+    """The binning thresholds only move rows between kernels (hash parts,
+    dense tiles, split tiles, tile buckets); results must not change."""
+    for k, v in tune.items():
+        monkeypatch.setenv(k, v)
+    for name, scale in [("scholarly", 0.02), ("news", 0.03)]:
+        hin, rng = configs.make_hin(name, scale)
+        qs = configs.make_queries(name, hin, rng)
+        ctx = make_ctx(atp, hin)
+        for q in qs:
+            ref = oracle_mod.eval_full(hin, q, nthreads=8)
+            assert_same(ctx.eval_query(q), ref, f"{tune} {q.name}")
+            assert_same(ctx.eval_query(q, plan="(((" + ",".join(str(i) for i in range(2)) + "),2),3)"
+                                       if len(q.types) == 5 else None), ref, f"{tune} {q.name} left-deep")
+        ctx.close()
+    hin, qs = configs.load("tiny", use_cache=False)
+    ctx = make_ctx(atp, hin)
+    assert_same(ctx.eval_query(qs[0]), oracle_mod.eval_full(hin, qs[0]), f"{tune} tiny")
+    ctx.close()
