@@ -58,6 +58,8 @@ typedef struct atp_result atp_result;
 #define ATP_OPT_PROFILE (1u << 0)   /* time every kernel launch with HIP events (atp_kernel_times) */
 #define ATP_OPT_PLAN_EAC (1u << 1)  /* planner uses the paper's uniform E_ac estimate (Sec. 3.2) */
 #define ATP_OPT_COUNT_BYTES (1u << 2) /* count algorithmic bytes per kernel (extra passes; not for timing) */
+#define ATP_OPT_NO_RESTRICT (1u << 3) /* compute right sub-chains on all rows, not only on the rows the left
+                                         operand reaches (same result; keeps sub-results start-independent) */
 
 typedef struct {
     int device;                 /* HIP device ordinal */

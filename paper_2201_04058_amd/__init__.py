@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libatrapos.so")
 
 ATP_OK, ATP_EINVAL, ATP_ENOMEM, ATP_EOVERFLOW, ATP_ESCHEMA, ATP_EDEVICE, ATP_EBUDGET, ATP_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
-ATP_OPT_PROFILE, ATP_OPT_PLAN_EAC, ATP_OPT_COUNT_BYTES = 1, 2, 4
+ATP_OPT_PROFILE, ATP_OPT_PLAN_EAC, ATP_OPT_COUNT_BYTES, ATP_OPT_NO_RESTRICT = 1, 2, 4, 8
 ATP_REL_DEVICE_PTRS, ATP_REL_ADD_REVERSE = 1, 2
 ATP_I16, ATP_I32, ATP_I64 = 1, 2, 3
 ATP_C_RANGE, ATP_C_IDSET = 1, 2
@@ -183,12 +183,13 @@ class Context:
     """One engine context (device, stream, memory pool, registered network)."""
 
     def __init__(self, device: int = 0, stream: int | None = None, budget_bytes: int = 0,
-                 profile: bool = False, plan_eac: bool = False):
+                 profile: bool = False, plan_eac: bool = False, no_restrict: bool = False):
         o = atp_options()
         o.device = device
         o.hip_stream = stream
         o.mem_budget_bytes = budget_bytes
-        o.flags = (ATP_OPT_PROFILE if profile else 0) | (ATP_OPT_PLAN_EAC if plan_eac else 0)
+        o.flags = (ATP_OPT_PROFILE if profile else 0) | (ATP_OPT_PLAN_EAC if plan_eac else 0) | \
+            (ATP_OPT_NO_RESTRICT if no_restrict else 0)
         h = ctypes.c_void_p()
         _check(lib().atp_create(ctypes.byref(o), ctypes.byref(h)), "atp_create")
         self._h = h
@@ -290,9 +291,10 @@ class Context:
         return self.eval(query.types, query.constraints, plan=plan)
 
     # --- diagnostics -----------------------------------------------------
-    def set_flags(self, profile: bool = False, plan_eac: bool = False, count_bytes: bool = False) -> None:
+    def set_flags(self, profile: bool = False, plan_eac: bool = False, count_bytes: bool = False,
+                  no_restrict: bool = False) -> None:
         f = (ATP_OPT_PROFILE if profile else 0) | (ATP_OPT_PLAN_EAC if plan_eac else 0) | \
-            (ATP_OPT_COUNT_BYTES if count_bytes else 0)
+            (ATP_OPT_COUNT_BYTES if count_bytes else 0) | (ATP_OPT_NO_RESTRICT if no_restrict else 0)
         _check(lib().atp_set_flags(self._h, f), "atp_set_flags")
 
     def kernel_times(self) -> dict:

@@ -404,14 +404,15 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     };
     if (n_cand == 0 || ycols_eff == 0) return finish_empty();
 
-    Buf hdr, nop, ub, nseg, bin, long_list, bin_lists, dense_chunks, slot_off, seg_base, task_base, tmp;
+    Buf hdr, nop, ub, nseg, bin, long_len, long_off, bin_lists, dense_chunks, slot_off, seg_base, task_base, tmp;
     Buf bucket_chunks, bucket_nop, chunk_base, prod_base, dense_split;
     TRY(hdr.alloc(pool, sizeof(StepHeader)));
     TRY(nop.alloc(pool, 8 * n_cand));
     TRY(ub.alloc(pool, 8 * n_cand));
     TRY(nseg.alloc(pool, 8 * n_cand));
     TRY(bin.alloc(pool, 4 * n_cand));
-    TRY(long_list.alloc(pool, 4 * n_cand));
+    TRY(long_len.alloc(pool, 8 * n_cand));
+    TRY(long_off.alloc(pool, 8 * (n_cand + 1)));
     TRY(bin_lists.alloc(pool, 4 * (size_t)n_cand * BIN_COUNT));
     TRY(dense_chunks.alloc(pool, 8 * n_cand));
     TRY(slot_off.alloc(pool, 8 * (n_cand + 1)));
@@ -441,7 +442,9 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     sa.ub = ub.as<int64_t>();
     sa.nseg = nseg.as<int64_t>();
     sa.bin = bin.as<int32_t>();
-    sa.long_list = long_list.as<int32_t>();
+    sa.long_len = long_len.as<int64_t>();
+    sa.long_off = long_off.as<int64_t>();
+    sa.scan_tmp = tmp.as<int64_t>();
     sa.bin_lists = bin_lists.as<int32_t>();
     sa.dense_chunks = dense_chunks.as<int64_t>();
     sa.bucket_chunks = bucket_chunks.as<int64_t>();
@@ -802,9 +805,48 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     int n_products = 0;
     bool overflow = false;
     std::vector<PlanTree> &tree = forced;
-    // post-order evaluation; returns the matrix of node `v` into `outm`
-    std::function<atp_status(int, bool, Mat &, int &, int &)> run =
-        [&](int v, bool as_left, Mat &outm, int &lo, int &hi) -> atp_status {
+    std::vector<Buf> keep;  // restriction buffers, alive until the query ends
+    const bool restrict_rows = (c->flags & ATP_OPT_NO_RESTRICT) == 0;
+    // Rows of a right sub-chain that can matter: the columns its left neighbour uses.
+    struct Restriction {
+        const uint32_t *bits = nullptr;
+        const int32_t *list = nullptr;
+        int64_t n = 0;
+    };
+    auto make_restriction = [&](const Mat &X, int64_t n_rows_y, Restriction &r) -> atp_status {
+        const int64_t words = (n_rows_y + 31) / 32;
+        Buf bits, cnt, scan, tmpb, list;
+        TRY(bits.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(words, 1)));
+        TRY(cnt.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(words, 1)));
+        TRY(scan.alloc(&c->pool, 8 * (size_t)(words + 1)));
+        TRY(tmpb.alloc(&c->pool, 8 * (size_t)scan_tmp_elems(words)));
+        launch_fill_u32(bits.as<uint32_t>(), words, 0u, s, t);
+        Buf len, off, tmpc;
+        if (X.leaf) {
+            TRY(len.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(X.n_cand, 1)));
+            TRY(off.alloc(&c->pool, 8 * (size_t)(X.n_cand + 1)));
+            TRY(tmpc.alloc(&c->pool, 8 * (size_t)scan_tmp_elems(X.n_cand)));
+            launch_leaf_cols_to_bits(X.op, X.cand, X.n_cand, len.as<int64_t>(), off.as<int64_t>(), tmpc.as<int64_t>(),
+                                     bits.as<uint32_t>(), s, t);
+        } else
+            launch_cols_to_bits(X.op.col, X.nnz, bits.as<uint32_t>(), s, t);
+        launch_bits_count(bits.as<uint32_t>(), words, cnt.as<int64_t>(), scan.as<int64_t>(), tmpb.as<int64_t>(), s, t);
+        int64_t n = 0;
+        HIPTRY(hipMemcpyAsync(&n, scan.as<int64_t>() + words, 8, hipMemcpyDeviceToHost, s));
+        TRY(sync(c));
+        TRY(list.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(n, 1)));
+        launch_bits_scatter(bits.as<uint32_t>(), words, scan.as<int64_t>(), list.as<int32_t>(), s, t);
+        r.bits = bits.as<uint32_t>();
+        r.list = list.as<int32_t>();
+        r.n = n;
+        keep.push_back(std::move(bits));
+        keep.push_back(std::move(list));
+        keep.push_back(std::move(scan));  // the scatter may still be reading it
+        return ATP_OK;
+    };
+    // post-order evaluation of node v into outm; rs restricts v's rows
+    std::function<atp_status(int, bool, const Restriction *, Mat &, int &, int &)> run =
+        [&](int v, bool as_left, const Restriction *rs, Mat &outm, int &lo, int &hi) -> atp_status {
         const PlanTree &nd = tree[v];
         if (nd.leaf >= 0) {
             lo = hi = nd.leaf;
@@ -817,12 +859,29 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
             outm.nnz = L.nnz;
             outm.cand = L.cand;
             outm.n_cand = L.n_cand;
+            if (rs) {
+                // rs.bits is a subset of this position's mask (it is the masked column set of the
+                // left neighbour), so it replaces the row mask; an id list stays the candidate list
+                outm.op.rmask = rs->bits;
+                if (!outm.cand) {
+                    outm.cand = rs->list;
+                    outm.n_cand = rs->n;
+                }
+            }
             return ATP_OK;
         }
         Mat X, Y;
         int l0, l1, r0, r1;
-        TRY(run(nd.left, true, X, l0, l1));
-        TRY(run(nd.right, false, Y, r0, r1));
+        TRY(run(nd.left, true, rs, X, l0, l1));
+        Restriction r2;
+        const Restriction *rp = nullptr;
+        const int64_t y_rows = c->types[types[l1 + 1]].count;
+        const bool x_small = X.leaf ? (X.cand != nullptr && X.n_cand < y_rows) : (X.nnz < y_rows / 2);
+        if (restrict_rows && x_small) {
+            TRY(make_restriction(X, y_rows, r2));
+            rp = &r2;
+        }
+        TRY(run(nd.right, false, rp, Y, r0, r1));
         lo = l0;
         hi = r1;
         const int last_pos = r1 + 1;  // metapath position of Y's last type
@@ -855,7 +914,7 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         n_products = 1;
         overflow = sat;
     } else {
-        stt = run(forced_root, false, R, lo, hi);
+        stt = run(forced_root, false, nullptr, R, lo, hi);
     }
     if (stt != ATP_OK) {
         if (stt == ATP_EDEVICE) c->broken = true;

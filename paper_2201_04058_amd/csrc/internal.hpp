@@ -62,8 +62,6 @@ struct StepHeader {
     int64_t slots_total;      // sum of per-row upper bounds
     int64_t segs_total;       // number of output segments
     int64_t n_op_total;       // products
-    int64_t n_long;           // rows handed to the long-row symbolic kernel
-    int64_t n_huge;           // rows split across the whole grid in the symbolic pass
     int64_t bin_count[BIN_COUNT];
     int64_t dense_tasks;      // dense-bin tasks
     int64_t bucket_chunks;    // bucket-bin work items
@@ -107,7 +105,9 @@ struct SymbolicArgs {
     int64_t *ub;              // [n_cand]
     int64_t *nseg;            // [n_cand]
     int32_t *bin;             // [n_cand]
-    int32_t *long_list;       // [n_cand] long X rows from the front, huge rows from the back
+    int64_t *long_len;        // [n_cand] chunks of rows left to the long-row pass
+    int64_t *long_off;        // [n_cand + 1] their exclusive scan
+    int64_t *scan_tmp;        // scan_tmp_elems(n_cand)
     int32_t *bin_lists;       // [BIN_COUNT * n_cand]
     int64_t *dense_chunks;    // [n_cand] tasks per dense candidate (indexed by dense list position)
     int64_t *dense_split;     // [n_cand] split slot * 256 + split factor per dense candidate
@@ -159,6 +159,18 @@ void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row
 void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
                            hipStream_t s, KernelTimer *t);
 void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s);
+
+// row restriction: columns used by a left operand -> bitmap -> ascending list
+void launch_cols_to_bits(const int32_t *col, int64_t nnz, uint32_t *bits, hipStream_t s, KernelTimer *t);
+// len/off hold n_cand (+1) int64, tmp scan_tmp_elems(n_cand)
+void launch_leaf_cols_to_bits(const Operand &X, const int32_t *cand, int64_t n_cand, int64_t *len, int64_t *off,
+                              int64_t *tmp, uint32_t *bits, hipStream_t s, KernelTimer *t);
+// per-word popcounts (cnt[words]) and their exclusive scan (scan[words+1], tmp scan_tmp_elems(words))
+void launch_bits_count(const uint32_t *bits, int64_t words, int64_t *cnt, int64_t *scan, int64_t *tmp, hipStream_t s,
+                       KernelTimer *t);
+// ascending list of set bits (list holds scan[words] entries)
+void launch_bits_scatter(const uint32_t *bits, int64_t words, const int64_t *scan, int32_t *list, hipStream_t s,
+                         KernelTimer *t);
 
 // algorithmic-byte accounting: acc[5] = rows, left entries, result entries,
 // distinct right rows, their entries

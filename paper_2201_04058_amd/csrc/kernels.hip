@@ -24,8 +24,8 @@ namespace atp {
 
 namespace {
 
-constexpr int kLongRow = 256;     // X rows longer than this get a workgroup in the symbolic pass
-constexpr int kHugeRow = 32768;   // ... and longer than this are split across the whole grid
+constexpr int kLongRow = 128;     // X rows longer than this go to the chunked symbolic pass
+constexpr int64_t kSymChunk = 4096;
 
 __device__ __forceinline__ bool bit_test(const uint32_t *b, int64_t i) {
     return (b[i >> 5] >> (i & 31)) & 1u;
@@ -281,69 +281,52 @@ __global__ void k_popcount(const uint32_t *bits, int64_t words, int64_t *out) {
 // symbolic pass
 
 __global__ void k_symbolic(SymbolicArgs a) {
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= a.n_cand) return;
-    int64_t i = a.cand ? a.cand[c] : c;
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t nop = 0;
-    if (!(a.X.rmask && !bit_test(a.X.rmask, i))) {
-        int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
-        if (e - b > kHugeRow) {
-            unsigned long long slot = atomicAdd((unsigned long long *)&a.hdr->n_huge, 1ull);
-            a.long_list[a.n_cand - 1 - (int64_t)slot] = (int32_t)c;
-            a.nop[c] = 0;
-            return;
+    if (c < a.n_cand) {
+        const int64_t i = a.cand ? a.cand[c] : c;
+        int64_t deferred = 0;
+        if (!(a.X.rmask && !bit_test(a.X.rmask, i))) {
+            const int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
+            if (e - b > kLongRow) {
+                deferred = (e - b + kSymChunk - 1) / kSymChunk;
+            } else {
+                for (int64_t p = b; p < e; ++p) {
+                    int32_t k = a.X.col[p];
+                    if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
+                    nop += a.Y.rp[k + 1] - a.Y.rp[k];
+                }
+            }
         }
-        if (e - b > kLongRow) {
-            unsigned long long slot = atomicAdd((unsigned long long *)&a.hdr->n_long, 1ull);
-            a.long_list[slot] = (int32_t)c;
-            a.nop[c] = 0;
-            return;
-        }
-        for (int64_t p = b; p < e; ++p) {
-            int32_t k = a.X.col[p];
-            if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
-            nop += a.Y.rp[k + 1] - a.Y.rp[k];
-        }
+        a.nop[c] = nop;
+        a.long_len[c] = deferred;  // chunks left to the long-row pass
     }
-    a.nop[c] = nop;
-    if (nop) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)nop);
+    int64_t wsum = nop;
+    for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
+    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)wsum);
 }
 
-__global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a) {
+// Long rows are cut into chunks of kSymChunk entries (long_len holds each
+// candidate's chunk count, long_off its exclusive scan); one workgroup per
+// chunk sums the products and adds them with one atomic.
+__global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a, const int64_t *long_off) {
     __shared__ int64_t sw[4];
-    const int64_t n_long = a.hdr->n_long;
-    for (int64_t t = blockIdx.x; t < n_long; t += gridDim.x) {
-        int32_t c = a.long_list[t];
-        int64_t i = a.cand ? a.cand[c] : c;
-        int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
+    __shared__ int64_t s_c;
+    const int64_t n_chunks = long_off[a.n_cand];
+    for (int64_t id = blockIdx.x; id < n_chunks; id += gridDim.x) {
+        if (threadIdx.x < 64) {
+            const int64_t c = group_lower_bound(long_off, 0, a.n_cand, id + 1, 64, threadIdx.x, ~0ull) - 1;
+            if (threadIdx.x == 0) s_c = c;
+        }
+        __syncthreads();
+        const int64_t c = s_c;
+        const int64_t i = a.cand ? a.cand[c] : c;
+        const int64_t q = id - long_off[c];
+        const int64_t b = a.X.rp[i] + q * kSymChunk;
+        const int64_t e = (b + kSymChunk < a.X.rp[i + 1]) ? b + kSymChunk : a.X.rp[i + 1];
         int64_t s = 0;
         for (int64_t p = b + threadIdx.x; p < e; p += blockDim.x) {
-            int32_t k = a.X.col[p];
-            if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
-            s += a.Y.rp[k + 1] - a.Y.rp[k];
-        }
-        int64_t tot;
-        block_inclusive_scan(s, sw, &tot);
-        if (threadIdx.x == 0) {
-            a.nop[c] = tot;
-            if (tot) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)tot);
-        }
-    }
-}
-
-// rows longer than kHugeRow: every block takes a slice of each row
-__global__ __launch_bounds__(256) void k_symbolic_huge(SymbolicArgs a) {
-    __shared__ int64_t sw[4];
-    const int64_t n_huge = a.hdr->n_huge;
-    for (int64_t t = 0; t < n_huge; ++t) {
-        int32_t c = a.long_list[a.n_cand - 1 - t];
-        int64_t i = a.cand ? a.cand[c] : c;
-        int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
-        int64_t chunk = (e - b + gridDim.x - 1) / gridDim.x;
-        int64_t lo = b + chunk * blockIdx.x, hi = lo + chunk < e ? lo + chunk : e;
-        int64_t s = 0;
-        for (int64_t p = lo + threadIdx.x; p < hi; p += blockDim.x) {
-            int32_t k = a.X.col[p];
+            const int32_t k = a.X.col[p];
             if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
             s += a.Y.rp[k + 1] - a.Y.rp[k];
         }
@@ -1330,6 +1313,64 @@ __global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int6
 __global__ void k_copy_i64(const int64_t *src, int64_t *dst) { *dst = *src; }
 
 // ---------------------------------------------------------------------------
+// row restriction of a right subtree: the columns that a left operand uses
+
+// bits |= columns of every stored entry of a product (all entries are live)
+__global__ void k_cols_to_bits(const int32_t *col, int64_t nnz, uint32_t *bits) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = col[e];
+        atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+}
+
+// lengths of the candidate rows of a relation (0 for rows outside the row mask)
+__global__ void k_cand_lengths(Operand X, const int32_t *cand, int64_t n_cand, int64_t *len) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n_cand; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = cand ? cand[c] : c;
+        len[c] = (X.rmask && !bit_test(X.rmask, i)) ? 0 : X.rp[i + 1] - X.rp[i];
+    }
+}
+
+// bits |= columns of the candidate rows (column mask applied), entries
+// flattened over the grid via the exclusive scan of the row lengths
+__global__ void k_leaf_cols_to_bits(Operand X, const int32_t *cand, int64_t n_cand, const int64_t *off,
+                                    uint32_t *bits) {
+    const int64_t total = off[n_cand];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = n_cand;  // last row with off <= e
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (off[mid] <= e)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t i = cand ? cand[lo] : lo;
+        const int32_t j = X.col[X.rp[i] + (e - off[lo])];
+        if (X.cmask && !bit_test(X.cmask, j)) continue;
+        atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+}
+
+__global__ void k_word_counts(const uint32_t *bits, int64_t words, int64_t *cnt) {
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x)
+        cnt[w] = __popc(bits[w]);
+}
+
+// ascending list of set bits, given the exclusive scan of the word counts
+__global__ void k_bits_to_list(const uint32_t *bits, int64_t words, const int64_t *scan, int32_t *list) {
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t b = bits[w];
+        int64_t pos = scan[w];
+        while (b) {
+            const int k = __builtin_ctz(b);
+            b &= b - 1;
+            list[pos++] = (int32_t)(w * 32 + k);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // algorithmic-byte accounting (counting mode only, never on the timed path)
 
 // acc[0] rows, acc[1] left-operand entries, acc[2] result entries; marks the
@@ -1458,8 +1499,9 @@ void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
     if (a.n_cand <= 0) return;
     if ((a.n_cand + 255) / 256 > 0x7FFFFFFF) return;
     ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic, dim3((unsigned)((a.n_cand + 255) / 256)), dim3(256), 0, s, a);
-    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic_long, dim3(device_cus() * 4), dim3(256), 0, s, a);
-    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic_huge, dim3(device_cus() * 4), dim3(256), 0, s, a);
+    launch_scan_i64(a.long_len, a.long_off, a.n_cand, a.scan_tmp, s, t);
+    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic_long, dim3(device_cus() * 8), dim3(256), 0, s, a,
+               (const int64_t *)a.long_off);
 }
 
 void launch_bin_rows(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
@@ -1552,6 +1594,35 @@ void launch_mark_bytes(const uint32_t *ymark, const int64_t *yrp, int64_t yrows,
     if (yrows <= 0) return;
     hipLaunchKernelGGL(k_mark_bytes, dim3(grid_for(yrows, 256, 4096)), dim3(256), 0, s, ymark, yrp, yrows,
                        (unsigned long long *)acc);
+}
+
+void launch_cols_to_bits(const int32_t *col, int64_t nnz, uint32_t *bits, hipStream_t s, KernelTimer *t) {
+    if (nnz <= 0) return;
+    ATP_LAUNCH("restrict", 0, 0, s, k_cols_to_bits, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, col, nnz, bits);
+}
+
+void launch_leaf_cols_to_bits(const Operand &X, const int32_t *cand, int64_t n_cand, int64_t *len, int64_t *off,
+                              int64_t *tmp, uint32_t *bits, hipStream_t s, KernelTimer *t) {
+    if (n_cand <= 0) return;
+    ATP_LAUNCH("restrict", 0, 0, s, k_cand_lengths, dim3(grid_for(n_cand, 256, 8192)), dim3(256), 0, s, X, cand, n_cand,
+               len);
+    launch_scan_i64(len, off, n_cand, tmp, s, t);
+    ATP_LAUNCH("restrict", 0, 0, s, k_leaf_cols_to_bits, dim3(device_cus() * 8), dim3(256), 0, s, X, cand, n_cand,
+               (const int64_t *)off, bits);
+}
+
+void launch_bits_count(const uint32_t *bits, int64_t words, int64_t *cnt, int64_t *scan, int64_t *tmp, hipStream_t s,
+                       KernelTimer *t) {
+    if (words <= 0) return;
+    ATP_LAUNCH("restrict", 0, 0, s, k_word_counts, dim3(grid_for(words, 256, 8192)), dim3(256), 0, s, bits, words, cnt);
+    launch_scan_i64(cnt, scan, words, tmp, s, t);
+}
+
+void launch_bits_scatter(const uint32_t *bits, int64_t words, const int64_t *scan, int32_t *list, hipStream_t s,
+                         KernelTimer *t) {
+    if (words <= 0) return;
+    ATP_LAUNCH("restrict", 0, 0, s, k_bits_to_list, dim3(grid_for(words, 256, 8192)), dim3(256), 0, s, bits, words,
+               scan, list);
 }
 
 void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s) {

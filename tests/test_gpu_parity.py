@@ -77,12 +77,13 @@ def test_random_tiny_networks(atp, oracle_mod, block):
         ctx.close()
 
 
+@pytest.mark.parametrize("no_restrict", [False, True])
 @pytest.mark.parametrize("name,scale", [("scholarly", 0.002), ("scholarly", 0.02), ("news", 0.005),
                                         ("news", 0.03)])
-def test_scaled_configs_every_plan(atp, oracle_mod, name, scale):
+def test_scaled_configs_every_plan(atp, oracle_mod, name, scale, no_restrict):
     hin, rng = configs.make_hin(name, scale)
     qs = configs.make_queries(name, hin, rng)
-    ctx = make_ctx(atp, hin)
+    ctx = make_ctx(atp, hin, no_restrict=no_restrict)
     for q in qs:
         ref = oracle_mod.eval_full(hin, q, nthreads=8)
         assert_same(ctx.eval_query(q), ref, q.name)
