@@ -165,6 +165,72 @@ atp_status atp_result_stats(const atp_result *res, atp_eval_stats *stats, char *
 
 atp_status atp_result_free(atp_result *res);
 
+/* --- workload evaluation with an intermediate-result cache (Sec. 3.3-3.4) ---
+ *
+ * With a cache configured, every atp_eval / atp_eval_plan call is one query
+ * of a metapath query workload (Problem 2, MQWE).  The query's type string is
+ * inserted into the context's Overlap Tree (Sec. 3.3: a generalised suffix
+ * tree of metapaths with per-node occurrence frequency and a constraints
+ * index), the planner prices every sub-chain whose result is cached at zero
+ * (Sec. 3.2, last paragraph), and after evaluation the cache insertion policy
+ * tries to keep results in device memory:
+ *   ATP_CACHE_OTREE  Atrapos-OTree: the whole query and the longest computed
+ *                    sub-metapath that is an Overlap-Tree overlap (Sec. 3.4.1),
+ *                    replaced by Algorithm 1 (PGDS utility f*c/s + L, with the
+ *                    cost of cached entries in an evicted / inserted entry's
+ *                    subtree reinstated / subtracted);
+ *   ATP_CACHE_PGDS   same insertion, plain PGDS replacement;
+ *   ATP_CACHE_LRU    same insertion, LRU replacement;
+ *   ATP_CACHE_CBS1   LRU of final query results only (Sec. 4.1 baseline CBS1);
+ *   ATP_CACHE_CBS2   LRU of every intermediate result (baseline CBS2).
+ * Items larger than 80% of the budget are never cached (Sec. 4.1).  Sub-chain
+ * results are always computed on all rows while a cache is configured (as if
+ * ATP_OPT_NO_RESTRICT were set) so a cached result is the full sub-metapath
+ * result.  Results are identical with and without a cache. */
+enum { ATP_CACHE_OFF = 0, ATP_CACHE_OTREE = 1, ATP_CACHE_PGDS = 2, ATP_CACHE_LRU = 3, ATP_CACHE_CBS1 = 4,
+       ATP_CACHE_CBS2 = 5 };
+
+/* Set the cache policy and its device-memory budget in bytes; drops every
+ * cached result and resets the Overlap Tree and statistics. */
+atp_status atp_cache_configure(atp_ctx *ctx, int32_t policy, uint64_t budget_bytes);
+
+typedef struct {
+    int64_t queries;          /* queries evaluated since configuration */
+    int64_t whole_hits;       /* queries answered entirely from the cache */
+    int64_t sub_hits;         /* cached sub-chain results used by plans */
+    int64_t insert_attempts;
+    int64_t inserts;
+    int64_t evictions;
+    int64_t items;            /* results currently cached */
+    int64_t bytes;            /* device bytes they hold */
+    int64_t otree_nodes;      /* Overlap Tree nodes (root included) */
+    int64_t otree_leaves;
+} atp_cache_stats;
+atp_status atp_cache_get_stats(const atp_ctx *ctx, atp_cache_stats *stats);
+
+/* --- Overlap Tree and cache policy as standalone host objects (no GPU) ---- */
+
+typedef struct atp_otree atp_otree;
+atp_status atp_otree_create(atp_otree **out);
+atp_status atp_otree_destroy(atp_otree *t);
+/* insert a metapath given as n >= 1 non-negative symbols (and all its suffixes) */
+atp_status atp_otree_insert(atp_otree *t, const int32_t *symbols, int32_t n);
+/* occurrences of symbols[0..n) as a substring of the inserted metapaths */
+atp_status atp_otree_frequency(const atp_otree *t, const int32_t *symbols, int32_t n, int64_t *f);
+/* node count (root included), leaves, sum of inserted lengths (lambda),
+ * internal nodes below the root with fewer than two children, and leaves with f != 1 */
+atp_status atp_otree_shape(const atp_otree *t, int64_t *nodes, int64_t *leaves, int64_t *lambda,
+                           int64_t *thin_internal, int64_t *leaves_f_not_1);
+
+/* Replay n_req requests of items 0..n_items-1 (size, cost; parent[i] is the
+ * item whose Overlap-Tree subtree holds item i, or -1) through a policy
+ * (ATP_CACHE_OTREE / PGDS / LRU) with the given budget.  hit[r] = item was
+ * cached before request r; cached_after[r] = it is cached after it;
+ * final_cached[i] = item i is cached at the end. */
+atp_status atp_cache_simulate(int32_t policy, double budget, int32_t n_items, const double *size,
+                              const double *cost, const int32_t *parent, int32_t n_req, const int32_t *req,
+                              int32_t *hit, int32_t *cached_after, int32_t *final_cached);
+
 /* --- planner (host only; usable without a GPU) ----------------------------- */
 
 /* Dynamic-programming chain order (Sec. 3.1, Eq. 1) for p = n_mats matrices

@@ -25,8 +25,10 @@ EXPORTS = [
     "atp_create", "atp_destroy", "atp_add_node_type", "atp_add_relation", "atp_add_property",
     "atp_eval", "atp_eval_plan", "atp_result_csr", "atp_result_to_host", "atp_result_stats",
     "atp_result_free", "atp_plan_chain", "atp_set_flags", "atp_kernel_times", "atp_kernel_times_reset",
-    "atp_device_bytes", "atp_status_str",
+    "atp_device_bytes", "atp_status_str", "atp_cache_configure", "atp_cache_get_stats", "atp_otree_create",
+    "atp_otree_destroy", "atp_otree_insert", "atp_otree_frequency", "atp_otree_shape", "atp_cache_simulate",
 ]
+ATP_CACHE_OFF, ATP_CACHE_OTREE, ATP_CACHE_PGDS, ATP_CACHE_LRU, ATP_CACHE_CBS1, ATP_CACHE_CBS2 = 0, 1, 2, 3, 4, 5
 
 
 class AtpError(RuntimeError):
@@ -53,6 +55,11 @@ class atp_constraint(ctypes.Structure):
                 ("hi", ctypes.c_int64),
                 ("ids", ctypes.c_void_p),
                 ("n_ids", ctypes.c_int64)]
+
+
+class atp_cache_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("queries", "whole_hits", "sub_hits", "insert_attempts", "inserts",
+                                              "evictions", "items", "bytes", "otree_nodes", "otree_leaves")]
 
 
 class atp_eval_stats(ctypes.Structure):
@@ -96,6 +103,14 @@ def lib() -> ctypes.CDLL:
         "atp_kernel_times_reset": ([vp], None),
         "atp_device_bytes": ([vp], i64),
         "atp_status_str": ([i32], ctypes.c_char_p),
+        "atp_cache_configure": ([vp, i32, ctypes.c_uint64], i32),
+        "atp_cache_get_stats": ([vp, P(atp_cache_stats)], i32),
+        "atp_otree_create": ([P(vp)], i32),
+        "atp_otree_destroy": ([vp], i32),
+        "atp_otree_insert": ([vp, vp, i32], i32),
+        "atp_otree_frequency": ([vp, vp, i32, P(i64)], i32),
+        "atp_otree_shape": ([vp, P(i64), P(i64), P(i64), P(i64), P(i64)], i32),
+        "atp_cache_simulate": ([i32, ctypes.c_double, i32, vp, vp, vp, i32, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -125,6 +140,52 @@ def plan_chain(dims, nnz=None, alpha=12.0, beta=12.0, gamma=12.0, dense=False) -
                               1 if dense else 0, buf, 4096, ctypes.byref(cost))
     _check(st, "atp_plan_chain")
     return buf.value.decode(), cost.value
+
+
+class OverlapTree:
+    """Standalone Overlap Tree (host only)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().atp_otree_create(ctypes.byref(h)), "atp_otree_create")
+        self._h = h
+
+    def insert(self, symbols) -> None:
+        a = np.ascontiguousarray(symbols, dtype=np.int32)
+        _check(lib().atp_otree_insert(self._h, a.ctypes.data, a.shape[0]), "atp_otree_insert")
+
+    def frequency(self, symbols) -> int:
+        a = np.ascontiguousarray(symbols, dtype=np.int32)
+        f = ctypes.c_int64()
+        _check(lib().atp_otree_frequency(self._h, a.ctypes.data if a.size else None, a.shape[0], ctypes.byref(f)),
+               "atp_otree_frequency")
+        return f.value
+
+    def shape(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(5)]
+        _check(lib().atp_otree_shape(self._h, *[ctypes.byref(x) for x in v]), "atp_otree_shape")
+        return dict(zip(("nodes", "leaves", "lambda", "thin_internal", "leaves_f_not_1"), [x.value for x in v]))
+
+    def __del__(self):
+        try:
+            lib().atp_otree_destroy(self._h)
+        except Exception:
+            pass
+
+
+def cache_simulate(policy: int, budget: float, sizes, costs, parents, requests) -> tuple:
+    """Replay requests through a cache policy (host only): (hit, cached_after, final_cached)."""
+    sz = np.ascontiguousarray(sizes, dtype=np.float64)
+    co = np.ascontiguousarray(costs, dtype=np.float64)
+    pa = np.ascontiguousarray(parents, dtype=np.int32)
+    rq = np.ascontiguousarray(requests, dtype=np.int32)
+    hit = np.zeros(len(rq), np.int32)
+    after = np.zeros(len(rq), np.int32)
+    fin = np.zeros(len(sz), np.int32)
+    _check(lib().atp_cache_simulate(policy, float(budget), len(sz), sz.ctypes.data, co.ctypes.data, pa.ctypes.data,
+                                    len(rq), rq.ctypes.data, hit.ctypes.data, after.ctypes.data, fin.ctypes.data),
+           "atp_cache_simulate")
+    return hit.astype(bool), after.astype(bool), fin.astype(bool)
 
 
 def torch_stream_handle(device: int = 0) -> int | None:
@@ -312,3 +373,12 @@ class Context:
 
     def device_bytes(self) -> int:
         return int(lib().atp_device_bytes(self._h))
+
+    # --- workload cache (Overlap Tree + replacement policy) ------------------
+    def cache_configure(self, policy: int, budget_bytes: int) -> None:
+        _check(lib().atp_cache_configure(self._h, int(policy), int(budget_bytes)), "atp_cache_configure")
+
+    def cache_stats(self) -> dict:
+        st = atp_cache_stats()
+        _check(lib().atp_cache_get_stats(self._h, ctypes.byref(st)), "atp_cache_get_stats")
+        return {n: getattr(st, n) for n, _ in atp_cache_stats._fields_}

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libatrapos.so")
-SOURCES = ["kernels.hip", "engine.cpp", "planner.cpp"]
+SOURCES = ["kernels.hip", "engine.cpp", "planner.cpp", "otree.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

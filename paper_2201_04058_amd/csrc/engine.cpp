@@ -16,7 +16,9 @@
 
 #include "../../include/atrapos.h"
 #include "internal.hpp"
+#include "otree.hpp"
 #include "planner.hpp"
+#include <chrono>
 
 using namespace atp;
 
@@ -267,6 +269,29 @@ static Tuning tuning_from_env() {
     return t;
 }
 
+// Device-resident cached results and their bookkeeping (Sec. 3.3-3.4).
+struct CachePayload {
+    Buf rp, col, val, active;
+    int64_t rows = 0, cols = 0, nnz = 0, n_active = -1;
+    double bytes = 0;
+};
+struct CacheItemInfo {
+    int node = -1;                    // Overlap Tree node, -1 if the string is not in the tree
+    std::vector<int32_t> types;       // the sub-metapath
+    std::vector<int32_t> rels;
+    std::vector<std::string> pos;     // constraint key of every position
+};
+struct CacheState {
+    int32_t policy = ATP_CACHE_OFF;
+    uint64_t budget = 0;
+    std::unique_ptr<OverlapTree> tree;
+    std::unique_ptr<CachePolicy> pol;
+    std::map<std::string, int64_t> item_by_key;
+    std::map<int64_t, CacheItemInfo> info;
+    std::map<int64_t, CachePayload> payload;
+    atp_cache_stats stats{};
+};
+
 struct atp_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -278,6 +303,7 @@ struct atp_ctx {
     std::map<std::pair<int, int>, JunctionSketch> sketches;
     std::map<int, ColumnHist> col_hists;
     KernelTimer timer;
+    CacheState cache;
     StepHeader *h_hdr = nullptr;  // pinned
     std::set<atp_result *> results;
     bool broken = false;
@@ -316,6 +342,8 @@ struct Mat {
     Buf rp, col, val;          // owned storage of products
     Buf active;                // ascending non-empty rows (products used as a left operand)
     int64_t n_active = -1;     // -1 = no list
+    const int32_t *active_ptr = nullptr;  // the list (owned above, or a cached result's)
+    bool view = false;                    // a cached result, not owned
     const int32_t *cand = nullptr;  // leaf: candidate rows from an id-set constraint
     int64_t n_cand = 0;
 };
@@ -384,8 +412,8 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     if (X.leaf && X.cand) {
         cand = X.cand;
         n_cand = X.n_cand;
-    } else if (!X.leaf && X.n_active >= 0) {
-        cand = X.active.as<int32_t>();
+    } else if (!X.leaf && X.n_active >= 0 && X.active_ptr) {
+        cand = X.active_ptr;
         n_cand = X.n_active;
     }
     TRY(Z.rp.alloc(pool, sizeof(int64_t) * (Z.rows + 1)));
@@ -397,6 +425,7 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
         if (need_active) {
             TRY(Z.active.alloc(pool, 4));
             Z.n_active = 0;
+            Z.active_ptr = Z.active.as<int32_t>();
         }
         Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
                        Z.rows, Z.cols, 0};
@@ -564,6 +593,7 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     if (need_active) {
         Z.n_active = h2.n_active;
         TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.n_active, 1)));
+        Z.active_ptr = Z.active.as<int32_t>();
         launch_active_scatter(cand, n_cand, flags_scan.as<int64_t>(), Z.active.as<int32_t>(), s, t);
     }
     Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
@@ -644,6 +674,172 @@ const JunctionSketch &sketch_for(atp_ctx *c, int rin, int rout) {
     const Rel &b = *c->rels[rout];
     JunctionSketch js = make_sketch(a.h_indeg.data(), b.h_rp.data(), (int64_t)b.h_rp.size() - 1);
     return c->sketches.emplace(key, std::move(js)).first->second;
+}
+
+// ---- cache keys (Sec. 3.3, "Handling constrained queries") ----------------
+
+uint64_t fnv1a64(const void *data, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *p = (const unsigned char *)data;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// canonical constraint string of every metapath position
+std::vector<std::string> position_keys(int32_t n_types, const atp_constraint *cons, int32_t n_cons) {
+    std::vector<std::vector<std::string>> per(n_types);
+    for (int q = 0; q < n_cons; ++q) {
+        const atp_constraint &k = cons[q];
+        char buf[96];
+        if (k.kind == ATP_C_RANGE) {
+            std::snprintf(buf, sizeof(buf), "R%d:%lld:%lld", k.prop_id, (long long)k.lo, (long long)k.hi);
+        } else {
+            std::vector<int32_t> ids(k.ids, k.ids + k.n_ids);
+            std::sort(ids.begin(), ids.end());
+            ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+            std::snprintf(buf, sizeof(buf), "I%zu:%016llx", ids.size(),
+                          (unsigned long long)fnv1a64(ids.data(), ids.size() * sizeof(int32_t)));
+        }
+        per[k.position].push_back(buf);
+    }
+    std::vector<std::string> out(n_types);
+    for (int i = 0; i < n_types; ++i) {
+        std::sort(per[i].begin(), per[i].end());
+        for (auto &x : per[i]) out[i] += (out[i].empty() ? "" : "&") + x;
+    }
+    return out;
+}
+
+std::string item_key(const std::vector<int32_t> &types, const std::vector<int32_t> &rels,
+                     const std::vector<std::string> &pos) {
+    std::string k = "t";
+    for (int32_t t : types) k += ":" + std::to_string(t);
+    k += "|r";
+    for (int32_t r : rels) k += ":" + std::to_string(r);
+    k += "|c";
+    for (auto &x : pos) k += ";" + x;
+    return k;
+}
+
+// cached items whose sub-metapath extends item q's to the right with the same
+// relations and constraints on q's positions (q's Overlap-Tree subtree)
+std::vector<int64_t> cache_subtree(const CacheState &cs, int64_t q) {
+    std::vector<int64_t> out;
+    auto iq = cs.info.find(q);
+    if (iq == cs.info.end() || !cs.tree) return out;
+    const CacheItemInfo &qi = iq->second;
+    const int node = cs.tree->find(qi.types);
+    if (node < 0) return out;
+    cs.tree->for_subtree(node, [&](int u) {
+        for (const auto &kv : cs.tree->node(u).keys) {
+            const int64_t e = kv.second.item;
+            if (e < 0 || e == q || !cs.payload.count(e)) continue;
+            const CacheItemInfo &ei = cs.info.at(e);
+            bool ok = ei.types.size() > qi.types.size();
+            for (size_t z = 0; ok && z < qi.rels.size(); ++z) ok = ei.rels[z] == qi.rels[z];
+            for (size_t z = 0; ok && z < qi.pos.size(); ++z) ok = ei.pos[z] == qi.pos[z];
+            if (ok) out.push_back(e);
+        }
+    });
+    return out;
+}
+
+// A product computed by the current query: leaves lo..hi, cumulative cost (s).
+struct KeptMat {
+    int lo, hi;
+    double cost;
+    Mat m;
+};
+
+// Cache insertion after a query (Sec. 3.4.1): record the hits on cached
+// sub-results, then try to insert the policy's candidates -- the whole query
+// and, for the Overlap-Tree policies, the longest computed sub-metapath whose
+// string is an overlap (an internal Overlap-Tree node); CBS1 only the whole
+// query; CBS2 every computed product.  Replacement follows the policy.
+atp_status cache_insert(atp_ctx *c, const Mat &R, double root_cost, std::vector<KeptMat> &kept,
+                        const std::vector<int64_t> &used, const int32_t *types, const std::vector<int> &rel,
+                        const std::vector<std::string> &pkeys, int p) {
+    CacheState &cs = c->cache;
+    hipStream_t s = c->stream;
+    for (int64_t id : used) {
+        std::vector<int64_t> ev;
+        cs.pol->request(id, ev);
+        cs.stats.sub_hits += 1;
+    }
+    struct Cand {
+        int lo, hi;
+        double cost;
+        Mat *m;
+        bool root;
+    };
+    std::vector<Cand> cands;
+    cands.push_back(Cand{0, p - 1, root_cost, const_cast<Mat *>(&R), true});
+    if (cs.policy == ATP_CACHE_CBS2) {
+        for (auto &k : kept) cands.push_back(Cand{k.lo, k.hi, k.cost, &k.m, false});
+    } else if (cs.policy != ATP_CACHE_CBS1) {
+        KeptMat *best = nullptr;
+        for (auto &k : kept) {
+            const int node = cs.tree->find(std::vector<int32_t>(types + k.lo, types + k.hi + 2));
+            if (node < 0 || cs.tree->node(node).leaf()) continue;
+            if (!best || (k.hi - k.lo) > (best->hi - best->lo)) best = &k;
+        }
+        if (best) cands.push_back(Cand{best->lo, best->hi, best->cost, &best->m, false});
+    }
+    for (const Cand &cd : cands) {
+        const std::vector<int32_t> ty(types + cd.lo, types + cd.hi + 2);
+        const std::vector<int32_t> rl(rel.begin() + cd.lo, rel.begin() + cd.hi + 1);
+        const std::vector<std::string> ps(pkeys.begin() + cd.lo, pkeys.begin() + cd.hi + 2);
+        const std::string key = item_key(ty, rl, ps);
+        const Mat &m = *cd.m;
+        int64_t id;
+        auto it = cs.item_by_key.find(key);
+        if (it != cs.item_by_key.end()) {
+            id = it->second;
+            if (cs.payload.count(id)) continue;  // already cached
+        } else {
+            const double bytes = 8.0 * (m.rows + 1) + 12.0 * m.nnz + (m.n_active >= 0 ? 4.0 * m.n_active : 0.0);
+            id = cs.pol->add_item(bytes, std::max(cd.cost, 1e-9));
+            const int node = cs.tree->find(ty);
+            cs.info[id] = CacheItemInfo{node, ty, rl, ps};
+            cs.item_by_key[key] = id;
+            if (node >= 0) cs.tree->node(node).keys[key].item = id;
+        }
+        cs.stats.insert_attempts += 1;
+        std::vector<int64_t> ev;
+        const bool ok = cs.pol->request(id, ev);
+        for (int64_t e : ev) {
+            cs.payload.erase(e);
+            cs.stats.evictions += 1;
+        }
+        if (!ok) continue;
+        CachePayload P;
+        P.rows = m.rows;
+        P.cols = m.cols;
+        P.nnz = m.nnz;
+        P.bytes = cs.pol->item(id).size;
+        if (cd.root) {  // the caller keeps R: copy it
+            TRY(P.rp.alloc(&c->pool, 8 * (size_t)(m.rows + 1)));
+            TRY(P.col.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(m.nnz, 1)));
+            TRY(P.val.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(m.nnz, 1)));
+            HIPTRY(hipMemcpyAsync(P.rp.p, m.rp.p, 8 * (m.rows + 1), hipMemcpyDeviceToDevice, s));
+            if (m.nnz) {
+                HIPTRY(hipMemcpyAsync(P.col.p, m.col.p, 4 * m.nnz, hipMemcpyDeviceToDevice, s));
+                HIPTRY(hipMemcpyAsync(P.val.p, m.val.p, 8 * m.nnz, hipMemcpyDeviceToDevice, s));
+            }
+            P.n_active = -1;
+        } else {
+            P.rp = std::move(cd.m->rp);
+            P.col = std::move(cd.m->col);
+            P.val = std::move(cd.m->val);
+            P.n_active = cd.m->n_active;
+            if (cd.m->n_active >= 0) P.active = std::move(cd.m->active);
+        }
+        cs.payload[id] = std::move(P);
+        cs.stats.inserts += 1;
+    }
+    return ATP_OK;
 }
 
 atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
@@ -753,9 +949,49 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         cs.cols = (double)r.nonempty_cols * sc;
         lst[i] = cs;
     }
+    // ---- workload cache: Overlap Tree update and cached sub-chains ----
+    CacheState &cs = c->cache;
+    const bool caching = cs.policy != ATP_CACHE_OFF && p >= 2;
+    std::vector<std::string> pkeys;
+    std::vector<std::vector<int64_t>> cached_item(p, std::vector<int64_t>(p, -1));
+    std::vector<ChainStats> cached_stats_store(p * p);
+    std::vector<std::vector<const ChainStats *>> cached_stats(p, std::vector<const ChainStats *>(p, nullptr));
+    auto sub_types = [&](int a, int b) { return std::vector<int32_t>(types + a, types + b + 2); };
+    auto sub_rels = [&](int a, int b) { return std::vector<int32_t>(rel.begin() + a, rel.begin() + b + 1); };
+    auto sub_pos = [&](int a, int b) { return std::vector<std::string>(pkeys.begin() + a, pkeys.begin() + b + 2); };
+    if (caching) {
+        pkeys = position_keys(n_types, cons, n_cons);
+        cs.tree->insert(std::vector<int32_t>(types, types + n_types));
+        cs.stats.queries += 1;
+        for (int a = 0; a < p; ++a)
+            for (int b = a; b < p; ++b) {
+                const std::vector<int32_t> st_ = sub_types(a, b);
+                const std::string key = item_key(st_, sub_rels(a, b), sub_pos(a, b));
+                const int node = cs.tree->find(st_);
+                if (node >= 0) cs.tree->node(node).keys[key].f += 1;
+                auto it = cs.item_by_key.find(key);
+                if (it == cs.item_by_key.end()) continue;
+                if (node >= 0) cs.tree->node(node).keys[key].item = it->second;
+                cs.info[it->second].node = node;
+                auto pl = cs.payload.find(it->second);
+                if (pl == cs.payload.end() || b == a) continue;
+                cached_item[a][b] = it->second;
+                ChainStats &z = cached_stats_store[a * p + b];
+                const CachePayload &P = pl->second;
+                z.dim_r = (double)P.rows;
+                z.dim_c = (double)P.cols;
+                z.nnz = (double)P.nnz;
+                z.rows = P.n_active >= 0 ? (double)P.n_active : std::min((double)P.rows, (double)P.nnz);
+                z.cols = std::min((double)P.cols, (double)P.nnz);
+                cached_stats[a][b] = &z;
+            }
+    }
+
     std::string plan_str;
     if (plan) {
         plan_str = plan;
+        for (const PlanTree &nd : forced)
+            if (nd.block_lo >= 0 && (!caching || cached_item[nd.block_lo][nd.block_hi] < 0)) return ATP_EINVAL;
     } else {
         std::vector<JunctionSketch> js;
         std::vector<double> jsel, csel;
@@ -775,7 +1011,8 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
             csel.push_back(sel_of(k + 1));
         }
         CostCoeffs cc;
-        PlanResult pr = plan_chain(lst, js, jsel, ch, csel, uniform ? Estimator::Uniform : Estimator::Sketch, cc);
+        PlanResult pr = plan_chain(lst, js, jsel, ch, csel, uniform ? Estimator::Uniform : Estimator::Sketch, cc,
+                                   caching ? &cached_stats : nullptr);
         plan_str = pr.plan;
         if (!parse_plan(plan_str.c_str(), p, forced, forced_root)) return ATP_ESTATE;
     }
@@ -806,7 +1043,7 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     bool overflow = false;
     std::vector<PlanTree> &tree = forced;
     std::vector<Buf> keep;  // restriction buffers, alive until the query ends
-    const bool restrict_rows = (c->flags & ATP_OPT_NO_RESTRICT) == 0;
+    const bool restrict_rows = (c->flags & ATP_OPT_NO_RESTRICT) == 0 && c->cache.policy == ATP_CACHE_OFF;
     // Rows of a right sub-chain that can matter: the columns its left neighbour uses.
     struct Restriction {
         const uint32_t *bits = nullptr;
@@ -844,10 +1081,31 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         keep.push_back(std::move(scan));  // the scatter may still be reading it
         return ATP_OK;
     };
-    // post-order evaluation of node v into outm; rs restricts v's rows
-    std::function<atp_status(int, bool, const Restriction *, Mat &, int &, int &)> run =
-        [&](int v, bool as_left, const Restriction *rs, Mat &outm, int &lo, int &hi) -> atp_status {
+    std::vector<KeptMat> kept;  // products kept for the cache's insertion policy
+    std::vector<int64_t> used_items;
+    // post-order evaluation of node v into outm; rs restricts v's rows; cost =
+    // seconds to compute it from the base relations in this query
+    std::function<atp_status(int, bool, const Restriction *, Mat &, int &, int &, double &)> run =
+        [&](int v, bool as_left, const Restriction *rs, Mat &outm, int &lo, int &hi, double &cost) -> atp_status {
         const PlanTree &nd = tree[v];
+        cost = 0;
+        if (nd.block_lo >= 0) {  // a cached result (caching implies no row restriction)
+            lo = nd.block_lo;
+            hi = nd.block_hi;
+            const int64_t id = cached_item[lo][hi];
+            const CachePayload &P = cs.payload.at(id);
+            outm = Mat();
+            outm.view = true;
+            outm.rows = P.rows;
+            outm.cols = P.cols;
+            outm.nnz = P.nnz;
+            outm.n_active = P.n_active;
+            outm.active_ptr = P.n_active >= 0 ? P.active.as<int32_t>() : nullptr;
+            outm.op = Operand{P.rp.as<int64_t>(), P.col.as<int32_t>(), P.val.as<uint64_t>(), nullptr, nullptr,
+                              P.rows, P.cols, P.nnz};
+            used_items.push_back(id);
+            return ATP_OK;
+        }
         if (nd.leaf >= 0) {
             lo = hi = nd.leaf;
             outm = Mat();
@@ -872,7 +1130,8 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         }
         Mat X, Y;
         int l0, l1, r0, r1;
-        TRY(run(nd.left, true, rs, X, l0, l1));
+        double cx = 0, cy = 0;
+        TRY(run(nd.left, true, rs, X, l0, l1, cx));
         Restriction r2;
         const Restriction *rp = nullptr;
         const int64_t y_rows = c->types[types[l1 + 1]].count;
@@ -881,17 +1140,23 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
             TRY(make_restriction(X, y_rows, r2));
             rp = &r2;
         }
-        TRY(run(nd.right, false, rp, Y, r0, r1));
+        TRY(run(nd.right, false, rp, Y, r0, r1, cy));
         lo = l0;
         hi = r1;
         const int last_pos = r1 + 1;  // metapath position of Y's last type
         const int64_t ycols_eff = masks[last_pos].pop >= 0 ? masks[last_pos].pop : Y.cols;
         bool sat = false;
         if (c->step_names) c->timer.suffix = "#" + std::to_string(n_products);
+        const auto t_0 = std::chrono::steady_clock::now();
         TRY(spgemm(c, X, Y, ycols_eff, as_left, outm, st, sat));
+        cost = cx + cy + std::chrono::duration<double>(std::chrono::steady_clock::now() - t_0).count();
         c->timer.suffix.clear();
         ++n_products;
         if (v == forced_root && sat) overflow = true;
+        if (caching) {  // keep computed operands for the insertion policy
+            if (!X.leaf && !X.view) kept.push_back(KeptMat{l0, l1, cx, std::move(X)});
+            if (!Y.leaf && !Y.view) kept.push_back(KeptMat{r0, r1, cy, std::move(Y)});
+        }
         return ATP_OK;
     };
     Mat R;
@@ -913,8 +1178,30 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         stt = spgemm(c, X, ident, ycols_eff, false, R, st, sat);
         n_products = 1;
         overflow = sat;
+    } else if (caching && tree[forced_root].block_lo == 0 && tree[forced_root].block_hi == p - 1) {
+        // the whole query is cached: hand out a copy
+        const int64_t id = cached_item[0][p - 1];
+        const CachePayload &P = cs.payload.at(id);
+        R.rows = P.rows;
+        R.cols = P.cols;
+        R.nnz = P.nnz;
+        stt = ATP_OK;
+        if ((stt = R.rp.alloc(&c->pool, 8 * (size_t)(P.rows + 1))) == ATP_OK &&
+            (stt = R.col.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK &&
+            (stt = R.val.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK) {
+            if (hipMemcpyAsync(R.rp.p, P.rp.p, 8 * (P.rows + 1), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                (P.nnz && hipMemcpyAsync(R.col.p, P.col.p, 4 * P.nnz, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+                (P.nnz && hipMemcpyAsync(R.val.p, P.val.p, 8 * P.nnz, hipMemcpyDeviceToDevice, s) != hipSuccess))
+                stt = ATP_EDEVICE;
+        }
+        std::vector<int64_t> ev;
+        cs.pol->request(id, ev);
+        cs.stats.whole_hits += 1;
     } else {
-        stt = run(forced_root, false, nullptr, R, lo, hi);
+        double root_cost = 0;
+        stt = run(forced_root, false, nullptr, R, lo, hi, root_cost);
+        if (stt == ATP_OK && caching && !overflow) stt = cache_insert(c, R, root_cost, kept, used_items, types,
+                                                                    rel, pkeys, p);
     }
     if (stt != ATP_OK) {
         if (stt == ATP_EDEVICE) c->broken = true;
@@ -1000,6 +1287,7 @@ atp_status atp_destroy(atp_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (atp_result *r : c->results) delete r;
     c->results.clear();
+    c->cache.payload.clear();
     c->rels.clear();
     c->props.clear();
     c->timer.flush();
@@ -1237,5 +1525,38 @@ void atp_kernel_times_reset(atp_ctx *c) {
 }
 
 int64_t atp_device_bytes(const atp_ctx *c) { return c ? c->pool.held : 0; }
+
+atp_status atp_cache_configure(atp_ctx *c, int32_t policy, uint64_t budget_bytes) {
+    if (!c || policy < ATP_CACHE_OFF || policy > ATP_CACHE_CBS2) return ATP_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    CacheState &cs = c->cache;
+    cs.payload.clear();
+    cs.info.clear();
+    cs.item_by_key.clear();
+    cs.stats = atp_cache_stats{};
+    cs.policy = policy;
+    cs.budget = budget_bytes;
+    cs.tree.reset(policy == ATP_CACHE_OFF ? nullptr : new OverlapTree());
+    cs.pol.reset();
+    if (policy != ATP_CACHE_OFF) {
+        const Policy pol = policy == ATP_CACHE_OTREE ? Policy::Otree : policy == ATP_CACHE_PGDS ? Policy::Pgds
+                                                                                                 : Policy::Lru;
+        cs.pol.reset(new CachePolicy(pol, (double)budget_bytes));
+        CacheState *csp = &cs;
+        cs.pol->set_subtree_fn([csp](int64_t id) { return cache_subtree(*csp, id); });
+    }
+    return ATP_OK;
+}
+
+atp_status atp_cache_get_stats(const atp_ctx *c, atp_cache_stats *st) {
+    if (!c || !st) return ATP_EINVAL;
+    const CacheState &cs = c->cache;
+    *st = cs.stats;
+    st->items = cs.pol ? cs.pol->cached_count() : 0;
+    st->bytes = cs.pol ? (int64_t)cs.pol->used() : 0;
+    st->otree_nodes = cs.tree ? cs.tree->size() : 0;
+    st->otree_leaves = cs.tree ? cs.tree->leaves() : 0;
+    return ATP_OK;
+}
 
 }  // extern "C"

@@ -111,7 +111,8 @@ ChainStats estimate_product(const ChainStats &x, const ChainStats &y, const Junc
 
 PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<JunctionSketch> &junctions,
                       const std::vector<double> &junction_sel, const std::vector<ColumnHist> &col_hists,
-                      const std::vector<double> &col_sel, Estimator est, const CostCoeffs &cc) {
+                      const std::vector<double> &col_sel, Estimator est, const CostCoeffs &cc,
+                      const std::vector<std::vector<const ChainStats *>> *cached) {
     const int p = (int)leaves.size();
     PlanResult out;
     if (p == 0) return out;
@@ -122,6 +123,12 @@ PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<J
     for (int len = 2; len <= p; ++len) {
         for (int i = 0; i + len - 1 < p; ++i) {
             const int j = i + len - 1;
+            if (cached && (*cached)[i][j]) {  // retrieved, not computed
+                C[i][j] = 0;
+                S[i][j] = -2;
+                D[i][j] = *(*cached)[i][j];
+                continue;
+            }
             double best = std::numeric_limits<double>::infinity();
             for (int k = i; k < j; ++k) {
                 const JunctionSketch *js = k < (int)junctions.size() ? &junctions[k] : nullptr;
@@ -147,6 +154,10 @@ PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<J
             return std::to_string(i);
         }
         const int k = S[i][j];
+        if (k == -2) {
+            out.node_stats.push_back(D[i][j]);
+            return "[" + std::to_string(i) + "-" + std::to_string(j) + "]";
+        }
         std::string l = str(i, k), r = str(k + 1, j);
         out.node_stats.push_back(D[i][j]);
         return "(" + l + "," + r + ")";
@@ -198,6 +209,22 @@ struct Parser {
     void ws() {
         while (s[pos] == ' ' || s[pos] == '\t' || s[pos] == '\n') ++pos;
     }
+    long read_num() {
+        if (!(s[pos] >= '0' && s[pos] <= '9')) {
+            ok = false;
+            return -1;
+        }
+        long v = 0;
+        while (s[pos] >= '0' && s[pos] <= '9') {
+            v = v * 10 + (s[pos] - '0');
+            if (v > 1000000) {
+                ok = false;
+                return -1;
+            }
+            ++pos;
+        }
+        return v;
+    }
     int node() {
         ws();
         if (s[pos] == '(') {
@@ -219,6 +246,27 @@ struct Parser {
             PlanTree t;
             t.left = l;
             t.right = r;
+            nodes.push_back(t);
+            return (int)nodes.size() - 1;
+        }
+        if (s[pos] == '[') {
+            ++pos;
+            long lo = read_num(), hi;
+            if (!ok || s[pos] != '-') {
+                ok = false;
+                return -1;
+            }
+            ++pos;
+            hi = read_num();
+            if (!ok || s[pos] != ']' || lo != next_leaf || hi < lo || hi >= p) {
+                ok = false;
+                return -1;
+            }
+            ++pos;
+            next_leaf = (int)hi + 1;
+            PlanTree t;
+            t.block_lo = (int)lo;
+            t.block_hi = (int)hi;
             nodes.push_back(t);
             return (int)nodes.size() - 1;
         }

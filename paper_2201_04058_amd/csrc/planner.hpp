@@ -56,9 +56,13 @@ struct PlanResult {
 // junction_sel[k] the fraction of its nodes kept by that position's mask.
 // col_hists[i] / col_sel[i] describe the columns of leaf i (used by Sketch to
 // estimate how many distinct cells the products of a product hit).
+// cached[i][j] (optional, p x p): the product of leaves i..j is available at
+// no cost with the given shape (Sec. 3.2: a cached result costs only its
+// retrieval); such a block appears in the plan string as "[i-j]".
 PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<JunctionSketch> &junctions,
                       const std::vector<double> &junction_sel, const std::vector<ColumnHist> &col_hists,
-                      const std::vector<double> &col_sel, Estimator est, const CostCoeffs &cc);
+                      const std::vector<double> &col_sel, Estimator est, const CostCoeffs &cc,
+                      const std::vector<std::vector<const ChainStats *>> *cached = nullptr);
 
 // Product estimate for X * Y meeting at a junction; ycols describes the
 // columns of Y's last relation (exposed for tests).
@@ -77,6 +81,7 @@ JunctionSketch make_sketch(const int32_t *in_deg, const int64_t *out_row_ptr, in
 struct PlanTree {
     int leaf = -1;
     int left = -1, right = -1;  // node indices
+    int block_lo = -1, block_hi = -1;  // a cached block of leaves (plan token "[lo-hi]")
 };
 bool parse_plan(const char *s, int p, std::vector<PlanTree> &nodes, int &root);
 

@@ -1,0 +1,77 @@
+"""Seeded metapath query workloads.
+
+Sessions as in the paper's workloads (Sec. 4.1, "Query Workloads"): a data
+scientist explores one entity of interest, fixed by an equality constraint
+(here: an id-set of one node at the first position), with consecutive
+metapath queries; at each step a new session (new entity and metapath) starts
+with restart probability p, otherwise the session continues with the same
+entity and a different metapath.  Metapaths are schema walks of 3..5 node
+types starting at the entity's type; the queries are shuffled at the end.
+Selections are uniform (default) or Zipf.  Type-level property predicates
+(e.g. P.year >= 2015) can be added at every position of their type.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .hin import HIN, Constraint, Query
+
+
+def schema_walks(hin: HIN, start: str, lengths=(3, 4, 5)) -> list:
+    """Every walk on the relation schema of the given lengths from `start`."""
+    out = {}
+    for (s, d) in hin.relations:
+        out.setdefault(s, []).append(d)
+    walks = []
+
+    def rec(path):
+        if len(path) in lengths:
+            walks.append(list(path))
+        if len(path) >= max(lengths):
+            return
+        for nb in sorted(out.get(path[-1], [])):
+            rec(path + [nb])
+
+    rec([start])
+    return walks
+
+
+def sessions(hin: HIN, seed: int, n_queries: int, start_type: str, restart_p: float = 0.08,
+             lengths=(3, 4, 5), zipf: float = 0.0, entities: int = 200, type_predicates=None) -> list:
+    """The shuffled query list of a session workload.
+
+    ``type_predicates`` maps a node type to (prop, lo, hi): a range constraint
+    added at every position of that type.  Entities are drawn from the
+    `entities` highest-degree-independent random nodes of ``start_type``.
+    """
+    rng = np.random.default_rng(seed)
+    walks = schema_walks(hin, start_type, lengths)
+    n0 = hin.counts[start_type]
+    pool = rng.choice(n0, size=min(entities, n0), replace=False)
+
+    def pick(n):
+        if zipf > 0:
+            w = np.arange(1, n + 1, dtype=np.float64) ** (-zipf)
+            return int(rng.choice(n, p=w / w.sum()))
+        return int(rng.integers(n))
+
+    qs = []
+    entity = int(pool[pick(len(pool))])
+    last = -1
+    for z in range(n_queries):
+        if z > 0 and rng.random() < restart_p:
+            entity = int(pool[pick(len(pool))])
+            last = -1
+        wi = pick(len(walks))
+        if wi == last and len(walks) > 1:
+            wi = (wi + 1) % len(walks)
+        last = wi
+        types = walks[wi]
+        cons = [Constraint(0, "idset", ids=np.array([entity], dtype=np.int32))]
+        for i, t in enumerate(types):
+            if type_predicates and t in type_predicates:
+                prop, lo, hi = type_predicates[t]
+                cons.append(Constraint(i, "range", prop=prop, lo=lo, hi=hi))
+        qs.append(Query("-".join(types), types, cons))
+    order = rng.permutation(len(qs))
+    return [qs[i] for i in order]
