@@ -71,6 +71,57 @@ def cpu_baseline(hin, queries, rows_per_query: int, threads: int) -> dict:
                       f"(of {len(ids)}), scaled by |start set| / sample"}
 
 
+def workload_mode(args) -> int:
+    """A session workload (Sec. 4.1 "Query Workloads": sessions on one entity,
+    restart probability 0.08, metapaths of 3-5 types, shuffled) on the full
+    network, evaluated with every cache policy and without a cache."""
+    import paper_2201_04058_amd as atp
+    from synth import configs, workload
+
+    hin, _ = configs.load(args.workload)
+    starts = {"scholarly": ["A", "V", "T"], "news": ["R", "O", "L"], "tiny": ["A", "T"]}[args.workload]
+    preds = {"scholarly": {"P": ("year", 2015, 32767)}, "news": {}, "tiny": {}}[args.workload]
+    qs = workload.sessions(hin, 4, args.queries, starts, restart_p=0.08, entities=100, type_predicates=preds)
+    stream = None
+    try:
+        import torch
+        torch.cuda.init()
+        stream = atp.torch_stream_handle(0)
+    except Exception:
+        pass
+    ctx = atp.Context(device=0, stream=stream)
+    ctx.load_hin(hin)
+    for q in qs[:20]:  # warm the pool and the planner's statistics
+        ctx.eval_query(q).free()
+    budget = int(args.cache_gb * (1 << 30))
+    rows = {}
+    for name in ["OFF", "OTREE", "PGDS", "LRU", "CBS1", "CBS2"]:
+        ctx.cache_configure(getattr(atp, "ATP_CACHE_" + name), budget if name != "OFF" else 0)
+        lat = []
+        t0 = time.perf_counter()
+        for q in qs:
+            tq = time.perf_counter()
+            ctx.eval_query(q).free()
+            lat.append(time.perf_counter() - tq)
+        el = time.perf_counter() - t0
+        lat = np.array(lat) * 1e3
+        st = ctx.cache_stats()
+        rows[name] = {"qps": round(len(qs) / el, 2), "mean_ms": round(float(lat.mean()), 3),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                      "whole_hits": st["whole_hits"], "sub_hits": st["sub_hits"], "inserts": st["inserts"],
+                      "evictions": st["evictions"], "cached_gb": round(st["bytes"] / 2**30, 3)}
+        log(f"{name}: {rows[name]}")
+    ctx.close()
+    out = {"metric": "metapath queries/s (session workload)", "value": rows["OTREE"]["qps"], "unit": "queries/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": args.workload + "-sessions", "queries": len(qs), "restart_p": 0.08,
+                      "cache_gb": args.cache_gb, "start_types": starts},
+           "vs_plain_path": round(rows["OTREE"]["qps"] / rows["OFF"]["qps"], 3), "policies": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +131,11 @@ def main() -> int:
     ap.add_argument("--cpu-rows", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan-eac", action="store_true", help="paper's uniform E_ac planner")
+    ap.add_argument("--mode", default="plain", choices=["plain", "workload"],
+                    help="plain: the workload's queries, one at a time; workload: a session query stream "
+                         "evaluated with each cache policy (Sec. 3.3-3.4) against the plain path")
+    ap.add_argument("--queries", type=int, default=500, help="workload mode: queries in the stream")
+    ap.add_argument("--cache-gb", type=float, default=4.0, help="workload mode: cache budget")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -102,6 +158,9 @@ def main() -> int:
 
     import paper_2201_04058_amd as atp
     from synth import configs
+
+    if args.mode == "workload":
+        return workload_mode(args)
 
     t0 = time.perf_counter()
     hin, queries = configs.load(args.workload)

@@ -36,18 +36,19 @@ def schema_walks(hin: HIN, start: str, lengths=(3, 4, 5)) -> list:
     return walks
 
 
-def sessions(hin: HIN, seed: int, n_queries: int, start_type: str, restart_p: float = 0.08,
+def sessions(hin: HIN, seed: int, n_queries: int, start_type, restart_p: float = 0.08,
              lengths=(3, 4, 5), zipf: float = 0.0, entities: int = 200, type_predicates=None) -> list:
     """The shuffled query list of a session workload.
 
-    ``type_predicates`` maps a node type to (prop, lo, hi): a range constraint
-    added at every position of that type.  Entities are drawn from the
-    `entities` highest-degree-independent random nodes of ``start_type``.
+    ``start_type`` is a node type or a list of them (each session picks one
+    uniformly).  ``type_predicates`` maps a node type to (prop, lo, hi): a
+    range constraint added at every position of that type.  Entities are drawn
+    from a seeded pool of ``entities`` random nodes per start type.
     """
     rng = np.random.default_rng(seed)
-    walks = schema_walks(hin, start_type, lengths)
-    n0 = hin.counts[start_type]
-    pool = rng.choice(n0, size=min(entities, n0), replace=False)
+    starts = [start_type] if isinstance(start_type, str) else list(start_type)
+    walks = {t: schema_walks(hin, t, lengths) for t in starts}
+    pools = {t: rng.choice(hin.counts[t], size=min(entities, hin.counts[t]), replace=False) for t in starts}
 
     def pick(n):
         if zipf > 0:
@@ -55,18 +56,23 @@ def sessions(hin: HIN, seed: int, n_queries: int, start_type: str, restart_p: fl
             return int(rng.choice(n, p=w / w.sum()))
         return int(rng.integers(n))
 
+    def new_session():
+        t = starts[int(rng.integers(len(starts)))]
+        return t, int(pools[t][pick(len(pools[t]))])
+
     qs = []
-    entity = int(pool[pick(len(pool))])
+    stype, entity = new_session()
     last = -1
     for z in range(n_queries):
         if z > 0 and rng.random() < restart_p:
-            entity = int(pool[pick(len(pool))])
+            stype, entity = new_session()
             last = -1
-        wi = pick(len(walks))
-        if wi == last and len(walks) > 1:
-            wi = (wi + 1) % len(walks)
+        ws = walks[stype]
+        wi = pick(len(ws))
+        if wi == last and len(ws) > 1:
+            wi = (wi + 1) % len(ws)
         last = wi
-        types = walks[wi]
+        types = ws[wi]
         cons = [Constraint(0, "idset", ids=np.array([entity], dtype=np.int32))]
         for i, t in enumerate(types):
             if type_predicates and t in type_predicates:
