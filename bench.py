@@ -14,6 +14,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,11 +30,27 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
+# Source regions a kernel's counters depend on: the shared device helpers at
+# the top of kernels.hip, the kernel's own section, and internal.hpp.
+KERNEL_SECTIONS = {"dense": ("// numeric: dense LDS tiles over column ranges", "// numeric: tile buckets")}
+
+
+def kernel_source_digest(kernel: str = "dense") -> str:
+    csrc = os.path.join(ROOT, "paper_2201_04058_amd", "csrc")
+    with open(os.path.join(csrc, "kernels.hip")) as fh:
+        text = fh.read()
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2201_04058_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    if kernel in KERNEL_SECTIONS:
+        a, b = KERNEL_SECTIONS[kernel]
+        h.update(text[:text.index("// fills, scans")].encode())
+        h.update(text[text.index(a):text.index(b)].encode())
+    else:
+        h.update(text.encode())
+    with open(os.path.join(csrc, "internal.hpp")) as fh:
+        hdr = fh.read()
+    # constants, enums and argument structs (not the launcher declarations)
+    for block in re.findall(r"^(?:constexpr .*?;|enum .*?^};|struct \w+ \{.*?^};)", hdr, re.S | re.M):
+        h.update(block.encode())
     return h.hexdigest()[:16]
 
 
@@ -45,7 +62,7 @@ def traffic_for(kernel: str, workload: str, launches_per_step: float) -> float |
         return None
     with open(p) as f:
         t = json.load(f)
-    if t.get("kernel_source") != kernel_source_digest():
+    if t.get("kernel_source") != kernel_source_digest(kernel):
         return None
     return t.get("bytes_per_launch")
 

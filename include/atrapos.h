@@ -208,6 +208,79 @@ typedef struct {
 } atp_cache_stats;
 atp_status atp_cache_get_stats(const atp_ctx *ctx, atp_cache_stats *stats);
 
+/* --- batches and serving (Problem 2, MQWE: a workload of metapath queries) --
+ *
+ * Both forms leave the arithmetic unchanged: every query's result is
+ * bit-identical to its own atp_eval.  Queries are executed on lanes: a lane
+ * is a HIP stream with its own memory pool, driven by its own host thread, so
+ * the kernels of queries on different lanes overlap on the device.  The
+ * context's cache (if configured) is shared by all lanes.
+ *
+ * Fusion: queries whose metapath, relations and constraints are the same
+ * except for a single id-set constraint on the first position are evaluated
+ * as ONE chain over the union of their start sets (every SpGEMM launch of the
+ * chain serves all of them: R[u,:] depends only on u and the rest of the
+ * chain, Def. 2-3); each query's rows are then copied out on the device.  A
+ * fused chain that fails (int64 overflow in another member's rows, memory)
+ * is retried one query at a time, so each query gets its own status.
+ *
+ * Memory admission: while lanes run, the slot arrays of each multiplication
+ * (12 bytes per unit of the symbolic per-row upper bound, Sec. 3.2's N_op
+ * bounded by the output width) are reserved against mem_budget_bytes before
+ * they are allocated; a lane whose reservation does not fit waits until
+ * other lanes release theirs (a reservation that exceeds the budget alone
+ * proceeds when no other is held). */
+typedef struct {
+    const int32_t *types;              /* n_types node-type ids (a metapath, Def. 2) */
+    int32_t n_types;
+    const int32_t *rel_ids;            /* n_types-1 relation ids, or NULL (as in atp_eval) */
+    const atp_constraint *cons;        /* as in atp_eval */
+    int32_t n_cons;
+} atp_query;
+
+/* Evaluate n queries on `lanes` lanes (1..16) with at most max_batch queries
+ * per fused chain (1 disables fusion).  out[i] / status[i] receive query i's
+ * result handle (NULL on error) and status.  Returns ATP_OK when every query
+ * was attempted (see status[]), ATP_EINVAL for bad arguments, ATP_ESTATE while
+ * a server runs on the context.  The input arrays are read during the call. */
+atp_status atp_eval_batch(atp_ctx *ctx, const atp_query *queries, int32_t n, int32_t lanes, int32_t max_batch,
+                          uint64_t mem_budget_bytes, atp_result **out, atp_status *status);
+
+/* Serving loop: a request queue drained by `lanes` worker lanes.  A free lane
+ * takes the oldest queued request together with up to max_batch-1 queued
+ * requests it can fuse with (continuous batching: requests that arrive while
+ * others run join the next batch).  atp_submit copies the query and returns
+ * at once; atp_poll hands out finished requests in completion order. */
+typedef struct {
+    int32_t lanes;                     /* 1..16 */
+    int32_t max_batch;                 /* >= 1 */
+    uint64_t mem_budget_bytes;         /* slot-array admission budget, 0 = none */
+} atp_server_options;
+
+typedef struct {
+    uint64_t tag;                      /* the caller's tag from atp_submit */
+    atp_status status;
+    atp_result *result;                /* owned by the caller (atp_result_free); NULL on error */
+    double t_submit, t_start, t_done;  /* seconds on a monotonic clock since atp_server_start */
+    int32_t batch_size;                /* queries in the fused chain that served it */
+    int32_t lane;
+} atp_completion;
+
+/* ATP_ESTATE if a server already runs on the context. */
+atp_status atp_server_start(atp_ctx *ctx, const atp_server_options *opts);
+/* Copy the query into the queue.  ATP_EINVAL for malformed arguments (checked
+ * as atp_eval does), ATP_ESTATE if no server runs. */
+atp_status atp_submit(atp_ctx *ctx, const atp_query *query, uint64_t tag);
+/* Move up to max finished requests into out, waiting up to wait_ms
+ * milliseconds for the first one (0 = do not wait).  Returns how many were
+ * written, or a negative status. */
+int32_t atp_poll(atp_ctx *ctx, atp_completion *out, int32_t max, int32_t wait_ms);
+/* Requests queued or running (not yet polled-ready). */
+int32_t atp_server_pending(atp_ctx *ctx);
+/* Finish every queued request, stop the workers; completions not yet polled
+ * are freed.  ATP_ESTATE if no server runs. */
+atp_status atp_server_stop(atp_ctx *ctx);
+
 /* --- Overlap Tree and cache policy as standalone host objects (no GPU) ---- */
 
 typedef struct atp_otree atp_otree;

@@ -27,6 +27,7 @@ EXPORTS = [
     "atp_result_free", "atp_plan_chain", "atp_set_flags", "atp_kernel_times", "atp_kernel_times_reset",
     "atp_device_bytes", "atp_status_str", "atp_cache_configure", "atp_cache_get_stats", "atp_otree_create",
     "atp_otree_destroy", "atp_otree_insert", "atp_otree_frequency", "atp_otree_shape", "atp_cache_simulate",
+    "atp_eval_batch", "atp_server_start", "atp_submit", "atp_poll", "atp_server_pending", "atp_server_stop",
 ]
 ATP_CACHE_OFF, ATP_CACHE_OTREE, ATP_CACHE_PGDS, ATP_CACHE_LRU, ATP_CACHE_CBS1, ATP_CACHE_CBS2 = 0, 1, 2, 3, 4, 5
 
@@ -60,6 +61,31 @@ class atp_constraint(ctypes.Structure):
 class atp_cache_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("queries", "whole_hits", "sub_hits", "insert_attempts", "inserts",
                                               "evictions", "items", "bytes", "otree_nodes", "otree_leaves")]
+
+
+class atp_query(ctypes.Structure):
+    _fields_ = [("types", ctypes.c_void_p),
+                ("n_types", ctypes.c_int32),
+                ("rel_ids", ctypes.c_void_p),
+                ("cons", ctypes.c_void_p),
+                ("n_cons", ctypes.c_int32)]
+
+
+class atp_server_options(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_uint64)]
+
+
+class atp_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64),
+                ("status", ctypes.c_int32),
+                ("result", ctypes.c_void_p),
+                ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double),
+                ("batch_size", ctypes.c_int32),
+                ("lane", ctypes.c_int32)]
 
 
 class atp_eval_stats(ctypes.Structure):
@@ -111,6 +137,12 @@ def lib() -> ctypes.CDLL:
         "atp_otree_frequency": ([vp, vp, i32, P(i64)], i32),
         "atp_otree_shape": ([vp, P(i64), P(i64), P(i64), P(i64), P(i64)], i32),
         "atp_cache_simulate": ([i32, ctypes.c_double, i32, vp, vp, vp, i32, vp, vp, vp, vp], i32),
+        "atp_eval_batch": ([vp, vp, i32, i32, i32, ctypes.c_uint64, vp, vp], i32),
+        "atp_server_start": ([vp, P(atp_server_options)], i32),
+        "atp_submit": ([vp, P(atp_query), ctypes.c_uint64], i32),
+        "atp_poll": ([vp, vp, i32, i32], i32),
+        "atp_server_pending": ([vp], i32),
+        "atp_server_stop": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -350,6 +382,67 @@ class Context:
 
     def eval_query(self, query, plan: str | None = None) -> Result:
         return self.eval(query.types, query.constraints, plan=plan)
+
+    def _query(self, query):
+        """(atp_query, arrays it points to) for a query object with types / constraints."""
+        tids = np.array([self.type_ids[t] if isinstance(t, str) else int(t) for t in query.types], dtype=np.int32)
+        names = [t if isinstance(t, str) else None for t in query.types]
+        arr, keep = self._constraints(names, list(query.constraints))
+        q = atp_query()
+        q.types = tids.ctypes.data
+        q.n_types = len(tids)
+        q.rel_ids = None
+        q.cons = ctypes.addressof(arr)
+        q.n_cons = len(query.constraints)
+        return q, (tids, arr, keep)
+
+    # --- batches and serving ---------------------------------------------
+    def eval_batch(self, queries, lanes: int = 4, max_batch: int = 64, mem_budget_bytes: int = 0) -> list:
+        """Evaluate a list of queries on `lanes` lanes, fusing queries that differ
+        only in their start set.  Returns one Result or AtpError per query."""
+        n = len(queries)
+        qs = (atp_query * max(1, n))()
+        keep = []
+        for i, q in enumerate(queries):
+            qs[i], k = self._query(q)
+            keep.append(k)
+        out = (ctypes.c_void_p * max(1, n))()
+        st = (ctypes.c_int32 * max(1, n))()
+        _check(lib().atp_eval_batch(self._h, qs, n, lanes, max_batch, int(mem_budget_bytes), out, st),
+               "atp_eval_batch")
+        del keep
+        return [Result(self, out[i]) if st[i] == ATP_OK else AtpError(st[i], "atp_eval_batch")
+                for i in range(n)]
+
+    def server_start(self, lanes: int = 4, max_batch: int = 64, mem_budget_bytes: int = 0) -> None:
+        o = atp_server_options(lanes, max_batch, int(mem_budget_bytes))
+        _check(lib().atp_server_start(self._h, ctypes.byref(o)), "atp_server_start")
+
+    def submit(self, query, tag: int) -> None:
+        q, keep = self._query(query)
+        _check(lib().atp_submit(self._h, ctypes.byref(q), int(tag)), "atp_submit")
+        del keep
+
+    def poll(self, max_n: int = 256, wait_ms: int = 0) -> list:
+        """Finished requests: dicts with tag, status, result (Result or None),
+        t_submit, t_start, t_done (s), batch, lane."""
+        buf = (atp_completion * max(1, max_n))()
+        k = lib().atp_poll(self._h, buf, max_n, int(wait_ms))
+        if k < 0:
+            raise AtpError(k, "atp_poll")
+        out = []
+        for z in range(k):
+            c = buf[z]
+            out.append({"tag": c.tag, "status": c.status, "result": Result(self, c.result) if c.result else None,
+                        "t_submit": c.t_submit, "t_start": c.t_start, "t_done": c.t_done,
+                        "batch": c.batch_size, "lane": c.lane})
+        return out
+
+    def server_pending(self) -> int:
+        return int(lib().atp_server_pending(self._h))
+
+    def server_stop(self) -> None:
+        _check(lib().atp_server_stop(self._h), "atp_server_stop")
 
     # --- diagnostics -----------------------------------------------------
     def set_flags(self, profile: bool = False, plan_eac: bool = False, count_bytes: bool = False,

@@ -8,11 +8,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libatrapos.so")
-SOURCES = ["kernels.hip", "engine.cpp", "planner.cpp", "otree.cpp"]
+SOURCES = ["kernels.hip", "engine.cpp", "planner.cpp", "otree.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     "--offload-arch=gfx950",
     # packed FP32 instructions stay off in every device pass
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

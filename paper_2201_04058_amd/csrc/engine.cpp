@@ -1,72 +1,18 @@
 // Host side of the engine: the C-ABI of atrapos.h, the HIN registry (Def. 1),
 // constraint masks (Def. 3, the diagonal matrices M_c of Sec. 2), the
 // planner call (Sec. 3.1-3.2) and the post-order executor of the plan tree.
-#include <hip/hip_runtime.h>
+#include "engine.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
-#include <map>
-#include <set>
-#include <memory>
-#include <string>
-#include <vector>
-
-#include "../../include/atrapos.h"
-#include "internal.hpp"
-#include "otree.hpp"
-#include "planner.hpp"
-#include <chrono>
 
 using namespace atp;
 
-// ---------------------------------------------------------------------------
-// kernel timing
-
 namespace atp {
-struct KernelTimer {
-    struct Rec {
-        std::string name;
-        hipEvent_t e0, e1;
-    };
-    std::string suffix;  // appended to kernel names (per-product breakdown)
-    std::vector<hipEvent_t> free_events;
-    std::vector<Rec> pending;
-    std::map<std::string, std::pair<double, int64_t>> acc;
-    std::map<std::string, double> bytes;
-    hipEvent_t take() {
-        if (!free_events.empty()) {
-            hipEvent_t e = free_events.back();
-            free_events.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    void flush() {
-        for (auto &r : pending) {
-            float ms = 0;
-            if (r.e0 && r.e1 && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
-                auto &a = acc[r.name];
-                a.first += ms;
-                a.second += 1;
-            }
-            if (r.e0) free_events.push_back(r.e0);
-            if (r.e1) free_events.push_back(r.e1);
-        }
-        pending.clear();
-    }
-    ~KernelTimer() {
-        for (auto &r : pending) {
-            if (r.e0) (void)hipEventDestroy(r.e0);
-            if (r.e1) (void)hipEventDestroy(r.e1);
-        }
-        for (auto e : free_events) (void)hipEventDestroy(e);
-    }
-};
 
 void timer_begin(KernelTimer *t, const char *name, hipStream_t s) {
     if (!t) return;
@@ -82,172 +28,7 @@ void timer_end(KernelTimer *t, hipStream_t s) {
 }
 }  // namespace atp
 
-// ---------------------------------------------------------------------------
-// device memory: caching pool (or caller callbacks) with an optional budget
-
-namespace {
-
-struct Pool {
-    void *(*user_alloc)(size_t, void *) = nullptr;
-    void (*user_free)(void *, void *) = nullptr;
-    void *user = nullptr;
-    uint64_t budget = 0;
-    int64_t held = 0;  // bytes obtained from the runtime (in use + cached)
-    std::multimap<size_t, void *> cache;
-    std::map<void *, size_t> live;
-
-    static size_t round(size_t n) {
-        if (n < 256) return 256;
-        size_t r = 256;
-        while (r < n && r < ((size_t)1 << 21)) r <<= 1;
-        if (r >= n) return r;
-        const size_t mb2 = (size_t)1 << 21;
-        return (n + mb2 - 1) / mb2 * mb2;
-    }
-    void release_cache() {
-        for (auto &kv : cache) {
-            (void)hipFree(kv.second);
-            held -= (int64_t)kv.first;
-        }
-        cache.clear();
-    }
-    atp_status alloc(size_t bytes, void **out) {
-        *out = nullptr;
-        if (bytes == 0) bytes = 1;
-        size_t n = round(bytes);
-        if (user_alloc) {
-            if (budget && (uint64_t)(held + n) > budget) return ATP_EBUDGET;
-            void *p = user_alloc(n, user);
-            if (!p) return ATP_ENOMEM;
-            live[p] = n;
-            held += (int64_t)n;
-            *out = p;
-            return ATP_OK;
-        }
-        auto it = cache.lower_bound(n);
-        if (it != cache.end() && it->first <= n + n / 4) {
-            void *p = it->second;
-            size_t sz = it->first;
-            cache.erase(it);
-            live[p] = sz;
-            *out = p;
-            return ATP_OK;
-        }
-        if (budget && (uint64_t)(held + n) > budget) {
-            release_cache();
-            if ((uint64_t)(held + n) > budget) return ATP_EBUDGET;
-        }
-        void *p = nullptr;
-        if (hipMalloc(&p, n) != hipSuccess) {
-            (void)hipGetLastError();
-            release_cache();
-            if (hipMalloc(&p, n) != hipSuccess) {
-                (void)hipGetLastError();
-                return ATP_ENOMEM;
-            }
-        }
-        held += (int64_t)n;
-        live[p] = n;
-        *out = p;
-        return ATP_OK;
-    }
-    void release(void *p) {
-        if (!p) return;
-        auto it = live.find(p);
-        if (it == live.end()) return;
-        size_t n = it->second;
-        live.erase(it);
-        if (user_free) {
-            user_free(p, user);
-            held -= (int64_t)n;
-            return;
-        }
-        cache.emplace(n, p);
-    }
-    void destroy() {
-        release_cache();
-        for (auto &kv : live) {
-            if (user_free)
-                user_free(kv.first, user);
-            else
-                (void)hipFree(kv.first);
-        }
-        live.clear();
-        held = 0;
-    }
-};
-
-// RAII device buffer from the pool
-struct Buf {
-    Pool *pool = nullptr;
-    void *p = nullptr;
-    size_t bytes = 0;
-    Buf() = default;
-    Buf(const Buf &) = delete;
-    Buf &operator=(const Buf &) = delete;
-    Buf(Buf &&o) noexcept : pool(o.pool), p(o.p), bytes(o.bytes) { o.p = nullptr; }
-    Buf &operator=(Buf &&o) noexcept {
-        reset();
-        pool = o.pool;
-        p = o.p;
-        bytes = o.bytes;
-        o.p = nullptr;
-        return *this;
-    }
-    ~Buf() { reset(); }
-    void reset() {
-        if (p && pool) pool->release(p);
-        p = nullptr;
-    }
-    atp_status alloc(Pool *pl, size_t n) {
-        reset();
-        pool = pl;
-        bytes = n;
-        return pl->alloc(n, &p);
-    }
-    template <typename T>
-    T *as() const {
-        return (T *)p;
-    }
-};
-
-#define TRY(x)                               \
-    do {                                     \
-        atp_status _st = (x);                \
-        if (_st != ATP_OK) return _st;       \
-    } while (0)
-#define HIPTRY(x)                            \
-    do {                                     \
-        if ((x) != hipSuccess) {             \
-            (void)hipGetLastError();         \
-            return ATP_EDEVICE;              \
-        }                                    \
-    } while (0)
-
-struct NodeType {
-    std::string name;
-    int64_t count;
-};
-
-struct Rel {
-    int32_t src, dst;
-    int64_t nnz;
-    Buf rp, col;
-    std::vector<int64_t> h_rp;      // host row pointers (planner statistics)
-    std::vector<int32_t> h_indeg;   // host column counts
-    int64_t nonempty_rows = 0, nonempty_cols = 0;
-};
-
-struct Prop {
-    int32_t type;
-    int32_t dtype;
-    std::string name;
-    Buf values;
-};
-
-}  // namespace
-
-static Tuning tuning_from_env() {
+Tuning atp::tuning_from_env() {
     Tuning t;
     auto get = [](const char *name, int64_t &v) {
         if (const char *e = std::getenv(name)) v = std::atoll(e);
@@ -269,69 +50,19 @@ static Tuning tuning_from_env() {
     return t;
 }
 
-// Device-resident cached results and their bookkeeping (Sec. 3.3-3.4).
-struct CachePayload {
-    Buf rp, col, val, active;
-    int64_t rows = 0, cols = 0, nnz = 0, n_active = -1;
-    double bytes = 0;
-};
-struct CacheItemInfo {
-    int node = -1;                    // Overlap Tree node, -1 if the string is not in the tree
-    std::vector<int32_t> types;       // the sub-metapath
-    std::vector<int32_t> rels;
-    std::vector<std::string> pos;     // constraint key of every position
-};
-struct CacheState {
-    int32_t policy = ATP_CACHE_OFF;
-    uint64_t budget = 0;
-    std::unique_ptr<OverlapTree> tree;
-    std::unique_ptr<CachePolicy> pol;
-    std::map<std::string, int64_t> item_by_key;
-    std::map<int64_t, CacheItemInfo> info;
-    std::map<int64_t, CachePayload> payload;
-    atp_cache_stats stats{};
-};
-
-struct atp_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    uint32_t flags = 0;
-    Pool pool;
-    std::vector<NodeType> types;
-    std::vector<std::unique_ptr<Rel>> rels;
-    std::vector<std::unique_ptr<Prop>> props;
-    std::map<std::pair<int, int>, JunctionSketch> sketches;
-    std::map<int, ColumnHist> col_hists;
-    KernelTimer timer;
-    CacheState cache;
-    StepHeader *h_hdr = nullptr;  // pinned
-    std::set<atp_result *> results;
-    bool broken = false;
-    bool step_names = std::getenv("ATP_PROFILE_STEPS") != nullptr;  // diagnostics: kernel names per product
-    Tuning tune = tuning_from_env();
-    KernelTimer *kt() { return (flags & ATP_OPT_PROFILE) ? &timer : nullptr; }
-};
-
-struct atp_result {
-    atp_ctx *ctx;
-    int64_t rows, cols, nnz;
-    Buf rp, col, val;
-    atp_eval_stats stats;
-    std::string plan;
-};
 
 // ---------------------------------------------------------------------------
 
 namespace {
 
-atp_status sync(atp_ctx *c) {
-    HIPTRY(hipStreamSynchronize(c->stream));
+atp_status sync(Lane *L) {
+    HIPTRY(hipStreamSynchronize(L->stream));
     return ATP_OK;
 }
 
-atp_status read_header(atp_ctx *c, const StepHeader *d_hdr) {
-    HIPTRY(hipMemcpyAsync(c->h_hdr, d_hdr, sizeof(StepHeader), hipMemcpyDeviceToHost, c->stream));
-    return sync(c);
+atp_status read_header(Lane *L, const StepHeader *d_hdr) {
+    HIPTRY(hipMemcpyAsync(L->h_hdr, d_hdr, sizeof(StepHeader), hipMemcpyDeviceToHost, L->stream));
+    return sync(L);
 }
 
 // A matrix produced by (or feeding) one plan node.
@@ -363,14 +94,14 @@ struct StepStats {
 
 // Counting mode: algorithmic bytes of the numeric launches of one product,
 // by kernel name (operands read once, results written once).
-atp_status count_bytes(atp_ctx *c, const Mat &X, const Mat &Y, const int32_t *cand, const int32_t *bin_lists,
+atp_status count_bytes(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, const int32_t *cand, const int32_t *bin_lists,
                        int64_t n_cand, const StepHeader &h1, const int64_t *row_nnz) {
     struct Group {
         const char *name;
         int b0, b1;
     } groups[] = {{"hash_wave", BIN_W64, BIN_W512}, {"hash_block", BIN_B1024, BIN_B8192}, {"dense", BIN_DENSE, BIN_DENSE},
                   {"bucket", BIN_BUCKET, BIN_BUCKET}};
-    hipStream_t s = c->stream;
+    hipStream_t s = L->stream;
     const double vx = X.op.val ? 8.0 : 0.0, vy = Y.op.val ? 8.0 : 0.0;
     for (const Group &g : groups) {
         int64_t rows_in_group = 0;
@@ -378,8 +109,8 @@ atp_status count_bytes(atp_ctx *c, const Mat &X, const Mat &Y, const int32_t *ca
         if (!rows_in_group) continue;
         Buf ymark, acc;
         const int64_t words = (Y.rows + 31) / 32;
-        TRY(ymark.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(words, 1)));
-        TRY(acc.alloc(&c->pool, 8 * 5));
+        TRY(ymark.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(words, 1)));
+        TRY(acc.alloc(&L->pool, 8 * 5));
         launch_fill_u32(ymark.as<uint32_t>(), words, 0u, s, nullptr);
         launch_fill_i64(acc.as<int64_t>(), 5, 0, s, nullptr);
         for (int b = g.b0; b <= g.b1; ++b)
@@ -388,8 +119,8 @@ atp_status count_bytes(atp_ctx *c, const Mat &X, const Mat &Y, const int32_t *ca
         launch_mark_bytes(ymark.as<uint32_t>(), Y.op.rp, Y.rows, acc.as<int64_t>(), s);
         int64_t h[5];
         HIPTRY(hipMemcpyAsync(h, acc.p, sizeof(h), hipMemcpyDeviceToHost, s));
-        TRY(sync(c));
-        c->timer.bytes[g.name] += 16.0 * h[0] + (4.0 + vx) * h[1] + 12.0 * h[2] + 16.0 * h[3] + (4.0 + vy) * h[4];
+        TRY(sync(L));
+        L->timer.bytes[g.name] += 16.0 * h[0] + (4.0 + vx) * h[1] + 12.0 * h[2] + 16.0 * h[3] + (4.0 + vy) * h[4];
     }
     return ATP_OK;
 }
@@ -397,11 +128,11 @@ atp_status count_bytes(atp_ctx *c, const Mat &X, const Mat &Y, const int32_t *ca
 // Z = X * Y, one product of the plan (Sec. 3.2).  ycols_eff bounds the
 // columns that can occur (mask popcount of Y's last position, or Y's width).
 // need_active: Z will be the left operand of a later product.
-atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, bool need_active, Mat &Z,
+atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols_eff, bool need_active, Mat &Z,
                   StepStats &st, bool &saturated) {
-    Pool *pool = &c->pool;
-    hipStream_t s = c->stream;
-    KernelTimer *t = c->kt();
+    Pool *pool = &L->pool;
+    hipStream_t s = L->stream;
+    KernelTimer *t = c->kt(L);
     Z.leaf = false;
     Z.rows = X.rows;
     Z.cols = Y.cols;
@@ -493,12 +224,16 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     launch_set_header_from_scan(chunk_base.as<int64_t>() + n_cand, &d_hdr->bucket_chunks, s);
     launch_scan_i64(bucket_nop.as<int64_t>(), prod_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
     launch_set_header_from_scan(prod_base.as<int64_t>() + n_cand, &d_hdr->bucket_products, s);
-    TRY(read_header(c, d_hdr));
-    const StepHeader h1 = *c->h_hdr;
+    TRY(read_header(L, d_hdr));
+    const StepHeader h1 = *L->h_hdr;
     st.n_op += h1.n_op_total;
     st.slots += h1.slots_total;
     if (h1.slots_total == 0) return finish_empty();
 
+    // admission: reserve the slot arrays (and the split accumulators) against the lanes' budget
+    const int64_t ntiles_y = (Y.cols + kTileW - 1) / kTileW;
+    GateHold hold(&c->gate, 12ull * (uint64_t)h1.slots_total +
+                                (uint64_t)h1.n_split * (uint64_t)ntiles_y * (uint64_t)kTileW * 9ull);
     Buf slot_col, slot_val, seg_cnt, seg_src, seg_dst, row_cursor, row_nnz;
     TRY(slot_col.alloc(pool, 4 * (size_t)h1.slots_total));
     TRY(slot_val.alloc(pool, 8 * (size_t)h1.slots_total));
@@ -563,7 +298,7 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
                               valued ? prod_val.as<uint64_t>() : nullptr, na, s, t);
     }
 
-    if (c->flags & ATP_OPT_COUNT_BYTES) TRY(count_bytes(c, X, Y, cand, bin_lists.as<int32_t>(), n_cand, h1,
+    if (c->flags & ATP_OPT_COUNT_BYTES) TRY(count_bytes(c, L, X, Y, cand, bin_lists.as<int32_t>(), n_cand, h1,
                                                        row_nnz.as<int64_t>()));
 
     // row pointers over every row of X; segment destinations in (row, tile) order
@@ -580,8 +315,8 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
         launch_scan_i64(flags.as<int64_t>(), flags_scan.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
         launch_set_header_from_scan(flags_scan.as<int64_t>() + n_cand, &d_hdr->n_active, s);
     }
-    TRY(read_header(c, d_hdr));
-    const StepHeader h2 = *c->h_hdr;
+    TRY(read_header(L, d_hdr));
+    const StepHeader h2 = *L->h_hdr;
     saturated = h2.saturated != 0;
     Z.nnz = h2.nnz_total;
     st.nnz += Z.nnz;
@@ -598,16 +333,16 @@ atp_status spgemm(atp_ctx *c, const Mat &X, const Mat &Y, int64_t ycols_eff, boo
     }
     Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
                    Z.rows, Z.cols, Z.nnz};
-    if (c->flags & ATP_OPT_COUNT_BYTES) c->timer.bytes["copy"] += 24.0 * (double)Z.nnz + 24.0 * (double)h1.segs_total;
+    if (c->flags & ATP_OPT_COUNT_BYTES) L->timer.bytes["copy"] += 24.0 * (double)Z.nnz + 24.0 * (double)h1.segs_total;
     // temporaries go back to the pool here; later work on the stream is ordered after this step
     return ATP_OK;
 }
 
 // Build the mask of one metapath position from its constraints (ANDed).
-atp_status build_mask(atp_ctx *c, int pos_type, const atp_constraint *cons, int n_cons, int pos, PosMask &m) {
-    Pool *pool = &c->pool;
-    hipStream_t s = c->stream;
-    KernelTimer *t = c->kt();
+atp_status build_mask(atp_ctx *c, Lane *L, int pos_type, const atp_constraint *cons, int n_cons, int pos, PosMask &m) {
+    Pool *pool = &L->pool;
+    hipStream_t s = L->stream;
+    KernelTimer *t = c->kt(L);
     const int64_t n = c->types[pos_type].count;
     const int64_t words = (n + 31) / 32;
     bool first = true;
@@ -667,6 +402,7 @@ double est_rows_with_ids(const Rel &r, const std::vector<int32_t> &ids, double *
 }
 
 const JunctionSketch &sketch_for(atp_ctx *c, int rin, int rout) {
+    std::lock_guard<std::mutex> g(c->stat_mu);  // map nodes are stable: the reference outlives the lock
     auto key = std::make_pair(rin, rout);
     auto it = c->sketches.find(key);
     if (it != c->sketches.end()) return it->second;
@@ -758,16 +494,17 @@ struct KeptMat {
 // and, for the Overlap-Tree policies, the longest computed sub-metapath whose
 // string is an overlap (an internal Overlap-Tree node); CBS1 only the whole
 // query; CBS2 every computed product.  Replacement follows the policy.
-atp_status cache_insert(atp_ctx *c, const Mat &R, double root_cost, std::vector<KeptMat> &kept,
+atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std::vector<KeptMat> &kept,
                         const std::vector<int64_t> &used, const int32_t *types, const std::vector<int> &rel,
-                        const std::vector<std::string> &pkeys, int p) {
-    CacheState &cs = c->cache;
-    hipStream_t s = c->stream;
-    for (int64_t id : used) {
-        std::vector<int64_t> ev;
-        cs.pol->request(id, ev);
-        cs.stats.sub_hits += 1;
-    }
+                        const std::vector<std::string> &pkeys, int p, int weight) {
+    CacheState &cs = c->cache;  // the caller holds cs.mu
+    hipStream_t s = L->stream;
+    for (int64_t id : used)
+        for (int w = 0; w < weight; ++w) {
+            std::vector<int64_t> ev;
+            cs.pol->request(id, ev);
+            cs.stats.sub_hits += 1;
+        }
     struct Cand {
         int lo, hi;
         double cost;
@@ -810,40 +547,43 @@ atp_status cache_insert(atp_ctx *c, const Mat &R, double root_cost, std::vector<
         std::vector<int64_t> ev;
         const bool ok = cs.pol->request(id, ev);
         for (int64_t e : ev) {
-            cs.payload.erase(e);
+            cs.payload.erase(e);  // a query still using it holds its own reference
             cs.stats.evictions += 1;
         }
         if (!ok) continue;
-        CachePayload P;
-        P.rows = m.rows;
-        P.cols = m.cols;
-        P.nnz = m.nnz;
-        P.bytes = cs.pol->item(id).size;
+        auto P = std::make_shared<CachePayload>();
+        P->rows = m.rows;
+        P->cols = m.cols;
+        P->nnz = m.nnz;
+        P->bytes = cs.pol->item(id).size;
         if (cd.root) {  // the caller keeps R: copy it
-            TRY(P.rp.alloc(&c->pool, 8 * (size_t)(m.rows + 1)));
-            TRY(P.col.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(m.nnz, 1)));
-            TRY(P.val.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(m.nnz, 1)));
-            HIPTRY(hipMemcpyAsync(P.rp.p, m.rp.p, 8 * (m.rows + 1), hipMemcpyDeviceToDevice, s));
+            TRY(P->rp.alloc(&L->pool, 8 * (size_t)(m.rows + 1)));
+            TRY(P->col.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(m.nnz, 1)));
+            TRY(P->val.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(m.nnz, 1)));
+            HIPTRY(hipMemcpyAsync(P->rp.p, m.rp.p, 8 * (m.rows + 1), hipMemcpyDeviceToDevice, s));
             if (m.nnz) {
-                HIPTRY(hipMemcpyAsync(P.col.p, m.col.p, 4 * m.nnz, hipMemcpyDeviceToDevice, s));
-                HIPTRY(hipMemcpyAsync(P.val.p, m.val.p, 8 * m.nnz, hipMemcpyDeviceToDevice, s));
+                HIPTRY(hipMemcpyAsync(P->col.p, m.col.p, 4 * m.nnz, hipMemcpyDeviceToDevice, s));
+                HIPTRY(hipMemcpyAsync(P->val.p, m.val.p, 8 * m.nnz, hipMemcpyDeviceToDevice, s));
             }
-            P.n_active = -1;
+            P->n_active = -1;
         } else {
-            P.rp = std::move(cd.m->rp);
-            P.col = std::move(cd.m->col);
-            P.val = std::move(cd.m->val);
-            P.n_active = cd.m->n_active;
-            if (cd.m->n_active >= 0) P.active = std::move(cd.m->active);
+            P->rp = std::move(cd.m->rp);
+            P->col = std::move(cd.m->col);
+            P->val = std::move(cd.m->val);
+            P->n_active = cd.m->n_active;
+            if (cd.m->n_active >= 0) P->active = std::move(cd.m->active);
         }
+        // other lanes order their reads after this lane's writes through the event
+        HIPTRY(hipEventCreateWithFlags(&P->ready, hipEventDisableTiming));
+        HIPTRY(hipEventRecord(P->ready, s));
         cs.payload[id] = std::move(P);
         cs.stats.inserts += 1;
     }
     return ATP_OK;
 }
 
-atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
-                     const atp_constraint *cons, int32_t n_cons, const char *plan, atp_result **out) {
+atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                     const atp_constraint *cons, int32_t n_cons, const char *plan, int weight, atp_result **out) {
     if (out) *out = nullptr;
     if (!c || !types || !out) return ATP_EINVAL;
     if (c->broken) return ATP_EDEVICE;
@@ -891,22 +631,22 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     int forced_root = -1;
     if (plan && !parse_plan(plan, p, forced, forced_root)) return ATP_EINVAL;
 
-    hipStream_t s = c->stream;
-    KernelTimer *t = c->kt();
+    hipStream_t s = L->stream;
+    KernelTimer *t = c->kt(L);
     // masks M_1..M_n (Def. 3)
     std::vector<PosMask> masks(n_types);
     Buf pops;
-    TRY(pops.alloc(&c->pool, 8 * n_types));
+    TRY(pops.alloc(&L->pool, 8 * n_types));
     launch_fill_i64(pops.as<int64_t>(), n_types, 0, s, t);
     for (int i = 0; i < n_types; ++i) {
-        TRY(build_mask(c, types[i], cons, n_cons, i, masks[i]));
+        TRY(build_mask(c, L, types[i], cons, n_cons, i, masks[i]));
         if (masks[i].pop >= 0)
             launch_popcount(masks[i].bits.as<uint32_t>(), (c->types[types[i]].count + 31) / 32,
                             pops.as<int64_t>() + i, s, t);
     }
     std::vector<int64_t> h_pop(n_types, 0);
     HIPTRY(hipMemcpyAsync(h_pop.data(), pops.p, 8 * n_types, hipMemcpyDeviceToHost, s));
-    TRY(sync(c));
+    TRY(sync(L));
     for (int i = 0; i < n_types; ++i)
         if (masks[i].pop >= 0) masks[i].pop = h_pop[i];
     auto sel_of = [&](int i) {
@@ -951,9 +691,11 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     }
     // ---- workload cache: Overlap Tree update and cached sub-chains ----
     CacheState &cs = c->cache;
+    std::unique_lock<std::mutex> cache_lock(cs.mu);
     const bool caching = cs.policy != ATP_CACHE_OFF && p >= 2;
     std::vector<std::string> pkeys;
     std::vector<std::vector<int64_t>> cached_item(p, std::vector<int64_t>(p, -1));
+    std::map<int64_t, PayloadRef> pins;  // cached results this query may read
     std::vector<ChainStats> cached_stats_store(p * p);
     std::vector<std::vector<const ChainStats *>> cached_stats(p, std::vector<const ChainStats *>(p, nullptr));
     auto sub_types = [&](int a, int b) { return std::vector<int32_t>(types + a, types + b + 2); };
@@ -961,14 +703,14 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     auto sub_pos = [&](int a, int b) { return std::vector<std::string>(pkeys.begin() + a, pkeys.begin() + b + 2); };
     if (caching) {
         pkeys = position_keys(n_types, cons, n_cons);
-        cs.tree->insert(std::vector<int32_t>(types, types + n_types));
-        cs.stats.queries += 1;
+        for (int w = 0; w < weight; ++w) cs.tree->insert(std::vector<int32_t>(types, types + n_types));
+        cs.stats.queries += weight;
         for (int a = 0; a < p; ++a)
             for (int b = a; b < p; ++b) {
                 const std::vector<int32_t> st_ = sub_types(a, b);
                 const std::string key = item_key(st_, sub_rels(a, b), sub_pos(a, b));
                 const int node = cs.tree->find(st_);
-                if (node >= 0) cs.tree->node(node).keys[key].f += 1;
+                if (node >= 0) cs.tree->node(node).keys[key].f += weight;
                 auto it = cs.item_by_key.find(key);
                 if (it == cs.item_by_key.end()) continue;
                 if (node >= 0) cs.tree->node(node).keys[key].item = it->second;
@@ -976,8 +718,9 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
                 auto pl = cs.payload.find(it->second);
                 if (pl == cs.payload.end() || b == a) continue;
                 cached_item[a][b] = it->second;
+                pins[it->second] = pl->second;
                 ChainStats &z = cached_stats_store[a * p + b];
-                const CachePayload &P = pl->second;
+                const CachePayload &P = *pl->second;
                 z.dim_r = (double)P.rows;
                 z.dim_c = (double)P.cols;
                 z.nnz = (double)P.nnz;
@@ -986,6 +729,7 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
                 cached_stats[a][b] = &z;
             }
     }
+    cache_lock.unlock();
 
     std::string plan_str;
     if (plan) {
@@ -1002,6 +746,7 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
             jsel.push_back(sel_of(k + 1));
         }
         for (int k = 0; k < p && !uniform; ++k) {
+            std::lock_guard<std::mutex> g(c->stat_mu);
             auto it = c->col_hists.find(rel[k]);
             if (it == c->col_hists.end()) {
                 const Rel &r = *c->rels[rel[k]];
@@ -1023,15 +768,15 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     Mat ident;
     if (p == 1) {
         const int64_t n = leaves[0].cols;
-        TRY(ident_rp.alloc(&c->pool, 8 * (n + 1)));
-        TRY(ident_col.alloc(&c->pool, 4 * std::max<int64_t>(n, 1)));
+        TRY(ident_rp.alloc(&L->pool, 8 * (n + 1)));
+        TRY(ident_col.alloc(&L->pool, 4 * std::max<int64_t>(n, 1)));
         std::vector<int64_t> h_rp(n + 1);
         std::vector<int32_t> h_col(n);
         for (int64_t z = 0; z <= n; ++z) h_rp[z] = z;
         for (int64_t z = 0; z < n; ++z) h_col[z] = (int32_t)z;
         HIPTRY(hipMemcpyAsync(ident_rp.p, h_rp.data(), 8 * (n + 1), hipMemcpyHostToDevice, s));
         if (n) HIPTRY(hipMemcpyAsync(ident_col.p, h_col.data(), 4 * n, hipMemcpyHostToDevice, s));
-        TRY(sync(c));
+        TRY(sync(L));
         ident.leaf = true;
         ident.rows = ident.cols = n;
         ident.nnz = n;
@@ -1043,7 +788,7 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     bool overflow = false;
     std::vector<PlanTree> &tree = forced;
     std::vector<Buf> keep;  // restriction buffers, alive until the query ends
-    const bool restrict_rows = (c->flags & ATP_OPT_NO_RESTRICT) == 0 && c->cache.policy == ATP_CACHE_OFF;
+    const bool restrict_rows = (c->flags & ATP_OPT_NO_RESTRICT) == 0 && !caching;
     // Rows of a right sub-chain that can matter: the columns its left neighbour uses.
     struct Restriction {
         const uint32_t *bits = nullptr;
@@ -1053,16 +798,16 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     auto make_restriction = [&](const Mat &X, int64_t n_rows_y, Restriction &r) -> atp_status {
         const int64_t words = (n_rows_y + 31) / 32;
         Buf bits, cnt, scan, tmpb, list;
-        TRY(bits.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(words, 1)));
-        TRY(cnt.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(words, 1)));
-        TRY(scan.alloc(&c->pool, 8 * (size_t)(words + 1)));
-        TRY(tmpb.alloc(&c->pool, 8 * (size_t)scan_tmp_elems(words)));
+        TRY(bits.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(words, 1)));
+        TRY(cnt.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(words, 1)));
+        TRY(scan.alloc(&L->pool, 8 * (size_t)(words + 1)));
+        TRY(tmpb.alloc(&L->pool, 8 * (size_t)scan_tmp_elems(words)));
         launch_fill_u32(bits.as<uint32_t>(), words, 0u, s, t);
         Buf len, off, tmpc;
         if (X.leaf) {
-            TRY(len.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(X.n_cand, 1)));
-            TRY(off.alloc(&c->pool, 8 * (size_t)(X.n_cand + 1)));
-            TRY(tmpc.alloc(&c->pool, 8 * (size_t)scan_tmp_elems(X.n_cand)));
+            TRY(len.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(X.n_cand, 1)));
+            TRY(off.alloc(&L->pool, 8 * (size_t)(X.n_cand + 1)));
+            TRY(tmpc.alloc(&L->pool, 8 * (size_t)scan_tmp_elems(X.n_cand)));
             launch_leaf_cols_to_bits(X.op, X.cand, X.n_cand, len.as<int64_t>(), off.as<int64_t>(), tmpc.as<int64_t>(),
                                      bits.as<uint32_t>(), s, t);
         } else
@@ -1070,8 +815,8 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         launch_bits_count(bits.as<uint32_t>(), words, cnt.as<int64_t>(), scan.as<int64_t>(), tmpb.as<int64_t>(), s, t);
         int64_t n = 0;
         HIPTRY(hipMemcpyAsync(&n, scan.as<int64_t>() + words, 8, hipMemcpyDeviceToHost, s));
-        TRY(sync(c));
-        TRY(list.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(n, 1)));
+        TRY(sync(L));
+        TRY(list.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(n, 1)));
         launch_bits_scatter(bits.as<uint32_t>(), words, scan.as<int64_t>(), list.as<int32_t>(), s, t);
         r.bits = bits.as<uint32_t>();
         r.list = list.as<int32_t>();
@@ -1093,7 +838,8 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
             lo = nd.block_lo;
             hi = nd.block_hi;
             const int64_t id = cached_item[lo][hi];
-            const CachePayload &P = cs.payload.at(id);
+            const CachePayload &P = *pins.at(id);
+            HIPTRY(hipStreamWaitEvent(s, P.ready, 0));
             outm = Mat();
             outm.view = true;
             outm.rows = P.rows;
@@ -1146,11 +892,11 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         const int last_pos = r1 + 1;  // metapath position of Y's last type
         const int64_t ycols_eff = masks[last_pos].pop >= 0 ? masks[last_pos].pop : Y.cols;
         bool sat = false;
-        if (c->step_names) c->timer.suffix = "#" + std::to_string(n_products);
+        if (c->step_names) L->timer.suffix = "#" + std::to_string(n_products);
         const auto t_0 = std::chrono::steady_clock::now();
-        TRY(spgemm(c, X, Y, ycols_eff, as_left, outm, st, sat));
+        TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat));
         cost = cx + cy + std::chrono::duration<double>(std::chrono::steady_clock::now() - t_0).count();
-        c->timer.suffix.clear();
+        L->timer.suffix.clear();
         ++n_products;
         if (v == forced_root && sat) overflow = true;
         if (caching) {  // keep computed operands for the insertion policy
@@ -1175,33 +921,39 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
         X.n_cand = leaves[0].n_cand;
         ident.op.cmask = leaves[0].op.cmask;
         bool sat = false;
-        stt = spgemm(c, X, ident, ycols_eff, false, R, st, sat);
+        stt = spgemm(c, L, X, ident, ycols_eff, false, R, st, sat);
         n_products = 1;
         overflow = sat;
     } else if (caching && tree[forced_root].block_lo == 0 && tree[forced_root].block_hi == p - 1) {
         // the whole query is cached: hand out a copy
         const int64_t id = cached_item[0][p - 1];
-        const CachePayload &P = cs.payload.at(id);
+        const CachePayload &P = *pins.at(id);
         R.rows = P.rows;
         R.cols = P.cols;
         R.nnz = P.nnz;
-        stt = ATP_OK;
-        if ((stt = R.rp.alloc(&c->pool, 8 * (size_t)(P.rows + 1))) == ATP_OK &&
-            (stt = R.col.alloc(&c->pool, 4 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK &&
-            (stt = R.val.alloc(&c->pool, 8 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK) {
+        stt = hipStreamWaitEvent(s, P.ready, 0) == hipSuccess ? ATP_OK : ATP_EDEVICE;
+        if (stt == ATP_OK && (stt = R.rp.alloc(&L->pool, 8 * (size_t)(P.rows + 1))) == ATP_OK &&
+            (stt = R.col.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK &&
+            (stt = R.val.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK) {
             if (hipMemcpyAsync(R.rp.p, P.rp.p, 8 * (P.rows + 1), hipMemcpyDeviceToDevice, s) != hipSuccess ||
                 (P.nnz && hipMemcpyAsync(R.col.p, P.col.p, 4 * P.nnz, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
                 (P.nnz && hipMemcpyAsync(R.val.p, P.val.p, 8 * P.nnz, hipMemcpyDeviceToDevice, s) != hipSuccess))
                 stt = ATP_EDEVICE;
         }
-        std::vector<int64_t> ev;
-        cs.pol->request(id, ev);
-        cs.stats.whole_hits += 1;
+        std::lock_guard<std::mutex> g(cs.mu);
+        for (int w = 0; w < weight; ++w) {
+            std::vector<int64_t> ev;
+            cs.pol->request(id, ev);
+            cs.stats.whole_hits += 1;
+        }
     } else {
         double root_cost = 0;
         stt = run(forced_root, false, nullptr, R, lo, hi, root_cost);
-        if (stt == ATP_OK && caching && !overflow) stt = cache_insert(c, R, root_cost, kept, used_items, types,
-                                                                    rel, pkeys, p);
+        if (stt == ATP_OK && caching && !overflow) {
+            std::lock_guard<std::mutex> g(cs.mu);
+            if (cs.pol)  // the cache may have been switched off meanwhile
+                stt = cache_insert(c, L, R, root_cost, kept, used_items, types, rel, pkeys, p, weight);
+        }
     }
     if (stt != ATP_OK) {
         if (stt == ATP_EDEVICE) c->broken = true;
@@ -1213,6 +965,7 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     if (overflow) return ATP_EOVERFLOW;
     atp_result *res = new atp_result();
     res->ctx = c;
+    res->stream = s;
     res->rows = R.rows;
     res->cols = R.cols;
     res->nnz = R.nnz;
@@ -1225,12 +978,53 @@ atp_status eval_impl(atp_ctx *c, const int32_t *types, int32_t n_types, const in
     res->stats.nnz_result = R.nnz;
     res->stats.nnz_intermediate_total = st.nnz - R.nnz;
     res->stats.slots_total = st.slots;
-    c->results.insert(res);
+    register_result(c, res);
     *out = res;
     return ATP_OK;
 }
 
 }  // namespace
+
+namespace atp {
+
+void register_result(atp_ctx *c, atp_result *r) {
+    std::lock_guard<std::mutex> g(c->results_mu);
+    c->results.insert(r);
+}
+
+atp_status eval_query(atp_ctx *c, Lane *L, const QueryRef &q, const char *plan, int weight, atp_result **out) {
+    return eval_impl(c, L, q.types, q.n_types, q.rel_ids, q.cons, q.n_cons, plan, weight < 1 ? 1 : weight, out);
+}
+
+atp_status lane_init(atp_ctx *c, Lane *L, int id) {
+    L->id = id;
+    L->pool.budget = c->main.pool.budget;
+    L->pool.user_alloc = c->main.pool.user_alloc;
+    L->pool.user_free = c->main.pool.user_free;
+    L->pool.user = c->main.pool.user;
+    if (hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return ATP_EDEVICE;
+    }
+    L->own_stream = true;
+    if (hipHostMalloc((void **)&L->h_hdr, sizeof(StepHeader), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return ATP_ENOMEM;
+    }
+    return ATP_OK;
+}
+
+void lane_destroy(Lane *L) {
+    if (L->stream) (void)hipStreamSynchronize(L->stream);
+    L->timer.flush();
+    L->pool.destroy();
+    if (L->h_hdr) (void)hipHostFree(L->h_hdr);
+    L->h_hdr = nullptr;
+    if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
+    L->stream = nullptr;
+}
+
+}  // namespace atp
 
 // ---------------------------------------------------------------------------
 // C-ABI
@@ -1266,13 +1060,13 @@ atp_status atp_create(const atp_options *o, atp_ctx **out) {
     if (hipSetDevice(d.device) != hipSuccess) return ATP_EDEVICE;
     atp_ctx *c = new atp_ctx();
     c->device = d.device;
-    c->stream = (hipStream_t)d.hip_stream;
+    c->main.stream = (hipStream_t)d.hip_stream;
     c->flags = d.flags;
-    c->pool.user_alloc = d.alloc;
-    c->pool.user_free = d.free;
-    c->pool.user = d.alloc_user;
-    c->pool.budget = d.mem_budget_bytes;
-    if (hipHostMalloc((void **)&c->h_hdr, sizeof(StepHeader), hipHostMallocDefault) != hipSuccess) {
+    c->main.pool.user_alloc = d.alloc;
+    c->main.pool.user_free = d.free;
+    c->main.pool.user = d.alloc_user;
+    c->main.pool.budget = d.mem_budget_bytes;
+    if (hipHostMalloc((void **)&c->main.h_hdr, sizeof(StepHeader), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return ATP_ENOMEM;
@@ -1284,15 +1078,19 @@ atp_status atp_create(const atp_options *o, atp_ctx **out) {
 atp_status atp_destroy(atp_ctx *c) {
     if (!c) return ATP_EINVAL;
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    server_shutdown(c);
+    (void)hipStreamSynchronize(c->main.stream);
+    for (auto &ln : c->lanes) (void)hipStreamSynchronize(ln->stream);
     for (atp_result *r : c->results) delete r;
     c->results.clear();
     c->cache.payload.clear();
+    for (auto &ln : c->lanes) lane_destroy(ln.get());
+    c->lanes.clear();
     c->rels.clear();
     c->props.clear();
-    c->timer.flush();
-    c->pool.destroy();
-    if (c->h_hdr) (void)hipHostFree(c->h_hdr);
+    c->main.timer.flush();
+    c->main.pool.destroy();
+    if (c->main.h_hdr) (void)hipHostFree(c->main.h_hdr);
     delete c;
     return ATP_OK;
 }
@@ -1311,15 +1109,15 @@ static atp_status add_rel_host(atp_ctx *c, int32_t src, int32_t dst, std::vector
     r->dst = dst;
     r->nnz = (int64_t)col.size();
     const int64_t m = c->types[src].count, n = c->types[dst].count;
-    TRY(r->rp.alloc(&c->pool, 8 * (m + 1)));
-    TRY(r->col.alloc(&c->pool, 4 * std::max<int64_t>(r->nnz, 1)));
-    HIPTRY(hipMemcpyAsync(r->rp.p, rp.data(), 8 * (m + 1), hipMemcpyHostToDevice, c->stream));
-    if (r->nnz) HIPTRY(hipMemcpyAsync(r->col.p, col.data(), 4 * r->nnz, hipMemcpyHostToDevice, c->stream));
+    TRY(r->rp.alloc(&c->main.pool, 8 * (m + 1)));
+    TRY(r->col.alloc(&c->main.pool, 4 * std::max<int64_t>(r->nnz, 1)));
+    HIPTRY(hipMemcpyAsync(r->rp.p, rp.data(), 8 * (m + 1), hipMemcpyHostToDevice, c->main.stream));
+    if (r->nnz) HIPTRY(hipMemcpyAsync(r->col.p, col.data(), 4 * r->nnz, hipMemcpyHostToDevice, c->main.stream));
     r->h_indeg.assign(n, 0);
     for (int32_t j : col) r->h_indeg[j]++;
     for (int64_t i = 0; i < m; ++i) r->nonempty_rows += rp[i + 1] > rp[i];
     for (int64_t j = 0; j < n; ++j) r->nonempty_cols += r->h_indeg[j] > 0;
-    HIPTRY(hipStreamSynchronize(c->stream));
+    HIPTRY(hipStreamSynchronize(c->main.stream));
     r->h_rp = std::move(rp);
     c->rels.push_back(std::move(r));
     if (rel_id) *rel_id = (int32_t)c->rels.size() - 1;
@@ -1384,9 +1182,9 @@ atp_status atp_add_property(atp_ctx *c, int32_t type_id, const char *name, int32
     p->type = type_id;
     p->dtype = dtype;
     p->name = name ? name : "";
-    TRY(p->values.alloc(&c->pool, es * std::max<int64_t>(n, 1)));
-    if (n) HIPTRY(hipMemcpyAsync(p->values.p, values, es * n, hipMemcpyHostToDevice, c->stream));
-    HIPTRY(hipStreamSynchronize(c->stream));
+    TRY(p->values.alloc(&c->main.pool, es * std::max<int64_t>(n, 1)));
+    if (n) HIPTRY(hipMemcpyAsync(p->values.p, values, es * n, hipMemcpyHostToDevice, c->main.stream));
+    HIPTRY(hipStreamSynchronize(c->main.stream));
     c->props.push_back(std::move(p));
     if (prop_id) *prop_id = (int32_t)c->props.size() - 1;
     return ATP_OK;
@@ -1395,13 +1193,13 @@ atp_status atp_add_property(atp_ctx *c, int32_t type_id, const char *name, int32
 atp_status atp_eval(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
                     const atp_constraint *cons, int32_t n_cons, atp_result **out) {
     if (c) (void)hipSetDevice(c->device);
-    return eval_impl(c, types, n_types, rel_ids, cons, n_cons, nullptr, out);
+    return eval_impl(c, &c->main, types, n_types, rel_ids, cons, n_cons, nullptr, 1, out);
 }
 
 atp_status atp_eval_plan(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
                          const atp_constraint *cons, int32_t n_cons, const char *plan, atp_result **out) {
     if (c) (void)hipSetDevice(c->device);
-    return eval_impl(c, types, n_types, rel_ids, cons, n_cons, plan, out);
+    return eval_impl(c, &c->main, types, n_types, rel_ids, cons, n_cons, plan, 1, out);
 }
 
 atp_status atp_result_csr(const atp_result *r, int64_t *n_rows, int64_t *n_cols, int64_t *nnz,
@@ -1418,7 +1216,7 @@ atp_status atp_result_csr(const atp_result *r, int64_t *n_rows, int64_t *n_cols,
 
 atp_status atp_result_to_host(const atp_result *r, int64_t *row_ptr, int32_t *col, int64_t *val) {
     if (!r) return ATP_EINVAL;
-    hipStream_t s = r->ctx->stream;
+    hipStream_t s = r->stream;
     if (row_ptr) HIPTRY(hipMemcpyAsync(row_ptr, r->rp.p, 8 * (r->rows + 1), hipMemcpyDeviceToHost, s));
     if (col && r->nnz) HIPTRY(hipMemcpyAsync(col, r->col.p, 4 * r->nnz, hipMemcpyDeviceToHost, s));
     if (val && r->nnz) HIPTRY(hipMemcpyAsync(val, r->val.p, 8 * r->nnz, hipMemcpyDeviceToHost, s));
@@ -1437,7 +1235,10 @@ atp_status atp_result_stats(const atp_result *r, atp_eval_stats *stats, char *pl
 
 atp_status atp_result_free(atp_result *r) {
     if (!r) return ATP_EINVAL;
-    r->ctx->results.erase(r);
+    {
+        std::lock_guard<std::mutex> g(r->ctx->results_mu);
+        r->ctx->results.erase(r);
+    }
     delete r;
     return ATP_OK;
 }
@@ -1499,19 +1300,19 @@ atp_status atp_set_flags(atp_ctx *c, uint32_t flags) {
 
 int32_t atp_kernel_times(atp_ctx *c, const char **names, double *ms, int64_t *launches, double *bytes, int32_t cap) {
     if (!c) return 0;
-    c->timer.flush();
+    c->main.timer.flush();
     std::map<std::string, int> keys;
-    for (auto &kv : c->timer.acc) keys[kv.first] = 1;
-    for (auto &kv : c->timer.bytes) keys[kv.first] = 1;
+    for (auto &kv : c->main.timer.acc) keys[kv.first] = 1;
+    for (auto &kv : c->main.timer.bytes) keys[kv.first] = 1;
     int32_t n = 0;
     for (auto &kv : keys) {
         if (n >= cap) break;
-        auto it = c->timer.acc.find(kv.first);
-        auto ib = c->timer.bytes.find(kv.first);
-        if (names) names[n] = kv.first == "" ? "" : (it != c->timer.acc.end() ? it->first.c_str() : ib->first.c_str());
-        if (ms) ms[n] = it != c->timer.acc.end() ? it->second.first : 0.0;
-        if (launches) launches[n] = it != c->timer.acc.end() ? it->second.second : 0;
-        if (bytes) bytes[n] = ib != c->timer.bytes.end() ? ib->second : 0.0;
+        auto it = c->main.timer.acc.find(kv.first);
+        auto ib = c->main.timer.bytes.find(kv.first);
+        if (names) names[n] = kv.first == "" ? "" : (it != c->main.timer.acc.end() ? it->first.c_str() : ib->first.c_str());
+        if (ms) ms[n] = it != c->main.timer.acc.end() ? it->second.first : 0.0;
+        if (launches) launches[n] = it != c->main.timer.acc.end() ? it->second.second : 0;
+        if (bytes) bytes[n] = ib != c->main.timer.bytes.end() ? ib->second : 0.0;
         ++n;
     }
     return n;
@@ -1519,17 +1320,23 @@ int32_t atp_kernel_times(atp_ctx *c, const char **names, double *ms, int64_t *la
 
 void atp_kernel_times_reset(atp_ctx *c) {
     if (!c) return;
-    c->timer.flush();
-    c->timer.acc.clear();
-    c->timer.bytes.clear();
+    c->main.timer.flush();
+    c->main.timer.acc.clear();
+    c->main.timer.bytes.clear();
 }
 
-int64_t atp_device_bytes(const atp_ctx *c) { return c ? c->pool.held : 0; }
+int64_t atp_device_bytes(const atp_ctx *c) {
+    if (!c) return 0;
+    int64_t n = c->main.pool.held;
+    for (auto &ln : c->lanes) n += ln->pool.held;
+    return n;
+}
 
 atp_status atp_cache_configure(atp_ctx *c, int32_t policy, uint64_t budget_bytes) {
     if (!c || policy < ATP_CACHE_OFF || policy > ATP_CACHE_CBS2) return ATP_EINVAL;
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->main.stream);
     CacheState &cs = c->cache;
+    std::lock_guard<std::mutex> g(cs.mu);
     cs.payload.clear();
     cs.info.clear();
     cs.item_by_key.clear();
@@ -1550,7 +1357,8 @@ atp_status atp_cache_configure(atp_ctx *c, int32_t policy, uint64_t budget_bytes
 
 atp_status atp_cache_get_stats(const atp_ctx *c, atp_cache_stats *st) {
     if (!c || !st) return ATP_EINVAL;
-    const CacheState &cs = c->cache;
+    CacheState &cs = const_cast<atp_ctx *>(c)->cache;
+    std::lock_guard<std::mutex> g(cs.mu);
     *st = cs.stats;
     st->items = cs.pol ? cs.pol->cached_count() : 0;
     st->bytes = cs.pol ? (int64_t)cs.pol->used() : 0;

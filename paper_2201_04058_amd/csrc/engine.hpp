@@ -1,0 +1,367 @@
+// Host-side structures of the engine shared by the executor (engine.cpp) and
+// the batch / serving layer (serve.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/atrapos.h"
+#include "internal.hpp"
+#include "otree.hpp"
+#include "planner.hpp"
+
+namespace atp {
+
+// Per-kernel event timing of one lane (ATP_OPT_PROFILE).
+struct KernelTimer {
+    struct Rec {
+        std::string name;
+        hipEvent_t e0, e1;
+    };
+    std::string suffix;  // appended to kernel names (per-product breakdown)
+    std::vector<hipEvent_t> free_events;
+    std::vector<Rec> pending;
+    std::map<std::string, std::pair<double, int64_t>> acc;
+    std::map<std::string, double> bytes;
+    hipEvent_t take() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void flush() {
+        for (auto &r : pending) {
+            float ms = 0;
+            if (r.e0 && r.e1 && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+                auto &a = acc[r.name];
+                a.first += ms;
+                a.second += 1;
+            }
+            if (r.e0) free_events.push_back(r.e0);
+            if (r.e1) free_events.push_back(r.e1);
+        }
+        pending.clear();
+    }
+    ~KernelTimer() {
+        for (auto &r : pending) {
+            if (r.e0) (void)hipEventDestroy(r.e0);
+            if (r.e1) (void)hipEventDestroy(r.e1);
+        }
+        for (auto e : free_events) (void)hipEventDestroy(e);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// device memory: caching pool (or caller callbacks) with an optional budget
+
+struct Pool {
+    void *(*user_alloc)(size_t, void *) = nullptr;
+    void (*user_free)(void *, void *) = nullptr;
+    void *user = nullptr;
+    uint64_t budget = 0;
+    int64_t held = 0;  // bytes obtained from the runtime (in use + cached)
+    std::multimap<size_t, void *> cache;
+    std::map<void *, size_t> live;
+    std::recursive_mutex mu;  // lanes release each other's buffers (cache eviction, results)
+
+    static size_t round(size_t n) {
+        if (n < 256) return 256;
+        size_t r = 256;
+        while (r < n && r < ((size_t)1 << 21)) r <<= 1;
+        if (r >= n) return r;
+        const size_t mb2 = (size_t)1 << 21;
+        return (n + mb2 - 1) / mb2 * mb2;
+    }
+    void release_cache() {
+        std::lock_guard<std::recursive_mutex> g(mu);
+        for (auto &kv : cache) {
+            (void)hipFree(kv.second);
+            held -= (int64_t)kv.first;
+        }
+        cache.clear();
+    }
+    atp_status alloc(size_t bytes, void **out) {
+        std::lock_guard<std::recursive_mutex> g(mu);
+        *out = nullptr;
+        if (bytes == 0) bytes = 1;
+        size_t n = round(bytes);
+        if (user_alloc) {
+            if (budget && (uint64_t)(held + n) > budget) return ATP_EBUDGET;
+            void *p = user_alloc(n, user);
+            if (!p) return ATP_ENOMEM;
+            live[p] = n;
+            held += (int64_t)n;
+            *out = p;
+            return ATP_OK;
+        }
+        auto it = cache.lower_bound(n);
+        if (it != cache.end() && it->first <= n + n / 4) {
+            void *p = it->second;
+            size_t sz = it->first;
+            cache.erase(it);
+            live[p] = sz;
+            *out = p;
+            return ATP_OK;
+        }
+        if (budget && (uint64_t)(held + n) > budget) {
+            release_cache();
+            if ((uint64_t)(held + n) > budget) return ATP_EBUDGET;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            release_cache();
+            if (hipMalloc(&p, n) != hipSuccess) {
+                (void)hipGetLastError();
+                return ATP_ENOMEM;
+            }
+        }
+        held += (int64_t)n;
+        live[p] = n;
+        *out = p;
+        return ATP_OK;
+    }
+    void release(void *p) {
+        if (!p) return;
+        std::lock_guard<std::recursive_mutex> g(mu);
+        auto it = live.find(p);
+        if (it == live.end()) return;
+        size_t n = it->second;
+        live.erase(it);
+        if (user_free) {
+            user_free(p, user);
+            held -= (int64_t)n;
+            return;
+        }
+        cache.emplace(n, p);
+    }
+    void destroy() {
+        std::lock_guard<std::recursive_mutex> g(mu);
+        release_cache();
+        for (auto &kv : live) {
+            if (user_free)
+                user_free(kv.first, user);
+            else
+                (void)hipFree(kv.first);
+        }
+        live.clear();
+        held = 0;
+    }
+};
+
+// RAII device buffer from the pool
+struct Buf {
+    Pool *pool = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    Buf() = default;
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+    Buf(Buf &&o) noexcept : pool(o.pool), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+    Buf &operator=(Buf &&o) noexcept {
+        reset();
+        pool = o.pool;
+        p = o.p;
+        bytes = o.bytes;
+        o.p = nullptr;
+        return *this;
+    }
+    ~Buf() { reset(); }
+    void reset() {
+        if (p && pool) pool->release(p);
+        p = nullptr;
+    }
+    atp_status alloc(Pool *pl, size_t n) {
+        reset();
+        pool = pl;
+        bytes = n;
+        return pl->alloc(n, &p);
+    }
+    template <typename T>
+    T *as() const {
+        return (T *)p;
+    }
+};
+
+#define TRY(x)                               \
+    do {                                     \
+        atp_status _st = (x);                \
+        if (_st != ATP_OK) return _st;       \
+    } while (0)
+#define HIPTRY(x)                            \
+    do {                                     \
+        if ((x) != hipSuccess) {             \
+            (void)hipGetLastError();         \
+            return ATP_EDEVICE;              \
+        }                                    \
+    } while (0)
+
+struct NodeType {
+    std::string name;
+    int64_t count;
+};
+
+struct Rel {
+    int32_t src, dst;
+    int64_t nnz;
+    Buf rp, col;
+    std::vector<int64_t> h_rp;      // host row pointers (planner statistics)
+    std::vector<int32_t> h_indeg;   // host column counts
+    int64_t nonempty_rows = 0, nonempty_cols = 0;
+};
+
+struct Prop {
+    int32_t type;
+    int32_t dtype;
+    std::string name;
+    Buf values;
+};
+
+Tuning tuning_from_env();
+
+// One execution lane: a stream with its own memory pool, pinned header and
+// timers.  The context's main lane runs atp_eval; batch and serving workers
+// each own another, so their work overlaps on the device.
+struct Lane {
+    int id = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Pool pool;
+    StepHeader *h_hdr = nullptr;  // pinned
+    KernelTimer timer;
+};
+
+// Device-resident cached results and their bookkeeping (Sec. 3.3-3.4).
+struct CachePayload {
+    Buf rp, col, val, active;
+    int64_t rows = 0, cols = 0, nnz = 0, n_active = -1;
+    double bytes = 0;
+    hipEvent_t ready = nullptr;  // recorded on the producing stream after the data is written
+    ~CachePayload() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
+};
+using PayloadRef = std::shared_ptr<CachePayload>;  // an evicted payload lives on while a query uses it
+struct CacheItemInfo {
+    int node = -1;                    // Overlap Tree node, -1 if the string is not in the tree
+    std::vector<int32_t> types;       // the sub-metapath
+    std::vector<int32_t> rels;
+    std::vector<std::string> pos;     // constraint key of every position
+};
+struct CacheState {
+    std::mutex mu;  // every field below; lanes share the cache
+    int32_t policy = ATP_CACHE_OFF;
+    uint64_t budget = 0;
+    std::unique_ptr<OverlapTree> tree;
+    std::unique_ptr<CachePolicy> pol;
+    std::map<std::string, int64_t> item_by_key;
+    std::map<int64_t, CacheItemInfo> info;
+    std::map<int64_t, PayloadRef> payload;
+    atp_cache_stats stats{};
+};
+
+// Admission of per-multiplication slot reservations across lanes: a
+// reservation waits while it does not fit next to the ones held (one that
+// exceeds the budget alone proceeds when nothing else is held).  Each lane
+// holds at most one reservation at a time, so waiting cannot deadlock.
+struct MemGate {
+    std::mutex mu;
+    std::condition_variable cv;
+    uint64_t budget = 0;  // 0 = no admission control
+    uint64_t used = 0;
+    int held = 0;
+    bool acquire(uint64_t b) {  // false: no admission control, nothing held
+        std::unique_lock<std::mutex> lk(mu);
+        if (!budget) return false;
+        cv.wait(lk, [&] { return held == 0 || used + b <= budget; });
+        used += b;
+        ++held;
+        return true;
+    }
+    void release(uint64_t b) {
+        std::lock_guard<std::mutex> g(mu);
+        used -= b;
+        --held;
+        cv.notify_all();
+    }
+};
+struct GateHold {
+    MemGate *g;
+    uint64_t b;
+    bool counted;
+    GateHold(MemGate *g_, uint64_t b_) : g(g_), b(b_), counted(g_->acquire(b_)) {}
+    GateHold(const GateHold &) = delete;
+    GateHold &operator=(const GateHold &) = delete;
+    ~GateHold() {
+        if (counted) g->release(b);
+    }
+};
+
+struct Server;  // serve.cpp
+
+}  // namespace atp
+
+struct atp_ctx {
+    int device = 0;
+    uint32_t flags = 0;
+    atp::Lane main;  // its pool also holds the network
+    std::vector<std::unique_ptr<atp::Lane>> lanes;  // batch / serving lanes (created on demand)
+    std::vector<atp::NodeType> types;
+    std::vector<std::unique_ptr<atp::Rel>> rels;
+    std::vector<std::unique_ptr<atp::Prop>> props;
+    std::mutex stat_mu;  // planner statistics below, filled on first use
+    std::map<std::pair<int, int>, atp::JunctionSketch> sketches;
+    std::map<int, atp::ColumnHist> col_hists;
+    atp::CacheState cache;
+    std::mutex results_mu;
+    std::set<atp_result *> results;
+    std::atomic<bool> broken{false};
+    bool step_names = std::getenv("ATP_PROFILE_STEPS") != nullptr;  // diagnostics: kernel names per product
+    atp::Tuning tune = atp::tuning_from_env();
+    atp::MemGate gate;
+    atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
+    atp::KernelTimer *kt(atp::Lane *L) { return (flags & ATP_OPT_PROFILE) ? &L->timer : nullptr; }
+};
+
+struct atp_result {
+    atp_ctx *ctx;
+    hipStream_t stream;  // the lane stream that produced it
+    int64_t rows, cols, nnz;
+    atp::Buf rp, col, val;
+    atp_eval_stats stats;
+    std::string plan;
+};
+
+namespace atp {
+
+// One metapath query (Def. 2-3) as the C-ABI passes it.
+struct QueryRef {
+    const int32_t *types;
+    int32_t n_types;
+    const int32_t *rel_ids;
+    const atp_constraint *cons;
+    int32_t n_cons;
+};
+
+// Evaluate one query on lane L.  weight = number of submitted queries this
+// evaluation stands for (Overlap Tree frequencies of a fused batch).
+atp_status eval_query(atp_ctx *c, Lane *L, const QueryRef &q, const char *plan, int weight, atp_result **out);
+atp_status lane_init(atp_ctx *c, Lane *L, int id);
+void lane_destroy(Lane *L);
+void register_result(atp_ctx *c, atp_result *r);
+void server_shutdown(atp_ctx *c);
+
+}  // namespace atp

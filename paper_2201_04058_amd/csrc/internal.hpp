@@ -172,6 +172,14 @@ void launch_bits_count(const uint32_t *bits, int64_t words, int64_t *cnt, int64_
 void launch_bits_scatter(const uint32_t *bits, int64_t words, const int64_t *scan, int32_t *list, hipStream_t s,
                          KernelTimer *t);
 
+// rows ids (ascending, unique) of a CSR R into a CSR of the same shape:
+// cnt[rows] (zeroed) receives their lengths; after its exclusive scan orp,
+// the copy fills ocol/oval
+void launch_gather_count(const int64_t *rrp, const int32_t *ids, int64_t n, int64_t *cnt, hipStream_t s,
+                         KernelTimer *t);
+void launch_gather_copy(const int64_t *rrp, const int32_t *rcol, const uint64_t *rval, const int32_t *ids, int64_t n,
+                        const int64_t *orp, int32_t *ocol, uint64_t *oval, hipStream_t s, KernelTimer *t);
+
 // algorithmic-byte accounting: acc[5] = rows, left entries, result entries,
 // distinct right rows, their entries
 void launch_bin_stats(const int32_t *list, int64_t n, const Operand &X, const int32_t *cand, const int64_t *row_nnz,

@@ -1313,6 +1313,33 @@ __global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int6
 __global__ void k_copy_i64(const int64_t *src, int64_t *dst) { *dst = *src; }
 
 // ---------------------------------------------------------------------------
+// rows of a fused batch result handed to one member query
+
+// cnt[ids[z]] = length of row ids[z] of R (cnt zeroed; ids ascending, unique)
+__global__ void k_gather_count(const int64_t *rrp, const int32_t *ids, int64_t n, int64_t *cnt) {
+    for (int64_t z = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; z < n; z += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = ids[z];
+        cnt[i] = rrp[i + 1] - rrp[i];
+    }
+}
+
+// one wavefront per listed row: copy its entries to the member's row pointers
+__global__ __launch_bounds__(256) void k_gather_copy(const int64_t *rrp, const int32_t *rcol, const uint64_t *rval,
+                                                     const int32_t *ids, int64_t n, const int64_t *orp,
+                                                     int32_t *ocol, uint64_t *oval) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t z = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; z < n; z += nwaves) {
+        const int32_t i = ids[z];
+        const int64_t b = rrp[i], len = rrp[i + 1] - b, o = orp[i];
+        for (int64_t e = lane; e < len; e += 64) {
+            ocol[o + e] = rcol[b + e];
+            oval[o + e] = rval[b + e];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // row restriction of a right subtree: the columns that a left operand uses
 
 // bits |= columns of every stored entry of a product (all entries are live)
@@ -1375,17 +1402,23 @@ __global__ void k_bits_to_list(const uint32_t *bits, int64_t words, const int64_
 
 // acc[0] rows, acc[1] left-operand entries, acc[2] result entries; marks the
 // right-operand rows the bin reads.
-__global__ void k_bin_stats(const int32_t *list, int64_t n, Operand X, const int32_t *cand, const int64_t *row_nnz,
-                            uint32_t *ymark, unsigned long long *acc) {
+__global__ __launch_bounds__(256) void k_bin_stats(const int32_t *list, int64_t n, Operand X, const int32_t *cand,
+                                                    const int64_t *row_nnz, uint32_t *ymark, unsigned long long *acc) {
+    // one wavefront per row; its lanes stride over the row's entries
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long rows = 0, xent = 0, outn = 0;
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t r = wave; r < n; r += nwaves) {
         const int32_t c = list[r];
         const int64_t i = cand ? cand[c] : c;
         const int64_t xb = X.rp[i], xe = X.rp[i + 1];
-        rows += 1;
-        xent += (unsigned long long)(xe - xb);
-        outn += (unsigned long long)row_nnz[i];
-        for (int64_t p = xb; p < xe; ++p) {
+        if (lane == 0) {
+            rows += 1;
+            xent += (unsigned long long)(xe - xb);
+            outn += (unsigned long long)row_nnz[i];
+        }
+        for (int64_t p = xb + lane; p < xe; p += 64) {
             int32_t k = X.col[p];
             if (X.cmask && !bit_test(X.cmask, k)) continue;
             atomicOr(&ymark[k >> 5], 1u << (k & 31));
@@ -1586,7 +1619,7 @@ void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *f
 void launch_bin_stats(const int32_t *list, int64_t n, const Operand &X, const int32_t *cand, const int64_t *row_nnz,
                       uint32_t *ymark, int64_t *acc, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_bin_stats, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, list, n, X, cand, row_nnz, ymark,
+    hipLaunchKernelGGL(k_bin_stats, dim3(grid_for(n * 64, 256, 4096)), dim3(256), 0, s, list, n, X, cand, row_nnz, ymark,
                        (unsigned long long *)acc);
 }
 
@@ -1627,6 +1660,19 @@ void launch_bits_scatter(const uint32_t *bits, int64_t words, const int64_t *sca
 
 void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, scan_total, dst);
+}
+
+void launch_gather_count(const int64_t *rrp, const int32_t *ids, int64_t n, int64_t *cnt, hipStream_t s,
+                         KernelTimer *t) {
+    if (n <= 0) return;
+    ATP_LAUNCH("gather", 0, 0, s, k_gather_count, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, rrp, ids, n, cnt);
+}
+
+void launch_gather_copy(const int64_t *rrp, const int32_t *rcol, const uint64_t *rval, const int32_t *ids, int64_t n,
+                        const int64_t *orp, int32_t *ocol, uint64_t *oval, hipStream_t s, KernelTimer *t) {
+    if (n <= 0) return;
+    ATP_LAUNCH("gather", 0, 0, s, k_gather_copy, dim3(grid_for(n * 64, 256, 8192)), dim3(256), 0, s, rrp, rcol, rval,
+               ids, n, orp, ocol, oval);
 }
 
 }  // namespace atp

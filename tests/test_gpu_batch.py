@@ -1,0 +1,207 @@
+"""Batches and the serving loop (workloads of queries, Problem 2): every
+result is bit-identical to the same query evaluated alone, whatever the lanes,
+fusion, memory admission, cache and arrival order; fused chains that overflow
+fall back to one query at a time."""
+import numpy as np
+import pytest
+
+from synth import configs, workload
+from synth.hin import HIN, Constraint, Query, add_bipartite
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def atp():
+    import paper_2201_04058_amd as atp
+    atp.lib()
+    return atp
+
+
+@pytest.fixture(scope="module")
+def net():
+    hin, _ = configs.make_hin("scholarly", 0.01)
+    return hin
+
+
+def host(res):
+    rp, col, val = res.to_host()
+    return rp, col, val
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def mixed_queries(hin):
+    """Session queries (single start entity, fusable) and random walks with
+    their own start sets and windows."""
+    qs = workload.sessions(hin, 21, 40, ["A", "T"], restart_p=0.1, entities=6,
+                           type_predicates={"P": ("year", 2012, 32767)})
+    qs += workload.random_walk_batch(hin, 3, 24, lengths=(3, 6), start_sizes=(5, 200))
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(qs))
+    return [qs[i] for i in order]
+
+
+def alone_results(atp, hin, qs):
+    ctx = atp.Context(device=0)
+    ctx.load_hin(hin)
+    out = []
+    for q in qs:
+        r = ctx.eval_query(q)
+        out.append(host(r))
+        r.free()
+    ctx.close()
+    return out
+
+
+@pytest.fixture(scope="module")
+def mixed(atp, net):
+    qs = mixed_queries(net)
+    return qs, alone_results(atp, net, qs)
+
+
+@pytest.mark.parametrize("lanes,max_batch,budget", [(1, 1, 0), (1, 16, 0), (4, 16, 0), (4, 64, 1 << 20),
+                                                    (3, 4, 0)])
+def test_batch_equals_alone(atp, net, mixed, lanes, max_batch, budget):
+    qs, ref = mixed
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    res = ctx.eval_batch(qs, lanes=lanes, max_batch=max_batch, mem_budget_bytes=budget)
+    for z, (r, want) in enumerate(zip(res, ref)):
+        assert not isinstance(r, Exception), (z, r)
+        assert same(host(r), want), (z, qs[z].name)
+        if max_batch > 1 and z < 3:
+            assert r.stats()["n_products"] >= 1
+        r.free()
+    ctx.close()
+
+
+def test_batch_fuses_and_matches_oracle(atp, oracle_mod, net):
+    """Queries that differ only in their start set (overlapping ones too) run
+    as one chain; each gets exactly its own rows."""
+    rng = np.random.default_rng(5)
+    yr = ("year", 2010, 32767)
+    qs = []
+    for z in range(12):
+        ids = np.sort(rng.choice(net.counts["A"], size=int(rng.integers(1, 40)), replace=False)).astype(np.int32)
+        if z == 3:
+            ids = np.concatenate([qs[0].constraints[0].ids[:5], ids[:3]])
+            ids = np.unique(ids).astype(np.int32)
+        qs.append(Query("A-P-T-P-A", ["A", "P", "T", "P", "A"],
+                        [Constraint(0, "idset", ids=ids), Constraint(1, "range", prop=yr[0], lo=yr[1], hi=yr[2]),
+                         Constraint(3, "range", prop=yr[0], lo=yr[1], hi=yr[2])]))
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    res = ctx.eval_batch(qs, lanes=2, max_batch=16)
+    for q, r in zip(qs, res):
+        want = oracle_mod.eval_full(net, q)
+        got = host(r)
+        assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+        assert np.array_equal(got[2], want[2].astype(np.int64))
+    ctx.close()
+
+
+def test_empty_and_invalid_members(atp, net):
+    """An empty start set and a malformed query inside a batch."""
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    good = Query("A-P-A", ["A", "P", "A"], [Constraint(0, "idset", ids=np.array([1, 2, 3], np.int32))])
+    empty = Query("A-P-A", ["A", "P", "A"], [Constraint(0, "idset", ids=np.zeros(0, np.int32))])
+    bad = Query("A-P-A", ["A", "P", "A"], [Constraint(7, "idset", ids=np.array([1], np.int32))])
+    res = ctx.eval_batch([good, empty, bad, good], lanes=2, max_batch=8)
+    assert isinstance(res[2], atp.AtpError) and res[2].status == atp.ATP_EINVAL
+    rp, col, val = host(res[1])
+    assert rp[-1] == 0
+    assert same(host(res[0]), host(res[3]))
+    alone = ctx.eval_query(good)
+    assert same(host(res[0]), host(alone))
+    ctx.close()
+
+
+def _overflow_net():
+    """A: node 0 reaches all 2^16 B nodes, node 1 only B node 0; counts along
+    A-B-A-B-A-B-A-B-A from node 0 reach 2^64, from node 1 stay below 2^52."""
+    nb = 1 << 16
+    pairs = [(0, j) for j in range(nb)] + [(1, 0)]
+    src = np.array([p[0] for p in pairs], np.int64)
+    dst = np.array([p[1] for p in pairs], np.int64)
+    hin = HIN(counts={"A": 2, "B": nb})
+    add_bipartite(hin, "A", "B", src, dst)
+    return hin
+
+
+def test_fused_overflow_falls_back_to_each_query(atp):
+    hin = _overflow_net()
+    types = ["A", "B"] * 4 + ["A"]
+    q0 = Query("hub", types, [Constraint(0, "idset", ids=np.array([0], np.int32))])
+    q1 = Query("leaf", types, [Constraint(0, "idset", ids=np.array([1], np.int32))])
+    ctx = atp.Context(device=0)
+    ctx.load_hin(hin)
+    with pytest.raises(atp.AtpError) as e:
+        ctx.eval_query(q0)
+    assert e.value.status == atp.ATP_EOVERFLOW
+    alone = host(ctx.eval_query(q1))
+    res = ctx.eval_batch([q0, q1], lanes=1, max_batch=2)
+    assert isinstance(res[0], atp.AtpError) and res[0].status == atp.ATP_EOVERFLOW
+    assert same(host(res[1]), alone)
+    ctx.close()
+
+
+@pytest.mark.parametrize("cache", [False, True])
+def test_server_results_equal_alone(atp, net, mixed, cache):
+    """Continuous batching: requests submitted while others run are fused and
+    overlapped; each completion equals the query alone."""
+    qs, ref = mixed
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    if cache:
+        ctx.cache_configure(atp.ATP_CACHE_OTREE, 1 << 30)
+    ctx.server_start(lanes=4, max_batch=16, mem_budget_bytes=1 << 30)
+    for z, q in enumerate(qs):
+        ctx.submit(q, tag=z)
+    got = {}
+    while len(got) < len(qs):
+        for cp in ctx.poll(64, wait_ms=2000):
+            assert cp["tag"] not in got
+            got[cp["tag"]] = cp
+    assert ctx.server_pending() == 0
+    batches = []
+    for z, q in enumerate(qs):
+        cp = got[z]
+        assert cp["status"] == atp.ATP_OK, (z, cp["status"])
+        assert same(host(cp["result"]), ref[z]), (z, q.name)
+        assert cp["t_submit"] <= cp["t_start"] <= cp["t_done"]
+        batches.append(cp["batch"])
+        cp["result"].free()
+    assert max(batches) > 1  # queued requests were fused
+    ctx.server_stop()
+    with pytest.raises(atp.AtpError):
+        ctx.server_stop()
+    ctx.close()
+
+
+def test_server_submit_during_run_and_stop_drains(atp, net, mixed):
+    qs, ref = mixed
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    ctx.server_start(lanes=2, max_batch=8)
+    with pytest.raises(atp.AtpError) as e:
+        ctx.eval_batch(qs[:2])
+    assert e.value.status == atp.ATP_ESTATE
+    got = {}
+    for z, q in enumerate(qs[:20]):
+        ctx.submit(q, tag=z)
+        for cp in ctx.poll(64):
+            got[cp["tag"]] = cp
+    while len(got) < 20:
+        for cp in ctx.poll(64, wait_ms=2000):
+            got[cp["tag"]] = cp
+    for z in range(20):
+        assert same(host(got[z]["result"]), ref[z])
+    for z, q in enumerate(qs[20:30]):
+        ctx.submit(q, tag=100 + z)
+    ctx.server_stop()  # finishes the queue; unpolled completions are freed
+    assert ctx.server_pending() == 0
+    ctx.close()

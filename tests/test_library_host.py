@@ -58,6 +58,23 @@ def test_create_without_gpu_reports_state_or_succeeds(atp):
     assert e.value.status == atp.ATP_ESTATE
 
 
+def test_batch_and_server_reject_bad_arguments(atp):
+    """Argument checks of the batch / serving entry points (no context needed)."""
+    L = atp.lib()
+    n = 2
+    out = (ctypes.c_void_p * n)()
+    st = (ctypes.c_int32 * n)()
+    qs = (atp.atp_query * n)()
+    assert L.atp_eval_batch(None, qs, n, 1, 1, 0, out, st) == atp.ATP_EINVAL
+    assert L.atp_submit(None, ctypes.byref(qs[0]), 0) == atp.ATP_EINVAL
+    buf = (atp.atp_completion * 4)()
+    assert L.atp_poll(None, buf, 4, 0) == atp.ATP_EINVAL
+    o = atp.atp_server_options(4, 8, 0)
+    assert L.atp_server_start(None, ctypes.byref(o)) == atp.ATP_EINVAL
+    assert L.atp_server_stop(None) == atp.ATP_EINVAL
+    assert L.atp_server_pending(None) == 0
+
+
 def _parens(i, j):
     if i == j:
         yield str(i), 0
