@@ -88,6 +88,11 @@ def cpu_baseline(hin, queries, rows_per_query: int, threads: int) -> dict:
                       f"(of {len(ids)}), scaled by |start set| / sample"}
 
 
+# session workloads: entity types that sessions start from, type-level predicates
+SESSION_STARTS = {"scholarly": ["A", "V", "T"], "news": ["R", "O", "L"], "tiny": ["A", "T"]}
+SESSION_PREDICATES = {"scholarly": {"P": ("year", 2015, 32767)}, "news": {}, "tiny": {}}
+
+
 def workload_mode(args) -> int:
     """A session workload (Sec. 4.1 "Query Workloads": sessions on one entity,
     restart probability 0.08, metapaths of 3-5 types, shuffled) on the full
@@ -96,8 +101,8 @@ def workload_mode(args) -> int:
     from synth import configs, workload
 
     hin, _ = configs.load(args.workload)
-    starts = {"scholarly": ["A", "V", "T"], "news": ["R", "O", "L"], "tiny": ["A", "T"]}[args.workload]
-    preds = {"scholarly": {"P": ("year", 2015, 32767)}, "news": {}, "tiny": {}}[args.workload]
+    starts = SESSION_STARTS[args.workload]
+    preds = SESSION_PREDICATES[args.workload]
     qs = workload.sessions(hin, 4, args.queries, starts, restart_p=0.08, entities=100, type_predicates=preds)
     stream = None
     try:
@@ -139,6 +144,178 @@ def workload_mode(args) -> int:
     return 0
 
 
+def _ctx_with_network(atp, hin):
+    stream = None
+    try:
+        import torch
+        torch.cuda.init()
+        stream = atp.torch_stream_handle(0)
+    except Exception:
+        pass
+    ctx = atp.Context(device=0, stream=stream)
+    ctx.load_hin(hin)
+    return ctx
+
+
+def _pct(a, q):
+    return round(float(np.percentile(np.asarray(a), q)), 3) if len(a) else None
+
+
+def batch_mode(args) -> int:
+    """Random schema walks (start type uniform, next type uniform over schema
+    neighbours, 3-7 types, a seeded start set, a P-year / D-day window at every
+    position of that type), evaluated one at a time and as one batch on lanes
+    with fusion.  Both runs produce the same results (the batch tests check
+    this); here the result sizes are compared as a guard."""
+    import paper_2201_04058_amd as atp
+    from synth import configs, workload
+
+    hin, _ = configs.load(args.workload)
+    qs = workload.random_walk_batch(hin, 3, args.queries, start_sizes=(args.start_min, args.start_max))
+    ctx = _ctx_with_network(atp, hin)
+    for q in qs[:8]:
+        ctx.eval_query(q).free()
+    t0 = time.perf_counter()
+    plain_nnz, lat = [], []
+    for q in qs:
+        tq = time.perf_counter()
+        r = ctx.eval_query(q)
+        plain_nnz.append(r.shape()[2])
+        r.free()
+        lat.append((time.perf_counter() - tq) * 1e3)
+    t_plain = time.perf_counter() - t0
+    log(f"one at a time: {len(qs)} queries in {t_plain:.2f} s")
+    tuned = None
+    if args.autotune:  # on queries of another seed, not the measured ones
+        sample = workload.random_walk_batch(hin, 13, args.tune_queries, start_sizes=(args.start_min, args.start_max))
+        tuned = ctx.autotune(sample)
+        log(f"autotuned: {tuned}")
+    ctx.eval_batch(qs[:8], lanes=args.lanes, max_batch=args.max_batch)
+    t0 = time.perf_counter()
+    res = ctx.eval_batch(qs, lanes=args.lanes, max_batch=args.max_batch,
+                         mem_budget_bytes=int(args.admit_gb * (1 << 30)))
+    t_batch = time.perf_counter() - t0
+    bad = [z for z, r in enumerate(res) if isinstance(r, Exception) or r.shape()[2] != plain_nnz[z]]
+    for r in res:
+        if not isinstance(r, Exception):
+            r.free()
+    log(f"batch: {len(qs)} queries in {t_batch:.2f} s, mismatches {bad}")
+    ctx.close()
+    out = {"metric": "metapath queries/s (batch)", "value": round(len(qs) / t_batch, 3), "unit": "queries/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": args.workload + "-random-walks", "queries": len(qs), "lengths": [3, 7],
+                      "start_set": [args.start_min, args.start_max], "selectivity": [0.01, 0.20],
+                      "lanes": args.lanes, "max_batch": args.max_batch, "admit_gb": args.admit_gb},
+           "one_at_a_time": {"qps": round(len(qs) / t_plain, 3), "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99)},
+           "vs_one_at_a_time": round(t_plain / t_batch, 3), "result_mismatches": len(bad), "autotuned": tuned}
+    print(json.dumps(out), flush=True)
+    return 0 if not bad else 1
+
+
+def _serve(atp, ctx, arrivals, qs, lanes, max_batch, admit_bytes, cap_s):
+    """Open-loop replay: submit each query at its arrival time, poll
+    completions; latency = completion - scheduled arrival."""
+    import threading
+    ctx.server_start(lanes=lanes, max_batch=max_batch, mem_budget_bytes=admit_bytes)
+    n = len(qs)
+    done = {}
+    t_start = time.perf_counter()
+    submitted = [0]
+
+    def feeder():
+        for z in range(n):
+            wait = arrivals[z] - (time.perf_counter() - t_start)
+            if wait > 0:
+                time.sleep(wait)
+            if time.perf_counter() - t_start > cap_s:
+                break
+            ctx.submit(qs[z], tag=z)
+            submitted[0] = z + 1
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    next_log = time.perf_counter() + 10
+    while th.is_alive() or len(done) < submitted[0]:
+        for cp in ctx.poll(256, wait_ms=50):
+            r = cp["result"]
+            done[cp["tag"]] = (cp["status"], r.shape()[2] if r is not None else -1, cp["t_done"], cp["batch"])
+            if r is not None:
+                r.free()
+        if time.perf_counter() > next_log:
+            log(f"  {len(done)} of {submitted[0]} submitted done")
+            next_log += 10
+    th.join()
+    wall = time.perf_counter() - t_start
+    ctx.server_stop()
+    # the server clock starts at server_start, just before t_start
+    lat = [(done[z][2] - arrivals[z]) * 1e3 for z in done]
+    last = max(d[2] for d in done.values()) if done else 0.0
+    return {"completed": len(done), "submitted": submitted[0], "wall_s": round(wall, 3),
+            "qps": round(len(done) / max(last, 1e-9), 3),
+            "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "mean_ms": round(float(np.mean(lat)), 3),
+            "errors": sum(1 for d in done.values() if d[0] != 0),
+            "error_status": sorted({int(d[0]) for d in done.values() if d[0] != 0}),
+            "mean_batch": round(float(np.mean([d[3] for d in done.values()])), 3)}, done
+
+
+def serve_mode(args) -> int:
+    """An open-loop query stream (Poisson arrivals; base walks drawn Zipf(1.0)
+    over 500 seeded schema walks of 3-5 types, extended by 0-2-step prefix and
+    suffix; start sets and windows from finite seeded pools) served by the
+    plain path (one lane, no fusion, no cache) and by the batched + cached
+    server (lanes, fusion, Atrapos-OTree cache, slot-memory admission)."""
+    import paper_2201_04058_amd as atp
+    from synth import configs, workload
+
+    hin, _ = configs.load(args.workload)
+    if args.stream == "walks":
+        arrivals, qs = workload.serving_stream(hin, 4, args.queries, qps=args.qps,
+                                               start_sizes=(args.start_min, args.start_max), pool=args.pool)
+    else:  # session queries (one entity each), Poisson arrivals
+        qs = workload.sessions(hin, 4, args.queries, SESSION_STARTS[args.workload], restart_p=0.08, entities=100,
+                               type_predicates=SESSION_PREDICATES[args.workload])
+        gaps = np.random.default_rng(4).exponential(1.0 / args.qps, size=len(qs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+    ctx = _ctx_with_network(atp, hin)
+    for q in qs[:8]:
+        ctx.eval_query(q).free()
+    plain, dp = {"qps": 0.0, "p99_ms": None}, {}
+    if not args.no_plain:
+        log(f"plain path: {len(qs)} queries at {args.qps} QPS")
+        plain, dp = _serve(atp, ctx, arrivals, qs, 1, 1, 0, args.cap_s)
+        log(f"plain: {plain}")
+    tuned = None
+    if args.autotune:  # on a stream of another seed, not the measured one
+        _, sample = workload.serving_stream(hin, 5, args.tune_queries, start_sizes=(args.start_min, args.start_max),
+                                            pool=args.pool)
+        tuned = ctx.autotune(sample)
+        log(f"autotuned: {tuned}")
+    if args.cache_gb > 0:
+        ctx.cache_configure(atp.ATP_CACHE_OTREE, int(args.cache_gb * (1 << 30)))
+    log(f"served: lanes {args.lanes}, max batch {args.max_batch}, cache {args.cache_gb} GB")
+    served, ds = _serve(atp, ctx, arrivals, qs, args.lanes, args.max_batch, int(args.admit_gb * (1 << 30)),
+                        args.cap_s)
+    st = ctx.cache_stats()
+    served.update({"whole_hits": st["whole_hits"], "sub_hits": st["sub_hits"], "cache_queries": st["queries"],
+                   "hit_rate": round((st["whole_hits"] + st["sub_hits"]) / max(1, st["queries"]), 3),
+                   "whole_hit_rate": round(st["whole_hits"] / max(1, st["queries"]), 3)})
+    log(f"served: {served}")
+    ctx.close()
+    bad = [z for z in ds if z in dp and ds[z][1] != dp[z][1]]
+    out = {"metric": "metapath queries/s + p50/p99 latency (served stream)", "value": served["qps"],
+           "unit": "queries/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"{args.workload}-{args.stream}-stream", "queries": len(qs), "arrival_qps": args.qps,
+                      "start_set": [args.start_min, args.start_max], "lanes": args.lanes,
+                      "max_batch": args.max_batch, "cache_gb": args.cache_gb, "admit_gb": args.admit_gb,
+                      "pool": args.pool},
+           "served": served, "plain": plain,
+           "vs_plain_qps": round(served["qps"] / max(plain["qps"], 1e-9), 3),
+           "vs_plain_p99": round(plain["p99_ms"] / max(served["p99_ms"], 1e-9), 3) if plain["p99_ms"] else None,
+           "result_mismatches": len(bad), "autotuned": tuned}
+    print(json.dumps(out), flush=True)
+    return 0 if not bad else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,11 +325,25 @@ def main() -> int:
     ap.add_argument("--cpu-rows", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan-eac", action="store_true", help="paper's uniform E_ac planner")
-    ap.add_argument("--mode", default="plain", choices=["plain", "workload"],
+    ap.add_argument("--mode", default="plain", choices=["plain", "workload", "batch", "serve"],
                     help="plain: the workload's queries, one at a time; workload: a session query stream "
-                         "evaluated with each cache policy (Sec. 3.3-3.4) against the plain path")
-    ap.add_argument("--queries", type=int, default=500, help="workload mode: queries in the stream")
-    ap.add_argument("--cache-gb", type=float, default=4.0, help="workload mode: cache budget")
+                         "evaluated with each cache policy (Sec. 3.3-3.4) against the plain path; batch: random "
+                         "walks one at a time and as a batch; serve: an open-loop stream, plain path and server")
+    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--admit-gb", type=float, default=64.0, help="batch/serve: slot-memory admission budget")
+    ap.add_argument("--start-min", type=int, default=100)
+    ap.add_argument("--start-max", type=int, default=5000)
+    ap.add_argument("--qps", type=float, default=200.0, help="serve: arrival rate")
+    ap.add_argument("--cap-s", type=float, default=120.0, help="serve: stop submitting after this many seconds")
+    ap.add_argument("--pool", type=int, default=16, help="serve: start sets per type and windows in the pools")
+    ap.add_argument("--autotune", action="store_true", help="batch/serve: autotune the tunables first")
+    ap.add_argument("--tune-queries", type=int, default=24)
+    ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain-path run")
+    ap.add_argument("--stream", default="walks", choices=["walks", "sessions"],
+                    help="serve: extended schema walks with pooled constraints, or session queries")
+    ap.add_argument("--queries", type=int, default=500, help="workload/batch/serve: queries")
+    ap.add_argument("--cache-gb", type=float, default=4.0, help="workload/serve: cache budget")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +369,10 @@ def main() -> int:
 
     if args.mode == "workload":
         return workload_mode(args)
+    if args.mode == "batch":
+        return batch_mode(args)
+    if args.mode == "serve":
+        return serve_mode(args)
 
     t0 = time.perf_counter()
     hin, queries = configs.load(args.workload)

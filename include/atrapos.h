@@ -183,10 +183,12 @@ atp_status atp_result_free(atp_result *res);
  *   ATP_CACHE_LRU    same insertion, LRU replacement;
  *   ATP_CACHE_CBS1   LRU of final query results only (Sec. 4.1 baseline CBS1);
  *   ATP_CACHE_CBS2   LRU of every intermediate result (baseline CBS2).
- * Items larger than 80% of the budget are never cached (Sec. 4.1).  Sub-chain
- * results are always computed on all rows while a cache is configured (as if
- * ATP_OPT_NO_RESTRICT were set) so a cached result is the full sub-metapath
- * result.  Results are identical with and without a cache. */
+ * Items larger than 80% of the budget are never cached (Sec. 4.1).  Only
+ * full sub-metapath results are kept: a right sub-chain is restricted to the
+ * rows its left neighbour reaches (and then not cached) unless its type string
+ * already occurred in an earlier query (Overlap-Tree frequency >= 2), in which
+ * case it is computed on all rows and becomes a cache candidate.  Results are
+ * identical with and without a cache. */
 enum { ATP_CACHE_OFF = 0, ATP_CACHE_OTREE = 1, ATP_CACHE_PGDS = 2, ATP_CACHE_LRU = 3, ATP_CACHE_CBS1 = 4,
        ATP_CACHE_CBS2 = 5 };
 
@@ -280,6 +282,45 @@ int32_t atp_server_pending(atp_ctx *ctx);
 /* Finish every queued request, stop the workers; completions not yet polled
  * are freed.  ATP_ESTATE if no server runs. */
 atp_status atp_server_stop(atp_ctx *ctx);
+
+/* --- kernel tunables and the autotuner ---------------------------------------
+ *
+ * Thresholds of the row binning and the numeric kernels.  They change which
+ * kernel handles a row and how its work is split, never a result.
+ *   part_target    expected products per part of a sparse row spanning several
+ *                  column tiles (parts group consecutive tiles), >= 1
+ *   part_hash_cap  a part with at most this many products uses an LDS hash
+ *                  instead of a dense tile, 0..2048
+ *   task_ops       target products per dense task, >= 1
+ *   bucket_pct     a row with more than 512 left entries whose entries x column
+ *                  tiles x 100 exceed bucket_pct x its products is bucketed by
+ *                  column tile (products materialised once) instead of searched
+ *                  per tile, >= 0
+ *   split_ops      products per (row, tile) beyond which a dense row's left
+ *                  entries are split over several workgroups, >= 1024 */
+typedef struct {
+    int64_t part_target;
+    int64_t part_hash_cap;
+    int64_t task_ops;
+    int64_t bucket_pct;
+    int64_t split_ops;
+} atp_tuning;
+atp_status atp_get_tuning(const atp_ctx *ctx, atp_tuning *t);
+/* Between queries (not while a server or batch runs).  ATP_EINVAL if a value
+ * is out of its range. */
+atp_status atp_set_tuning(atp_ctx *ctx, const atp_tuning *t);
+
+/* Pick the tunables for a workload: coordinate descent over a fixed grid of
+ * each tunable (bucket_pct, part_target, task_ops, split_ops, part_hash_cap),
+ * `rounds` passes, timing the n sample queries end to end on the context's
+ * stream (best of two runs per setting).  The fastest setting found is kept
+ * in the context and written to *chosen; *ms_before / *ms_after receive the
+ * sample's time with the starting and the chosen setting (either may be
+ * NULL).  ATP_ESTATE while a cache is configured or a server runs (cached
+ * results would hide the kernels).  A query that fails stops the search with
+ * its status, the starting setting restored. */
+atp_status atp_autotune(atp_ctx *ctx, const atp_query *sample, int32_t n, int32_t rounds, atp_tuning *chosen,
+                        double *ms_before, double *ms_after);
 
 /* --- Overlap Tree and cache policy as standalone host objects (no GPU) ---- */
 

@@ -28,7 +28,9 @@ EXPORTS = [
     "atp_device_bytes", "atp_status_str", "atp_cache_configure", "atp_cache_get_stats", "atp_otree_create",
     "atp_otree_destroy", "atp_otree_insert", "atp_otree_frequency", "atp_otree_shape", "atp_cache_simulate",
     "atp_eval_batch", "atp_server_start", "atp_submit", "atp_poll", "atp_server_pending", "atp_server_stop",
+    "atp_get_tuning", "atp_set_tuning", "atp_autotune",
 ]
+TUNABLES = ("part_target", "part_hash_cap", "task_ops", "bucket_pct", "split_ops")
 ATP_CACHE_OFF, ATP_CACHE_OTREE, ATP_CACHE_PGDS, ATP_CACHE_LRU, ATP_CACHE_CBS1, ATP_CACHE_CBS2 = 0, 1, 2, 3, 4, 5
 
 
@@ -88,6 +90,10 @@ class atp_completion(ctypes.Structure):
                 ("lane", ctypes.c_int32)]
 
 
+class atp_tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in TUNABLES]
+
+
 class atp_eval_stats(ctypes.Structure):
     _fields_ = [("n_products", ctypes.c_int32),
                 ("n_op_total", ctypes.c_int64),
@@ -143,6 +149,9 @@ def lib() -> ctypes.CDLL:
         "atp_poll": ([vp, vp, i32, i32], i32),
         "atp_server_pending": ([vp], i32),
         "atp_server_stop": ([vp], i32),
+        "atp_get_tuning": ([vp, P(atp_tuning)], i32),
+        "atp_set_tuning": ([vp, P(atp_tuning)], i32),
+        "atp_autotune": ([vp, vp, i32, i32, P(atp_tuning), P(ctypes.c_double), P(ctypes.c_double)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -436,6 +445,36 @@ class Context:
             out.append({"tag": c.tag, "status": c.status, "result": Result(self, c.result) if c.result else None,
                         "t_submit": c.t_submit, "t_start": c.t_start, "t_done": c.t_done,
                         "batch": c.batch_size, "lane": c.lane})
+        return out
+
+    # --- kernel tunables ---------------------------------------------------
+    def tuning(self) -> dict:
+        t = atp_tuning()
+        _check(lib().atp_get_tuning(self._h, ctypes.byref(t)), "atp_get_tuning")
+        return {n: getattr(t, n) for n in TUNABLES}
+
+    def set_tuning(self, **kw) -> None:
+        cur = self.tuning()
+        cur.update(kw)
+        t = atp_tuning(*[int(cur[n]) for n in TUNABLES])
+        _check(lib().atp_set_tuning(self._h, ctypes.byref(t)), "atp_set_tuning")
+
+    def autotune(self, sample, rounds: int = 1) -> dict:
+        """Coordinate-descent search of the tunables on a sample of queries;
+        keeps the fastest setting.  Returns it with the sample's ms before/after."""
+        n = len(sample)
+        qs = (atp_query * max(1, n))()
+        keep = []
+        for i, q in enumerate(sample):
+            qs[i], k = self._query(q)
+            keep.append(k)
+        t = atp_tuning()
+        b, a = ctypes.c_double(), ctypes.c_double()
+        _check(lib().atp_autotune(self._h, qs, n, rounds, ctypes.byref(t), ctypes.byref(b), ctypes.byref(a)),
+               "atp_autotune")
+        del keep
+        out = {n_: getattr(t, n_) for n_ in TUNABLES}
+        out.update({"ms_before": b.value, "ms_after": a.value})
         return out
 
     def server_pending(self) -> int:

@@ -36,7 +36,7 @@ Tuning atp::tuning_from_env() {
     get("ATP_PART_TARGET", t.part_target);
     get("ATP_PART_HASH_CAP", t.part_hash_cap);
     get("ATP_TASK_OPS", t.task_ops);
-    get("ATP_BUCKET_RATIO", t.bucket_ratio);
+    get("ATP_BUCKET_PCT", t.bucket_pct);
     get("ATP_SPLIT_OPS", t.split_ops);
     if (t.split_ops < 1024) t.split_ops = 1024;
     int dev = 0, cus = 0;
@@ -486,6 +486,7 @@ std::vector<int64_t> cache_subtree(const CacheState &cs, int64_t q) {
 struct KeptMat {
     int lo, hi;
     double cost;
+    bool partial;  // computed on a subset of its rows (row restriction): not a cacheable result
     Mat m;
 };
 
@@ -514,10 +515,12 @@ atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std
     std::vector<Cand> cands;
     cands.push_back(Cand{0, p - 1, root_cost, const_cast<Mat *>(&R), true});
     if (cs.policy == ATP_CACHE_CBS2) {
-        for (auto &k : kept) cands.push_back(Cand{k.lo, k.hi, k.cost, &k.m, false});
+        for (auto &k : kept)
+            if (!k.partial) cands.push_back(Cand{k.lo, k.hi, k.cost, &k.m, false});
     } else if (cs.policy != ATP_CACHE_CBS1) {
         KeptMat *best = nullptr;
         for (auto &k : kept) {
+            if (k.partial) continue;
             const int node = cs.tree->find(std::vector<int32_t>(types + k.lo, types + k.hi + 2));
             if (node < 0 || cs.tree->node(node).leaf()) continue;
             if (!best || (k.hi - k.lo) > (best->hi - best->lo)) best = &k;
@@ -696,6 +699,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     std::vector<std::string> pkeys;
     std::vector<std::vector<int64_t>> cached_item(p, std::vector<int64_t>(p, -1));
     std::map<int64_t, PayloadRef> pins;  // cached results this query may read
+    std::vector<std::vector<int64_t>> freq(p, std::vector<int64_t>(p, 0));  // Overlap Tree f of each sub-chain
     std::vector<ChainStats> cached_stats_store(p * p);
     std::vector<std::vector<const ChainStats *>> cached_stats(p, std::vector<const ChainStats *>(p, nullptr));
     auto sub_types = [&](int a, int b) { return std::vector<int32_t>(types + a, types + b + 2); };
@@ -711,6 +715,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
                 const std::string key = item_key(st_, sub_rels(a, b), sub_pos(a, b));
                 const int node = cs.tree->find(st_);
                 if (node >= 0) cs.tree->node(node).keys[key].f += weight;
+                freq[a][b] = cs.tree->frequency(st_);
                 auto it = cs.item_by_key.find(key);
                 if (it == cs.item_by_key.end()) continue;
                 if (node >= 0) cs.tree->node(node).keys[key].item = it->second;
@@ -788,7 +793,14 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     bool overflow = false;
     std::vector<PlanTree> &tree = forced;
     std::vector<Buf> keep;  // restriction buffers, alive until the query ends
-    const bool restrict_rows = (c->flags & ATP_OPT_NO_RESTRICT) == 0 && !caching;
+    const bool restrict_rows = (c->flags & ATP_OPT_NO_RESTRICT) == 0;
+    // leaves covered by a plan node
+    std::function<std::pair<int, int>(int)> span = [&](int v) -> std::pair<int, int> {
+        const PlanTree &nd = tree[v];
+        if (nd.leaf >= 0) return {nd.leaf, nd.leaf};
+        if (nd.block_lo >= 0) return {nd.block_lo, nd.block_hi};
+        return {span(nd.left).first, span(nd.right).second};
+    };
     // Rows of a right sub-chain that can matter: the columns its left neighbour uses.
     struct Restriction {
         const uint32_t *bits = nullptr;
@@ -882,7 +894,11 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         const Restriction *rp = nullptr;
         const int64_t y_rows = c->types[types[l1 + 1]].count;
         const bool x_small = X.leaf ? (X.cand != nullptr && X.n_cand < y_rows) : (X.nnz < y_rows / 2);
-        if (restrict_rows && x_small) {
+        // with a cache, a right sub-chain that is an overlap (seen in an earlier
+        // query) is computed on all its rows so that its result can be kept
+        const std::pair<int, int> ysp = span(nd.right);
+        const bool keep_whole = caching && ysp.second > ysp.first && freq[ysp.first][ysp.second] >= 2;
+        if (restrict_rows && x_small && !keep_whole) {
             TRY(make_restriction(X, y_rows, r2));
             rp = &r2;
         }
@@ -900,8 +916,8 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         ++n_products;
         if (v == forced_root && sat) overflow = true;
         if (caching) {  // keep computed operands for the insertion policy
-            if (!X.leaf && !X.view) kept.push_back(KeptMat{l0, l1, cx, std::move(X)});
-            if (!Y.leaf && !Y.view) kept.push_back(KeptMat{r0, r1, cy, std::move(Y)});
+            if (!X.leaf && !X.view) kept.push_back(KeptMat{l0, l1, cx, rs != nullptr, std::move(X)});
+            if (!Y.leaf && !Y.view) kept.push_back(KeptMat{r0, r1, cy, rp != nullptr, std::move(Y)});
         }
         return ATP_OK;
     };
@@ -996,8 +1012,14 @@ atp_status eval_query(atp_ctx *c, Lane *L, const QueryRef &q, const char *plan, 
     return eval_impl(c, L, q.types, q.n_types, q.rel_ids, q.cons, q.n_cons, plan, weight < 1 ? 1 : weight, out);
 }
 
+void release_pool_caches(atp_ctx *c) {
+    c->main.pool.release_cache();
+    for (auto &ln : c->lanes) ln->pool.release_cache();
+}
+
 atp_status lane_init(atp_ctx *c, Lane *L, int id) {
     L->id = id;
+    L->pool.on_oom = [c]() { release_pool_caches(c); };
     L->pool.budget = c->main.pool.budget;
     L->pool.user_alloc = c->main.pool.user_alloc;
     L->pool.user_free = c->main.pool.user_free;
@@ -1066,6 +1088,7 @@ atp_status atp_create(const atp_options *o, atp_ctx **out) {
     c->main.pool.user_free = d.free;
     c->main.pool.user = d.alloc_user;
     c->main.pool.budget = d.mem_budget_bytes;
+    c->main.pool.on_oom = [c]() { release_pool_caches(c); };
     if (hipHostMalloc((void **)&c->main.h_hdr, sizeof(StepHeader), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
@@ -1364,6 +1387,101 @@ atp_status atp_cache_get_stats(const atp_ctx *c, atp_cache_stats *st) {
     st->bytes = cs.pol ? (int64_t)cs.pol->used() : 0;
     st->otree_nodes = cs.tree ? cs.tree->size() : 0;
     st->otree_leaves = cs.tree ? cs.tree->leaves() : 0;
+    return ATP_OK;
+}
+
+// ---- tunables and the autotuner ----
+
+static atp_tuning to_abi(const Tuning &t) {
+    return atp_tuning{t.part_target, t.part_hash_cap, t.task_ops, t.bucket_pct, t.split_ops};
+}
+
+atp_status atp_get_tuning(const atp_ctx *c, atp_tuning *t) {
+    if (!c || !t) return ATP_EINVAL;
+    *t = to_abi(c->tune);
+    return ATP_OK;
+}
+
+atp_status atp_set_tuning(atp_ctx *c, const atp_tuning *t) {
+    if (!c || !t) return ATP_EINVAL;
+    if (t->part_target < 1 || t->part_hash_cap < 0 || t->part_hash_cap > 2048 || t->task_ops < 1 ||
+        t->bucket_pct < 0 || t->split_ops < 1024)
+        return ATP_EINVAL;
+    c->tune.part_target = t->part_target;
+    c->tune.part_hash_cap = t->part_hash_cap;
+    c->tune.task_ops = t->task_ops;
+    c->tune.bucket_pct = t->bucket_pct;
+    c->tune.split_ops = t->split_ops;
+    return ATP_OK;
+}
+
+atp_status atp_autotune(atp_ctx *c, const atp_query *sample, int32_t n, int32_t rounds, atp_tuning *chosen,
+                        double *ms_before, double *ms_after) {
+    if (!c || n < 1 || !sample || rounds < 1) return ATP_EINVAL;
+    if (c->server) return ATP_ESTATE;
+    {
+        std::lock_guard<std::mutex> g(c->cache.mu);
+        if (c->cache.policy != ATP_CACHE_OFF) return ATP_ESTATE;
+    }
+    (void)hipSetDevice(c->device);
+    const Tuning start = c->tune;
+    // wall time of the sample (best of two), every query synchronised
+    auto run = [&](double &ms) -> atp_status {
+        ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int32_t i = 0; i < n; ++i) {
+                const atp_query &q = sample[i];
+                atp_result *r = nullptr;
+                atp_status st = eval_impl(c, &c->main, q.types, q.n_types, q.rel_ids, q.cons, q.n_cons, nullptr, 1, &r);
+                if (st != ATP_OK) return st;
+                atp_result_free(r);
+            }
+            ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        return ATP_OK;
+    };
+    struct Knob {
+        int64_t Tuning::*field;
+        std::vector<int64_t> grid;
+    };
+    const std::vector<Knob> knobs = {
+        {&Tuning::bucket_pct, {25, 50, 100, 200, 400, 800}},
+        {&Tuning::part_target, {300, 600, 1200, 2400}},
+        {&Tuning::task_ops, {8192, 16384, 32768, 65536}},
+        {&Tuning::split_ops, {16384, 65536, 262144}},
+        {&Tuning::part_hash_cap, {512, 1024, 2048}},
+    };
+    double best = 0;
+    atp_status st = run(best);  // also warms the pool and the planner statistics
+    if (st == ATP_OK) st = run(best);
+    if (st != ATP_OK) {
+        c->tune = start;
+        return st;
+    }
+    const double before = best;
+    for (int r = 0; r < rounds; ++r)
+        for (const Knob &k : knobs) {
+            const int64_t keep = c->tune.*(k.field);
+            int64_t arg = keep;
+            for (int64_t v : k.grid) {
+                if (v == keep) continue;
+                c->tune.*(k.field) = v;
+                double ms = 0;
+                if ((st = run(ms)) != ATP_OK) {
+                    c->tune = start;
+                    return st;
+                }
+                if (ms < best) {
+                    best = ms;
+                    arg = v;
+                }
+            }
+            c->tune.*(k.field) = arg;
+        }
+    if (chosen) *chosen = to_abi(c->tune);
+    if (ms_before) *ms_before = before;
+    if (ms_after) *ms_after = best;
     return ATP_OK;
 }
 

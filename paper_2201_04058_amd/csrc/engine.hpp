@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <condition_variable>
+#include <functional>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -93,7 +94,16 @@ struct Pool {
         }
         cache.clear();
     }
+    std::function<void()> on_oom;  // frees the cached blocks of every pool of the context
     atp_status alloc(size_t bytes, void **out) {
+        atp_status st = alloc_once(bytes, out);
+        if (st == ATP_ENOMEM && on_oom) {  // other lanes may hold the memory in their caches
+            on_oom();
+            st = alloc_once(bytes, out);
+        }
+        return st;
+    }
+    atp_status alloc_once(size_t bytes, void **out) {
         std::lock_guard<std::recursive_mutex> g(mu);
         *out = nullptr;
         if (bytes == 0) bytes = 1;
@@ -362,6 +372,7 @@ atp_status eval_query(atp_ctx *c, Lane *L, const QueryRef &q, const char *plan, 
 atp_status lane_init(atp_ctx *c, Lane *L, int id);
 void lane_destroy(Lane *L);
 void register_result(atp_ctx *c, atp_result *r);
+void release_pool_caches(atp_ctx *c);
 void server_shutdown(atp_ctx *c);
 
 }  // namespace atp

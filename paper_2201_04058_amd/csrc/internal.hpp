@@ -52,7 +52,7 @@ struct Tuning {
     int64_t part_target = kPartTarget;
     int64_t part_hash_cap = kPartHashCap;
     int64_t task_ops = kTaskOps;
-    int64_t bucket_ratio = 4;  // bucket a row when left entries x tiles > ratio x products
+    int64_t bucket_pct = 400;  // bucket a row when left entries x tiles x 100 > pct x products
     int64_t split_ops = kSplitOps;
     int64_t wg_slots = 512;    // resident dense workgroups (2 per compute unit)
 };

@@ -96,7 +96,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // lanes per X entry: power of two near the average Y-row length, in [1, 64]
-__device__ __forceinline__ int group_size(int64_t avg) {
+__host__ __device__ inline int group_size(int64_t avg) {
     int g = 1;
     while (g < 64 && (int64_t)g * 2 <= avg + (avg >> 1)) g <<= 1;
     return g;
@@ -356,7 +356,7 @@ __global__ void k_bin_rows(SymbolicArgs a) {
             if (ntiles > 1 && ntiles <= kMaxBucketTiles) {
                 const int64_t i = a.cand ? a.cand[c] : c;
                 const int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
-                if (xlen > kCursorCap && xlen * ntiles > a.tune.bucket_ratio * nop) bin = BIN_BUCKET;
+                if (xlen > kCursorCap && xlen * ntiles * 100 > a.tune.bucket_pct * nop) bin = BIN_BUCKET;
             }
         } else {
             nseg = 1;
@@ -1125,7 +1125,8 @@ __device__ __forceinline__ void bucket_chunk(const int64_t *chunk_base, int64_t 
     *q = id - chunk_base[lo];
 }
 
-// Products of X entries [e0, e1) of row i; f(tile, col, value) for each.
+// Products of X entries [e0, e1) of one row, eight lanes per X entry (short
+// right rows); f(tile, col, value) for each.
 template <typename F>
 __device__ __forceinline__ void for_products(const Operand &X, const Operand &Y, int64_t e0, int64_t e1, F f) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1145,6 +1146,69 @@ __device__ __forceinline__ void for_products(const Operand &X, const Operand &Y,
     }
 }
 
+// Runs of one lane group: consecutive active lanes whose products fall into
+// the same column tile (the lanes of a group read consecutive entries of one
+// sorted right-operand row, so a row's products in one tile are adjacent).
+// Every lane of the group calls it together.
+struct TileRun {
+    bool head;      // first lane of its run
+    int head_lane;  // wavefront lane of the run's head
+    int len;        // lanes in the run (valid at the head)
+    int rank;       // position within the run
+};
+
+__device__ __forceinline__ TileRun tile_run(bool act, int32_t tile, int lane, int g) {
+    const int li = lane & (g - 1);
+    const int gbase = lane - li;
+    const uint64_t gmask = (g == 64 ? ~0ull : ((1ull << g) - 1)) << gbase;
+    const int key = act ? tile : -1 - lane;  // an inactive lane matches no neighbour
+    const int prev = __shfl_up(key, 1, g);
+    const bool head = act && (li == 0 || prev != key);
+    const uint64_t hm = __ballot(head) & gmask;
+    const uint64_t bound = hm | (~__ballot(act) & gmask);
+    TileRun r;
+    r.head = head;
+    const uint64_t upto = (2ull << lane) - 1;  // lanes 0..lane (all lanes when lane = 63)
+    r.head_lane = (act && (hm & upto)) ? 63 - __builtin_clzll(hm & upto) : lane;
+    const uint64_t above = bound & ~((2ull << r.head_lane) - 1);
+    const int end = above ? __builtin_ctzll(above) : gbase + g;
+    r.len = end - r.head_lane;
+    r.rank = lane - r.head_lane;
+    return r;
+}
+
+// Products of X entries [e0, e1) of one row, one X entry per group of g lanes
+// (g a power of two); the group walks the right row in steps of g entries so
+// that its lanes stay together.  f(act, tile, col, value, run) is called by
+// every lane of the group in every step; act = the lane holds a product.
+template <typename F>
+__device__ __forceinline__ void for_product_runs(const Operand &X, const Operand &Y, int64_t e0, int64_t e1, int g,
+                                                 F f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per_wave = 64 / g;
+    const int gid = wave * per_wave + lane / g, ng = (blockDim.x / 64) * per_wave, li = lane & (g - 1);
+    for (int64_t e = e0 + gid; e < e1; e += ng) {  // uniform within the group
+        const int32_t k = X.col[e];
+        if (X.cmask && !bit_test(X.cmask, k)) continue;
+        const uint64_t xv = X.val ? X.val[e] : 1ull;
+        const int64_t yb = Y.rp[k], ye = Y.rp[k + 1];
+        for (int64_t base = yb; base < ye; base += g) {
+            const int64_t fpos = base + li;
+            bool act = fpos < ye;
+            const int32_t j = act ? Y.col[fpos] : 0;
+            if (act && Y.cmask) act = bit_test(Y.cmask, j);
+            const uint64_t v = act ? (Y.val ? sat_mul(xv, Y.val[fpos]) : xv) : 0ull;
+            const int32_t tile = j >> kTileShift;
+            const TileRun r = tile_run(act, tile, lane, g);
+            f(act, tile, j, v, r);
+        }
+    }
+}
+
+// right rows of at least this many lanes' worth of entries are walked in
+// tile runs (one LDS atomic per run); shorter rows one product per lane
+constexpr int kRunMinLanes = 16;
+
 struct BucketArgs {
     const int32_t *list;        // bucket rows (candidate indices)
     int64_t n_list;
@@ -1156,6 +1220,7 @@ struct BucketArgs {
     int64_t *tile_off;          // [n_list * (ntiles + 1)] absolute bucket offsets
     int32_t *prod_col;
     uint64_t *prod_val;
+    int g;                      // lanes per left entry (power of two <= 64)
 };
 
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, NumericArgs a) {
@@ -1169,7 +1234,12 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, N
         const int64_t e0 = xb + q * kBucketChunk, e1 = e0 + kBucketChunk < xe ? e0 + kBucketChunk : xe;
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
         __syncthreads();
-        for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+        if (b.g >= kRunMinLanes)
+            for_product_runs(a.X, a.Y, e0, e1, b.g, [&](bool, int32_t tile, int32_t, uint64_t, const TileRun &r) {
+                if (r.head) atomicAdd(&hist[tile], r.len);
+            });
+        else
+            for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
         __syncthreads();
         int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x)
@@ -1213,7 +1283,12 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
         const int64_t e0 = xb + q * kBucketChunk, e1 = e0 + kBucketChunk < xe ? e0 + kBucketChunk : xe;
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
         __syncthreads();
-        for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+        if (b.g >= kRunMinLanes)
+            for_product_runs(a.X, a.Y, e0, e1, b.g, [&](bool, int32_t tile, int32_t, uint64_t, const TileRun &r) {
+                if (r.head) atomicAdd(&hist[tile], r.len);
+            });
+        else
+            for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
         __syncthreads();
         int64_t *cur = b.tile_cnt + p * (b.ntiles + 1);
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
@@ -1223,11 +1298,24 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
         }
         __syncthreads();
         const bool valued = b.prod_val != nullptr;
-        for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t j, uint64_t v) {
-            int64_t pos = base[tile] + atomicAdd(&hist[tile], 1);
-            b.prod_col[pos] = j;
-            if (valued) b.prod_val[pos] = v;
-        });
+        if (b.g >= kRunMinLanes)
+            for_product_runs(a.X, a.Y, e0, e1, b.g,
+                             [&](bool act, int32_t tile, int32_t j, uint64_t v, const TileRun &r) {
+                int32_t at = 0;
+                if (r.head) at = atomicAdd(&hist[tile], r.len);
+                at = __shfl(at, r.head_lane);  // the run's lanes take consecutive positions
+                if (act) {
+                    const int64_t pos = base[tile] + at + r.rank;
+                    b.prod_col[pos] = j;
+                    if (valued) b.prod_val[pos] = v;
+                }
+            });
+        else
+            for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t j, uint64_t v) {
+                const int64_t pos = base[tile] + atomicAdd(&hist[tile], 1);
+                b.prod_col[pos] = j;
+                if (valued) b.prod_val[pos] = v;
+            });
         __syncthreads();
     }
 }
@@ -1582,7 +1670,9 @@ void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *c
                            int32_t *prod_col, uint64_t *prod_val, const NumericArgs &a, hipStream_t s,
                            KernelTimer *t) {
     if (n_list <= 0 || n_chunks <= 0) return;
-    BucketArgs b{list, n_list, chunk_base, n_chunks, prod_base, ntiles, tile_cnt, tile_off, prod_col, prod_val};
+    const int64_t yavg = a.Y.rows > 0 ? a.Y.nnz / a.Y.rows : 1;
+    BucketArgs b{list, n_list, chunk_base, n_chunks, prod_base, ntiles, tile_cnt, tile_off, prod_col, prod_val,
+                 group_size(yavg)};
     const int cus = device_cus();
     const int64_t gc = n_chunks < (int64_t)cus * 4 ? n_chunks : (int64_t)cus * 4;
     ATP_LAUNCH("bucket", 0, 0, s, k_bucket_count, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);

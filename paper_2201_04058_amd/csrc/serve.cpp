@@ -255,6 +255,56 @@ void run_group(atp_ctx *c, Lane *L, std::vector<Member *> &g) {
     atp_result_free(R);
 }
 
+// Lanes run groups concurrently; a group whose queries ran out of device
+// memory next to the others is re-run alone once every other lane is idle.
+struct LaneGate {
+    std::mutex mu;
+    std::condition_variable cv;
+    int running = 0;
+    bool exclusive = false;
+    void enter() {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return !exclusive; });
+        ++running;
+    }
+    void leave() {
+        std::lock_guard<std::mutex> lk(mu);
+        --running;
+        cv.notify_all();
+    }
+    void enter_exclusive() {  // called without holding a shared entry
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return !exclusive; });
+        exclusive = true;
+        cv.wait(lk, [&] { return running == 0; });
+    }
+    void leave_exclusive() {
+        std::lock_guard<std::mutex> lk(mu);
+        exclusive = false;
+        cv.notify_all();
+    }
+};
+
+bool out_of_memory(atp_status st) { return st == ATP_ENOMEM || st == ATP_EBUDGET; }
+
+void run_group_gated(atp_ctx *c, Lane *L, std::vector<Member *> &g, LaneGate &gate, int lanes) {
+    gate.enter();
+    run_group(c, L, g);
+    gate.leave();
+    if (lanes < 2) return;
+    bool again = false;
+    for (Member *m : g) again |= out_of_memory(m->st);
+    if (!again) return;
+    gate.enter_exclusive();
+    release_pool_caches(c);
+    for (Member *m : g)
+        if (out_of_memory(m->st)) {
+            m->batch = 1;
+            m->st = eval_query(c, L, m->q, nullptr, 1, &m->res);
+        }
+    gate.leave_exclusive();
+}
+
 // Fusion groups of at most max_batch members, in order of first appearance.
 std::vector<std::vector<Member *>> make_groups(const std::vector<Member *> &ms, int max_batch) {
     std::vector<std::vector<Member *>> groups;
@@ -305,6 +355,8 @@ struct Server {
     int running = 0;  // requests taken by workers and not yet completed
     bool stopping = false;
     int max_batch = 1;
+    int lanes = 1;
+    LaneGate gate;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 };
 
@@ -335,7 +387,7 @@ void worker(atp_ctx *c, Lane *L) {
         const double t_start = now_s(sv.t0);
         std::vector<Member *> g;
         for (auto &r : batch) g.push_back(&r->m);
-        run_group(c, L, g);
+        run_group_gated(c, L, g, sv.gate, sv.lanes);
         const double t_done = now_s(sv.t0);
         {
             std::lock_guard<std::mutex> lk(sv.mu);
@@ -407,11 +459,12 @@ atp_status atp_eval_batch(atp_ctx *c, const atp_query *queries, int32_t n, int32
         c->gate.budget = mem_budget_bytes;
     }
     std::atomic<size_t> next{0};
+    LaneGate gate;
+    const int nl = std::min<int>(lanes, (int)std::max<size_t>(groups.size(), 1));
     auto drain = [&](Lane *L) {
         (void)hipSetDevice(c->device);
-        for (size_t gi; (gi = next.fetch_add(1)) < groups.size();) run_group(c, L, groups[gi]);
+        for (size_t gi; (gi = next.fetch_add(1)) < groups.size();) run_group_gated(c, L, groups[gi], gate, nl);
     };
-    const int nl = std::min<int>(lanes, (int)std::max<size_t>(groups.size(), 1));
     std::vector<std::thread> th;
     for (int l = 1; l < nl; ++l) th.emplace_back(drain, c->lanes[l].get());
     drain(c->lanes[0].get());
@@ -439,6 +492,7 @@ atp_status atp_server_start(atp_ctx *c, const atp_server_options *o) {
     }
     c->server = new Server();
     c->server->max_batch = o->max_batch;
+    c->server->lanes = o->lanes;
     for (int l = 0; l < o->lanes; ++l) c->server->workers.emplace_back(worker, c, c->lanes[l].get());
     return ATP_OK;
 }

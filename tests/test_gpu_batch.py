@@ -205,3 +205,35 @@ def test_server_submit_during_run_and_stop_drains(atp, net, mixed):
     ctx.server_stop()  # finishes the queue; unpolled completions are freed
     assert ctx.server_pending() == 0
     ctx.close()
+
+
+def test_tuning_get_set_and_autotune(atp, net, mixed):
+    """Tunables change kernels, never results; the autotuner keeps a setting
+    from its grid and refuses to run with a cache configured."""
+    qs, ref = mixed
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    t0 = ctx.tuning()
+    assert t0["bucket_pct"] == 400 and t0["part_hash_cap"] == 2048
+    for bad in ({"part_target": 0}, {"part_hash_cap": 4096}, {"bucket_pct": -1}, {"split_ops": 10}):
+        with pytest.raises(atp.AtpError) as e:
+            ctx.set_tuning(**bad)
+        assert e.value.status == atp.ATP_EINVAL
+    assert ctx.tuning() == t0
+    ctx.set_tuning(bucket_pct=0, part_target=64, split_ops=1024, task_ops=1)
+    for q, want in zip(qs[:20], ref[:20]):
+        assert same(host(ctx.eval_query(q)), want)
+    ctx.set_tuning(**t0)
+    got = ctx.autotune(qs[:10], rounds=1)
+    assert got["bucket_pct"] in (25, 50, 100, 200, 400, 800)
+    assert got["part_target"] in (300, 600, 1200, 2400)
+    assert got["part_hash_cap"] in (512, 1024, 2048)
+    assert got["ms_after"] <= got["ms_before"] * 1.0001
+    assert {k: ctx.tuning()[k] for k in atp.TUNABLES} == {k: got[k] for k in atp.TUNABLES}
+    for q, want in zip(qs, ref):
+        assert same(host(ctx.eval_query(q)), want)
+    ctx.cache_configure(atp.ATP_CACHE_OTREE, 1 << 30)
+    with pytest.raises(atp.AtpError) as e:
+        ctx.autotune(qs[:2])
+    assert e.value.status == atp.ATP_ESTATE
+    ctx.close()

@@ -73,6 +73,10 @@ def test_batch_and_server_reject_bad_arguments(atp):
     assert L.atp_server_start(None, ctypes.byref(o)) == atp.ATP_EINVAL
     assert L.atp_server_stop(None) == atp.ATP_EINVAL
     assert L.atp_server_pending(None) == 0
+    t = atp.atp_tuning()
+    assert L.atp_get_tuning(None, ctypes.byref(t)) == atp.ATP_EINVAL
+    assert L.atp_set_tuning(None, ctypes.byref(t)) == atp.ATP_EINVAL
+    assert L.atp_autotune(None, qs, n, 1, None, None, None) == atp.ATP_EINVAL
 
 
 def _parens(i, j):
