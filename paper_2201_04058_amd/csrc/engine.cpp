@@ -230,6 +230,8 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     st.slots += h1.slots_total;
     if (h1.slots_total == 0) return finish_empty();
 
+    // the numeric phase of a heavy product runs alone across lanes
+    ProductHold alone(&c->products, h1.n_op_total > c->heavy_ops);
     // admission: reserve the slot arrays (and the split accumulators) against the lanes' budget
     const int64_t ntiles_y = (Y.cols + kTileW - 1) / kTileW;
     GateHold hold(&c->gate, 12ull * (uint64_t)h1.slots_total +
@@ -1102,6 +1104,15 @@ atp_status atp_destroy(atp_ctx *c) {
     if (!c) return ATP_EINVAL;
     (void)hipSetDevice(c->device);
     server_shutdown(c);
+    if (std::getenv("ATP_POOL_STATS")) {  // diagnostics: runtime allocations per lane
+        std::fprintf(stderr, "pool main: %lld mallocs %.3f s, %lld frees %.3f s, held %.2f GB\n",
+                     (long long)c->main.pool.n_malloc, c->main.pool.malloc_s, (long long)c->main.pool.n_free,
+                     c->main.pool.free_s, c->main.pool.held / 1e9);
+        for (auto &ln : c->lanes)
+            std::fprintf(stderr, "pool lane %d: %lld mallocs %.3f s, %lld frees %.3f s, held %.2f GB\n", ln->id,
+                         (long long)ln->pool.n_malloc, ln->pool.malloc_s, (long long)ln->pool.n_free, ln->pool.free_s,
+                         ln->pool.held / 1e9);
+    }
     (void)hipStreamSynchronize(c->main.stream);
     for (auto &ln : c->lanes) (void)hipStreamSynchronize(ln->stream);
     for (atp_result *r : c->results) delete r;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <functional>
 #include <cstdint>
@@ -77,6 +78,10 @@ struct Pool {
     std::multimap<size_t, void *> cache;
     std::map<void *, size_t> live;
     std::recursive_mutex mu;  // lanes release each other's buffers (cache eviction, results)
+    size_t cached = 0;                // bytes of free blocks in `cache`
+    size_t cache_limit = (size_t)16 << 30;
+    int64_t n_malloc = 0, n_free = 0;  // runtime allocations and frees (diagnostics)
+    double malloc_s = 0, free_s = 0;
 
     static size_t round(size_t n) {
         if (n < 256) return 256;
@@ -88,11 +93,15 @@ struct Pool {
     }
     void release_cache() {
         std::lock_guard<std::recursive_mutex> g(mu);
+        const auto t0 = std::chrono::steady_clock::now();
         for (auto &kv : cache) {
             (void)hipFree(kv.second);
             held -= (int64_t)kv.first;
+            n_free += 1;
         }
         cache.clear();
+        cached = 0;
+        free_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     std::function<void()> on_oom;  // frees the cached blocks of every pool of the context
     atp_status alloc(size_t bytes, void **out) {
@@ -122,6 +131,7 @@ struct Pool {
             void *p = it->second;
             size_t sz = it->first;
             cache.erase(it);
+            cached -= sz;
             live[p] = sz;
             *out = p;
             return ATP_OK;
@@ -131,6 +141,7 @@ struct Pool {
             if ((uint64_t)(held + n) > budget) return ATP_EBUDGET;
         }
         void *p = nullptr;
+        const auto t0 = std::chrono::steady_clock::now();
         if (hipMalloc(&p, n) != hipSuccess) {
             (void)hipGetLastError();
             release_cache();
@@ -139,6 +150,8 @@ struct Pool {
                 return ATP_ENOMEM;
             }
         }
+        n_malloc += 1;
+        malloc_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         held += (int64_t)n;
         live[p] = n;
         *out = p;
@@ -157,6 +170,16 @@ struct Pool {
             return;
         }
         cache.emplace(n, p);
+        cached += n;
+        // keep at most cache_limit bytes of free blocks: drop the largest first
+        while (cached > cache_limit && !cache.empty()) {
+            auto last = std::prev(cache.end());
+            (void)hipFree(last->second);
+            held -= (int64_t)last->first;
+            cached -= last->first;
+            n_free += 1;
+            cache.erase(last);
+        }
     }
     void destroy() {
         std::lock_guard<std::recursive_mutex> g(mu);
@@ -320,6 +343,44 @@ struct GateHold {
     }
 };
 
+// Products of different lanes overlap, except that a heavy product runs
+// alone: concurrent work evicts the right operand it re-reads from the
+// caches.  Writer-preferring shared/exclusive gate, held for one product.
+struct ProductGate {
+    std::mutex mu;
+    std::condition_variable cv;
+    int shared = 0, waiting = 0;
+    bool exclusive = false;
+    void lock(bool excl) {
+        std::unique_lock<std::mutex> lk(mu);
+        if (excl) {
+            ++waiting;
+            cv.wait(lk, [&] { return !exclusive && shared == 0; });
+            --waiting;
+            exclusive = true;
+        } else {
+            cv.wait(lk, [&] { return !exclusive && waiting == 0; });
+            ++shared;
+        }
+    }
+    void unlock(bool excl) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (excl)
+            exclusive = false;
+        else
+            --shared;
+        cv.notify_all();
+    }
+};
+struct ProductHold {
+    ProductGate *g;
+    bool excl;
+    ProductHold(ProductGate *g_, bool e) : g(g_), excl(e) { g->lock(excl); }
+    ProductHold(const ProductHold &) = delete;
+    ProductHold &operator=(const ProductHold &) = delete;
+    ~ProductHold() { g->unlock(excl); }
+};
+
 struct Server;  // serve.cpp
 
 }  // namespace atp
@@ -342,6 +403,8 @@ struct atp_ctx {
     bool step_names = std::getenv("ATP_PROFILE_STEPS") != nullptr;  // diagnostics: kernel names per product
     atp::Tuning tune = atp::tuning_from_env();
     atp::MemGate gate;
+    atp::ProductGate products;     // a product above heavy_ops products runs alone across lanes
+    int64_t heavy_ops = 64ll << 20;
     atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
     atp::KernelTimer *kt(atp::Lane *L) { return (flags & ATP_OPT_PROFILE) ? &L->timer : nullptr; }
 };
