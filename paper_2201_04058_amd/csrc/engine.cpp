@@ -183,14 +183,11 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     TRY(bucket_nop.alloc(pool, 8 * n_cand));
     TRY(chunk_base.alloc(pool, 8 * (n_cand + 1)));
     TRY(prod_base.alloc(pool, 8 * (n_cand + 1)));
-    const int64_t tmp_n = std::max(scan_tmp_elems(n_cand), scan_tmp_elems(Z.rows));
+    const int64_t tmp_n = std::max(5 * scan_tmp_elems(n_cand), scan_tmp_elems(Z.rows));
     TRY(tmp.alloc(pool, 8 * tmp_n));
 
     StepHeader *d_hdr = hdr.as<StepHeader>();
     launch_fill_i64((int64_t *)d_hdr, sizeof(StepHeader) / 8, 0, s, t);
-    launch_fill_i64(dense_chunks.as<int64_t>(), n_cand, 0, s, t);
-    launch_fill_i64(bucket_chunks.as<int64_t>(), n_cand, 0, s, t);
-    launch_fill_i64(bucket_nop.as<int64_t>(), n_cand, 0, s, t);
 
     SymbolicArgs sa;
     sa.X = X.op;
@@ -214,16 +211,12 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     sa.tune = c->tune;
     launch_symbolic(sa, s, t);
     launch_bin_rows(sa, s, t);
-    launch_scan_i64(ub.as<int64_t>(), slot_off.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
-    launch_set_header_from_scan(slot_off.as<int64_t>() + n_cand, &d_hdr->slots_total, s);
-    launch_scan_i64(nseg.as<int64_t>(), seg_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
-    launch_set_header_from_scan(seg_base.as<int64_t>() + n_cand, &d_hdr->segs_total, s);
-    launch_scan_i64(dense_chunks.as<int64_t>(), task_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
-    launch_set_header_from_scan(task_base.as<int64_t>() + n_cand, &d_hdr->dense_tasks, s);
-    launch_scan_i64(bucket_chunks.as<int64_t>(), chunk_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
-    launch_set_header_from_scan(chunk_base.as<int64_t>() + n_cand, &d_hdr->bucket_chunks, s);
-    launch_scan_i64(bucket_nop.as<int64_t>(), prod_base.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
-    launch_set_header_from_scan(prod_base.as<int64_t>() + n_cand, &d_hdr->bucket_products, s);
+    const ScanJob jobs[5] = {{ub.as<int64_t>(), slot_off.as<int64_t>(), &d_hdr->slots_total},
+                             {nseg.as<int64_t>(), seg_base.as<int64_t>(), &d_hdr->segs_total},
+                             {dense_chunks.as<int64_t>(), task_base.as<int64_t>(), &d_hdr->dense_tasks},
+                             {bucket_chunks.as<int64_t>(), chunk_base.as<int64_t>(), &d_hdr->bucket_chunks},
+                             {bucket_nop.as<int64_t>(), prod_base.as<int64_t>(), &d_hdr->bucket_products}};
+    launch_scan_multi(jobs, 5, n_cand, tmp.as<int64_t>(), s, t);
     TRY(read_header(L, d_hdr));
     const StepHeader h1 = *L->h_hdr;
     st.n_op += h1.n_op_total;
@@ -304,8 +297,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
                                                        row_nnz.as<int64_t>()));
 
     // row pointers over every row of X; segment destinations in (row, tile) order
-    launch_scan_i64(row_nnz.as<int64_t>(), Z.rp.as<int64_t>(), Z.rows, tmp.as<int64_t>(), s, t);
-    launch_set_header_from_scan(Z.rp.as<int64_t>() + Z.rows, &d_hdr->nnz_total, s);
+    launch_scan_i64(row_nnz.as<int64_t>(), Z.rp.as<int64_t>(), Z.rows, tmp.as<int64_t>(), s, t, &d_hdr->nnz_total);
     Buf tmp_seg;
     TRY(tmp_seg.alloc(pool, 8 * (size_t)scan_tmp_elems(h1.segs_total)));
     launch_scan_i64(seg_cnt.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total, tmp_seg.as<int64_t>(), s, t);
@@ -314,8 +306,8 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         TRY(flags.alloc(pool, 8 * n_cand));
         TRY(flags_scan.alloc(pool, 8 * (n_cand + 1)));
         launch_active_flags(cand, n_cand, row_nnz.as<int64_t>(), flags.as<int64_t>(), s, t);
-        launch_scan_i64(flags.as<int64_t>(), flags_scan.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t);
-        launch_set_header_from_scan(flags_scan.as<int64_t>() + n_cand, &d_hdr->n_active, s);
+        launch_scan_i64(flags.as<int64_t>(), flags_scan.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t,
+                        &d_hdr->n_active);
     }
     TRY(read_header(L, d_hdr));
     const StepHeader h2 = *L->h_hdr;

@@ -82,11 +82,22 @@ void timer_end(KernelTimer *t, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s, KernelTimer *t);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s, KernelTimer *t);
 
-// exclusive scan of n int64 values; out has n+1 entries (out[n] = total);
-// tmp must hold scan_tmp_elems(n) int64.
+// exclusive scan of n int64 values; out has n+1 entries (out[n] = total,
+// also stored to *total when given); tmp must hold scan_tmp_elems(n) int64.
 int64_t scan_tmp_elems(int64_t n);
 void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s,
-                     KernelTimer *t);
+                     KernelTimer *t, int64_t *total = nullptr);
+// up to kMaxScanJobs scans of the same length in one launch sequence; tmp
+// holds n_jobs * scan_tmp_elems(n) int64.  Arrays of at most
+// kSmallScanTiles * 2048 elements take a single launch.
+constexpr int kMaxScanJobs = 8;
+constexpr int64_t kSmallScanTiles = 8;
+struct ScanJob {
+    const int64_t *in;
+    int64_t *out;
+    int64_t *total;  // optional
+};
+void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t);
 
 // masks
 void launch_mask_range(const void *prop, int32_t dtype, int64_t n, int64_t lo, int64_t hi,

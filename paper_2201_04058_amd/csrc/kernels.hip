@@ -182,58 +182,91 @@ __device__ int64_t block_inclusive_scan(int64_t x, int64_t *smem_waves, int64_t 
     return v + pre;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int64_t *in, int64_t n, int64_t *tmp) {
+// Several scans of the same length in one launch sequence: job = blockIdx.y.
+struct ScanJobs {
+    ScanJob job[kMaxScanJobs];
+    int64_t n;
+    int64_t stride;  // tmp entries per job
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(ScanJobs sj, int64_t *tmp) {
     __shared__ int64_t sw[kScanThreads / 64];
+    const int64_t *in = sj.job[blockIdx.y].in;
+    int64_t *t = tmp + blockIdx.y * sj.stride;
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     int64_t s = 0;
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-        if (i < n) s += in[i];
+        if (i < sj.n) s += in[i];
     }
     int64_t tot;
     block_inclusive_scan(s, sw, &tot);
-    if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
+    if (threadIdx.x == 0) t[blockIdx.x] = tot;
 }
 
-// exclusive scan of tmp[0..nb) in place, tmp[nb] = total; one block
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *tmp, int64_t nb) {
+// exclusive scan of tmp[0..nb) in place, tmp[nb] = total; one block per job
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *tmp, int64_t nb, int64_t stride) {
     __shared__ int64_t sw[kScanThreads / 64];
+    int64_t *t = tmp + blockIdx.x * stride;
     int64_t carry = 0;
     for (int64_t base = 0; base < nb; base += kScanThreads) {
         int64_t i = base + threadIdx.x;
-        int64_t x = i < nb ? tmp[i] : 0;
+        int64_t x = i < nb ? t[i] : 0;
         int64_t tot;
         int64_t inc = block_inclusive_scan(x, sw, &tot);
-        if (i < nb) tmp[i] = carry + inc - x;
+        if (i < nb) t[i] = carry + inc - x;
         carry += tot;
     }
-    if (threadIdx.x == 0) tmp[nb] = carry;
+    if (threadIdx.x == 0) t[nb] = carry;
 }
 
-// per block: exclusive scan of its tile with offset tmp[block]
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int64_t *in, int64_t *out, int64_t n,
-                                                             const int64_t *tmp, int64_t nb) {
-    __shared__ int64_t sw[kScanThreads / 64];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+// one tile [base, base + kScanTile) of job j with offset `carry`; returns the tile sum
+__device__ __forceinline__ int64_t scan_tile(const ScanJob &j, int64_t n, int64_t tile_base, int64_t carry,
+                                             int64_t *sw) {
+    const int64_t base = tile_base + (int64_t)threadIdx.x * kScanItems;
     int64_t x[kScanItems];
     int64_t s = 0;
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         int64_t i = base + r;
-        x[r] = i < n ? in[i] : 0;
+        x[r] = i < n ? j.in[i] : 0;
         s += x[r];
     }
     int64_t tot;
     int64_t inc = block_inclusive_scan(s, sw, &tot);
-    int64_t run = tmp[blockIdx.x] + inc - s;
+    int64_t run = carry + inc - s;
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         int64_t i = base + r;
-        if (i < n) out[i] = run;
+        if (i < n) j.out[i] = run;
         run += x[r];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tmp[nb];
+    return tot;
+}
+
+// per block: exclusive scan of its tile with offset tmp[block]
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(ScanJobs sj, const int64_t *tmp, int64_t nb) {
+    __shared__ int64_t sw[kScanThreads / 64];
+    const ScanJob &j = sj.job[blockIdx.y];
+    const int64_t *t = tmp + blockIdx.y * sj.stride;
+    scan_tile(j, sj.n, (int64_t)blockIdx.x * kScanTile, t[blockIdx.x], sw);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        j.out[sj.n] = t[nb];
+        if (j.total) *j.total = t[nb];
+    }
+}
+
+// short arrays: one block per job walks its tiles with a running carry
+__global__ __launch_bounds__(kScanThreads) void k_scan_small(ScanJobs sj) {
+    __shared__ int64_t sw[kScanThreads / 64];
+    const ScanJob &j = sj.job[blockIdx.x];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < sj.n; base += kScanTile) carry += scan_tile(j, sj.n, base, carry, sw);
+    if (threadIdx.x == 0) {
+        j.out[sj.n] = carry;
+        if (j.total) *j.total = carry;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -300,6 +333,10 @@ __global__ void k_symbolic(SymbolicArgs a) {
         }
         a.nop[c] = nop;
         a.long_len[c] = deferred;  // chunks left to the long-row pass
+        // per-bin-list-position counts that the binning fills sparsely (scanned over all n_cand)
+        a.dense_chunks[c] = 0;
+        a.bucket_chunks[c] = 0;
+        a.bucket_nop[c] = 0;
     }
     int64_t wsum = nop;
     for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
@@ -1575,13 +1612,28 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s, KernelTi
 
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 2; }
 
-void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t) {
-    int64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (nb < 1) nb = 1;
-    ATP_LAUNCH("scan", 0, 0, s, k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, tmp);
-    ATP_LAUNCH("scan", 0, 0, s, k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb);
-    ATP_LAUNCH("scan", 0, 0, s, k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t) {
+    if (n_jobs < 1 || n_jobs > kMaxScanJobs || n < 0) return;
+    ScanJobs sj{};
+    for (int z = 0; z < n_jobs; ++z) sj.job[z] = jobs[z];
+    sj.n = n;
+    sj.stride = scan_tmp_elems(n);
+    const int64_t nb = std::max<int64_t>((n + kScanTile - 1) / kScanTile, 1);
+    if (nb <= kSmallScanTiles) {
+        ATP_LAUNCH("scan", 0, 0, s, k_scan_small, dim3((unsigned)n_jobs), dim3(kScanThreads), 0, s, sj);
+        return;
+    }
+    ATP_LAUNCH("scan", 0, 0, s, k_scan_reduce, dim3((unsigned)nb, (unsigned)n_jobs), dim3(kScanThreads), 0, s, sj,
+               tmp);
+    ATP_LAUNCH("scan", 0, 0, s, k_scan_top, dim3((unsigned)n_jobs), dim3(kScanThreads), 0, s, tmp, nb, sj.stride);
+    ATP_LAUNCH("scan", 0, 0, s, k_scan_down, dim3((unsigned)nb, (unsigned)n_jobs), dim3(kScanThreads), 0, s, sj,
                (const int64_t *)tmp, nb);
+}
+
+void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t,
+                     int64_t *total) {
+    const ScanJob j{in, out, total};
+    launch_scan_multi(&j, 1, n, tmp, s, t);
 }
 
 void launch_mask_range(const void *prop, int32_t dtype, int64_t n, int64_t lo, int64_t hi, uint32_t *bits,

@@ -133,8 +133,7 @@ atp_status gather_member(atp_ctx *c, Lane *L, const atp_result &R, const Buf &d_
     TRY(out->rp.alloc(&L->pool, 8 * (size_t)(R.rows + 1)));
     launch_fill_i64(cnt.as<int64_t>(), R.rows, 0, s, t);
     launch_gather_count(R.rp.as<int64_t>(), d_ids.as<int32_t>(), n_ids, cnt.as<int64_t>(), s, t);
-    launch_scan_i64(cnt.as<int64_t>(), out->rp.as<int64_t>(), R.rows, tmp.as<int64_t>(), s, t);
-    launch_set_header_from_scan(out->rp.as<int64_t>() + R.rows, d_total, s);
+    launch_scan_i64(cnt.as<int64_t>(), out->rp.as<int64_t>(), R.rows, tmp.as<int64_t>(), s, t, d_total);
     return ATP_OK;
 }
 
