@@ -85,6 +85,8 @@ struct PosMask {
     Buf ids;                // sorted unique ids of an id-set constraint (smallest set)
     int64_t n_ids = -1;
     std::vector<int32_t> h_ids;
+    std::vector<std::vector<int32_t>> staged;  // host sources of asynchronous copies
+    std::vector<Buf> spent;                    // device id lists of the other id sets
 };
 
 struct StepStats {
@@ -355,10 +357,8 @@ atp_status build_mask(atp_ctx *c, Lane *L, int pos_type, const atp_constraint *c
             ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
             Buf d_ids;
             TRY(d_ids.alloc(pool, 4 * std::max<size_t>(ids.size(), 1)));
-            if (!ids.empty()) {
+            if (!ids.empty())  // the host copy lives in m.staged until the query ends
                 HIPTRY(hipMemcpyAsync(d_ids.p, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, s));
-                HIPTRY(hipStreamSynchronize(s));  // `ids` is released at the end of this scope
-            }
             if (first) {
                 launch_fill_u32(m.bits.as<uint32_t>(), words, 0u, s, t);
                 launch_mask_ids(d_ids.as<int32_t>(), (int64_t)ids.size(), m.bits.as<uint32_t>(), s, t);
@@ -368,13 +368,16 @@ atp_status build_mask(atp_ctx *c, Lane *L, int pos_type, const atp_constraint *c
                 launch_fill_u32(tmpb.as<uint32_t>(), words, 0u, s, t);
                 launch_mask_ids(d_ids.as<int32_t>(), (int64_t)ids.size(), tmpb.as<uint32_t>(), s, t);
                 launch_mask_and(m.bits.as<uint32_t>(), tmpb.as<uint32_t>(), words, s, t);
-                HIPTRY(hipStreamSynchronize(s));  // tmpb returns to the pool
+                // tmpb returns to this lane's pool; its reuse is ordered after these launches
             }
             if (m.n_ids < 0 || (int64_t)ids.size() < m.n_ids) {
                 m.n_ids = (int64_t)ids.size();
                 m.h_ids = ids;
                 m.ids = std::move(d_ids);
+            } else {
+                m.spent.push_back(std::move(d_ids));  // the mask kernel may still read it
             }
+            m.staged.push_back(std::move(ids));
         }
         first = false;
     }
@@ -630,22 +633,53 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
 
     hipStream_t s = L->stream;
     KernelTimer *t = c->kt(L);
-    // masks M_1..M_n (Def. 3)
+    // masks M_1..M_n (Def. 3).  Their popcounts (planner selectivities) come
+    // from the id count of a lone id-set constraint, from a memo of range
+    // constraints seen before, or from the device (one readback)
+    const std::vector<std::string> mkeys = position_keys(n_types, cons, n_cons);
+    std::vector<int> n_at(n_types, 0), ranges_at(n_types, 0);
+    for (int q = 0; q < n_cons; ++q) {
+        n_at[cons[q].position] += 1;
+        ranges_at[cons[q].position] += cons[q].kind == ATP_C_RANGE;
+    }
     std::vector<PosMask> masks(n_types);
     Buf pops;
     TRY(pops.alloc(&L->pool, 8 * n_types));
-    launch_fill_i64(pops.as<int64_t>(), n_types, 0, s, t);
+    std::vector<std::string> memo_key(n_types);
+    bool readback = false;
     for (int i = 0; i < n_types; ++i) {
         TRY(build_mask(c, L, types[i], cons, n_cons, i, masks[i]));
-        if (masks[i].pop >= 0)
-            launch_popcount(masks[i].bits.as<uint32_t>(), (c->types[types[i]].count + 31) / 32,
-                            pops.as<int64_t>() + i, s, t);
+        if (masks[i].pop < 0) continue;
+        if (n_at[i] == 1 && ranges_at[i] == 0) {
+            masks[i].pop = masks[i].n_ids;
+            continue;
+        }
+        memo_key[i] = std::to_string(types[i]) + "|" + mkeys[i];
+        {
+            std::lock_guard<std::mutex> g(c->stat_mu);
+            auto it = c->pop_memo.find(memo_key[i]);
+            if (it != c->pop_memo.end()) {
+                masks[i].pop = it->second;
+                memo_key[i].clear();
+                continue;
+            }
+        }
+        if (!readback) launch_fill_i64(pops.as<int64_t>(), n_types, 0, s, t);
+        readback = true;
+        launch_popcount(masks[i].bits.as<uint32_t>(), (c->types[types[i]].count + 31) / 32, pops.as<int64_t>() + i,
+                        s, t);
     }
-    std::vector<int64_t> h_pop(n_types, 0);
-    HIPTRY(hipMemcpyAsync(h_pop.data(), pops.p, 8 * n_types, hipMemcpyDeviceToHost, s));
-    TRY(sync(L));
-    for (int i = 0; i < n_types; ++i)
-        if (masks[i].pop >= 0) masks[i].pop = h_pop[i];
+    if (readback) {
+        std::vector<int64_t> h_pop(n_types, 0);
+        HIPTRY(hipMemcpyAsync(h_pop.data(), pops.p, 8 * n_types, hipMemcpyDeviceToHost, s));
+        TRY(sync(L));
+        std::lock_guard<std::mutex> g(c->stat_mu);
+        for (int i = 0; i < n_types; ++i)
+            if (!memo_key[i].empty()) {
+                masks[i].pop = h_pop[i];
+                c->pop_memo[memo_key[i]] = h_pop[i];
+            }
+    }
     auto sel_of = [&](int i) {
         const double n = (double)c->types[types[i]].count;
         return masks[i].pop >= 0 ? (n > 0 ? masks[i].pop / n : 0.0) : 1.0;

@@ -396,6 +396,7 @@ struct atp_ctx {
     std::mutex stat_mu;  // planner statistics below, filled on first use
     std::map<std::pair<int, int>, atp::JunctionSketch> sketches;
     std::map<int, atp::ColumnHist> col_hists;
+    std::map<std::string, int64_t> pop_memo;  // mask popcount by (type, position constraint key)
     atp::CacheState cache;
     std::mutex results_mu;
     std::set<atp_result *> results;
