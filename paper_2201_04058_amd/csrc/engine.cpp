@@ -243,7 +243,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     launch_fill_i64(row_cursor.as<int64_t>(), n_cand, 0, s, t);
     launch_fill_i64(row_nnz.as<int64_t>(), Z.rows, 0, s, t);
 
-    NumericArgs na;
+    NumericArgs na{};
     na.X = X.op;
     na.Y = Y.op;
     na.cand = cand;
@@ -276,6 +276,18 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     }
     for (int b = BIN_W64; b <= BIN_B8192; ++b)
         launch_numeric_hash(b, bin_lists.as<int32_t>() + (int64_t)b * n_cand, h1.bin_count[b], na, s, t);
+    Buf ytile;
+    na.ytile = nullptr;
+    if (h1.bin_count[BIN_DENSE] > 0) {
+        // segment bounds from a per-row tile index instead of searches, when it is small enough
+        const int64_t ntiles = (Y.cols + kTileW - 1) / kTileW;
+        const int64_t entries = (Y.rows) * (ntiles + 1);
+        if (ntiles > 1 && entries <= c->tile_index_cap && Y.nnz < ((int64_t)1 << 31)) {
+            TRY(ytile.alloc(pool, 4 * (size_t)entries));
+            launch_tile_index(Y.op, ntiles, ytile.as<int32_t>(), s, t);
+            na.ytile = ytile.as<int32_t>();
+        }
+    }
     if (h1.bin_count[BIN_DENSE] > 0)
         launch_numeric_dense(bin_lists.as<int32_t>() + (int64_t)BIN_DENSE * n_cand, h1.bin_count[BIN_DENSE],
                              task_base.as<int64_t>(), h1.dense_tasks, na, s, t);

@@ -406,6 +406,8 @@ struct atp_ctx {
     atp::MemGate gate;
     atp::ProductGate products;     // a product above heavy_ops products runs alone across lanes
     int64_t heavy_ops = 64ll << 20;
+    int64_t tile_index_cap = std::getenv("ATP_TILE_INDEX_CAP") ? std::atoll(std::getenv("ATP_TILE_INDEX_CAP"))
+                                                               : (int64_t)256 << 20;  // entries (4 B each)
     atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
     atp::KernelTimer *kt(atp::Lane *L) { return (flags & ATP_OPT_PROFILE) ? &L->timer : nullptr; }
 };

@@ -149,6 +149,7 @@ struct NumericArgs {
     unsigned long long *split_acc;     // [n_split * ntiles * kTileW] (zeroed)
     uint32_t *split_sat;               // [n_split * ntiles * kTileW / 32] (zeroed)
     int32_t *split_done;               // [n_split * ntiles] (zeroed)
+    const int32_t *ytile;              // [Y.rows * (ntiles + 1)] tile index of Y, or nullptr
     Tuning tune;
 };
 void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const NumericArgs &a, hipStream_t s,
@@ -156,6 +157,8 @@ void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const Nume
 void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *task_base, int64_t n_tasks,
                           const NumericArgs &a, hipStream_t s, KernelTimer *t);
 
+// per-row column-tile offsets of Y (the dense kernel's segment bounds)
+void launch_tile_index(const Operand &Y, int64_t ntiles, int32_t *ytile, hipStream_t s, KernelTimer *t);
 void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *chunk_base, int64_t n_chunks,
                            const int64_t *prod_base, int64_t ntiles, int64_t *tile_cnt, int64_t *tile_off,
                            int32_t *prod_col, uint64_t *prod_val, const NumericArgs &a, hipStream_t s,

@@ -907,6 +907,30 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
     auto segments = [&](int64_t xb, int64_t xlen, int64_t eb, int64_t c0, int64_t c1, bool from_cursor,
                         bool keep_cursor) -> int64_t {
         const int64_t nb = (xlen - eb < NT) ? xlen - eb : NT;
+        if (a.ytile) {  // the right operand's tile index gives both bounds directly
+            if (tid < nb) {
+                const int64_t e = eb + tid;
+                const int32_t k = a.X.col[xb + e];
+                if (a.X.cmask && !bit_test(a.X.cmask, k)) {
+                    seg_s[tid] = 0;
+                    seg_l[tid] = 0;
+                } else {
+                    const int32_t *yt = a.ytile + (int64_t)k * (ntiles + 1);
+                    const int64_t yb = a.Y.rp[k];
+                    const int32_t lo = yt[c0 >> kTileShift], hi = yt[(c1 + W - 1) >> kTileShift];
+                    seg_s[tid] = yb + lo;
+                    seg_l[tid] = hi - lo;
+                }
+            }
+            __syncthreads();
+            const int64_t len = tid < nb ? seg_l[tid] : 0;
+            int64_t tot;
+            const int64_t inc = block_inclusive_scan(len, sw, &tot);
+            seg_o[tid] = (int32_t)(inc - len);
+            if (tid == NT - 1) seg_o[NT] = (int32_t)inc;
+            __syncthreads();
+            return tot;
+        }
         if (tid < nb) {
             const int64_t e = eb + tid;
             const int32_t k = a.X.col[xb + e];
@@ -1097,8 +1121,9 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
             continue;
         }
 
-        // dense part: tile by tile
-        if (single) {  // cursors at the part start
+        // dense part: tile by tile (cursors only without the tile index)
+        const bool cursors = single && !a.ytile;
+        if (cursors) {  // cursors at the part start
             for (int64_t e = tid; e < xlen; e += NT) {
                 int32_t k = a.X.col[xb + e];
                 cur[e] = a.Y.rp[k];
@@ -1121,7 +1146,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
             const int64_t c0 = t * W;
             const int64_t c1 = (c0 + W < ycols) ? c0 + W : ycols;
             for (int64_t eb = 0; eb < xlen; eb += NT) {
-                const int64_t tot = segments(xb, xlen, eb, c0, c1, single, single);
+                const int64_t tot = segments(xb, xlen, eb, c0, c1, cursors, cursors);
                 const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
                 products(tot, xval, [&](int32_t j, uint64_t v) {
                     const uint32_t slot = (uint32_t)(j - c0);
@@ -1140,6 +1165,27 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
     }
     __syncthreads();
     if (tid == 0 && s_sat) atomicOr(&a.hdr->saturated, 1);
+}
+
+// Tile index of a right operand: ytile[k * (ntiles + 1) + t] = entries of
+// row k in column tiles below t (so tile t of row k is entries
+// [ytile[..t], ytile[..t+1]) from the row start).  One thread per (row,
+// boundary): a binary search of the boundary column; consecutive threads
+// write consecutive words.
+__global__ __launch_bounds__(256) void k_tile_index(Operand Y, int64_t ntiles, int32_t *ytile) {
+    const int64_t per = ntiles + 1, n = Y.rows * per;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = idx / per, t = idx - k * per;
+        const int64_t yb = Y.rp[k], ye = Y.rp[k + 1];
+        int64_t v;
+        if (t == 0)
+            v = 0;
+        else if (t == ntiles)
+            v = ye - yb;
+        else
+            v = lower_bound_col(Y.col, yb, ye, (int32_t)(t << kTileShift)) - yb;
+        ytile[idx] = (int32_t)v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1715,6 +1761,13 @@ void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *ta
     int64_t g = n_tasks < (int64_t)cus * 2 ? n_tasks : (int64_t)cus * 2;
     ATP_LAUNCH("dense", 0, 0, s, k_dense, dim3((unsigned)g), dim3(kDenseThreads), 0, s, list, n_list, task_base,
                n_tasks, a);
+}
+
+void launch_tile_index(const Operand &Y, int64_t ntiles, int32_t *ytile, hipStream_t s, KernelTimer *t) {
+    if (Y.rows <= 0) return;
+    const int cus = device_cus();
+    ATP_LAUNCH("tile_index", 0, 0, s, k_tile_index, dim3(grid_for(Y.rows * (ntiles + 1), 256, (int64_t)cus * 64)),
+               dim3(256), 0, s, Y, ntiles, ytile);
 }
 
 void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *chunk_base, int64_t n_chunks,
