@@ -297,13 +297,15 @@ atp_status atp_server_stop(atp_ctx *ctx);
  *                  column tile (products materialised once) instead of searched
  *                  per tile, >= 0
  *   split_ops      products per (row, tile) beyond which a dense row's left
- *                  entries are split over several workgroups, >= 1024 */
+ *                  entries are split over several workgroups, >= 1024
+ *   bucket_chunk   left entries per work item of a bucketed row, >= 64 */
 typedef struct {
     int64_t part_target;
     int64_t part_hash_cap;
     int64_t task_ops;
     int64_t bucket_pct;
     int64_t split_ops;
+    int64_t bucket_chunk;
 } atp_tuning;
 atp_status atp_get_tuning(const atp_ctx *ctx, atp_tuning *t);
 /* Between queries (not while a server or batch runs).  ATP_EINVAL if a value

@@ -30,7 +30,7 @@ EXPORTS = [
     "atp_eval_batch", "atp_server_start", "atp_submit", "atp_poll", "atp_server_pending", "atp_server_stop",
     "atp_get_tuning", "atp_set_tuning", "atp_autotune",
 ]
-TUNABLES = ("part_target", "part_hash_cap", "task_ops", "bucket_pct", "split_ops")
+TUNABLES = ("part_target", "part_hash_cap", "task_ops", "bucket_pct", "split_ops", "bucket_chunk")
 ATP_CACHE_OFF, ATP_CACHE_OTREE, ATP_CACHE_PGDS, ATP_CACHE_LRU, ATP_CACHE_CBS1, ATP_CACHE_CBS2 = 0, 1, 2, 3, 4, 5
 
 

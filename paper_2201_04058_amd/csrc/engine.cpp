@@ -38,6 +38,8 @@ Tuning atp::tuning_from_env() {
     get("ATP_TASK_OPS", t.task_ops);
     get("ATP_BUCKET_PCT", t.bucket_pct);
     get("ATP_SPLIT_OPS", t.split_ops);
+    get("ATP_BUCKET_CHUNK", t.bucket_chunk);
+    if (t.bucket_chunk < 64) t.bucket_chunk = 64;
     if (t.split_ops < 1024) t.split_ops = 1024;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -1442,7 +1444,7 @@ atp_status atp_cache_get_stats(const atp_ctx *c, atp_cache_stats *st) {
 // ---- tunables and the autotuner ----
 
 static atp_tuning to_abi(const Tuning &t) {
-    return atp_tuning{t.part_target, t.part_hash_cap, t.task_ops, t.bucket_pct, t.split_ops};
+    return atp_tuning{t.part_target, t.part_hash_cap, t.task_ops, t.bucket_pct, t.split_ops, t.bucket_chunk};
 }
 
 atp_status atp_get_tuning(const atp_ctx *c, atp_tuning *t) {
@@ -1454,13 +1456,14 @@ atp_status atp_get_tuning(const atp_ctx *c, atp_tuning *t) {
 atp_status atp_set_tuning(atp_ctx *c, const atp_tuning *t) {
     if (!c || !t) return ATP_EINVAL;
     if (t->part_target < 1 || t->part_hash_cap < 0 || t->part_hash_cap > 2048 || t->task_ops < 1 ||
-        t->bucket_pct < 0 || t->split_ops < 1024)
+        t->bucket_pct < 0 || t->split_ops < 1024 || t->bucket_chunk < 64)
         return ATP_EINVAL;
     c->tune.part_target = t->part_target;
     c->tune.part_hash_cap = t->part_hash_cap;
     c->tune.task_ops = t->task_ops;
     c->tune.bucket_pct = t->bucket_pct;
     c->tune.split_ops = t->split_ops;
+    c->tune.bucket_chunk = t->bucket_chunk;
     return ATP_OK;
 }
 
@@ -1500,6 +1503,7 @@ atp_status atp_autotune(atp_ctx *c, const atp_query *sample, int32_t n, int32_t 
         {&Tuning::task_ops, {8192, 16384, 32768, 65536}},
         {&Tuning::split_ops, {16384, 65536, 262144}},
         {&Tuning::part_hash_cap, {512, 1024, 2048}},
+        {&Tuning::bucket_chunk, {1024, 2048, 4096, 8192}},
     };
     double best = 0;
     atp_status st = run(best);  // also warms the pool and the planner statistics

@@ -22,7 +22,6 @@ constexpr int kPartMaxTiles = 16;      // ... if it spans at most this many tile
 constexpr int64_t kSplitOps = 65536;   // products per (row, tile) beyond which the row's entries are split
 constexpr int kMaxSplit = 64;
 constexpr int kMaxBucketTiles = 4096;  // column tiles a bucketed row may span
-constexpr int64_t kBucketChunk = 8192; // left-operand entries per bucketing work item
 constexpr int kBucketThreads = 512;
 
 // Hash bins: table sizes (slots); wave-level tables for small rows, block-level otherwise.
@@ -55,6 +54,7 @@ struct Tuning {
     int64_t bucket_pct = 400;  // bucket a row when left entries x tiles x 100 > pct x products
     int64_t split_ops = kSplitOps;
     int64_t wg_slots = 512;    // resident dense workgroups (2 per compute unit)
+    int64_t bucket_chunk = 4096;  // left-operand entries per bucketing work item
 };
 
 // Per-step device scratch header read back by the host (one small copy).

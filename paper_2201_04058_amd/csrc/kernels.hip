@@ -421,7 +421,7 @@ __global__ void k_bin_rows(SymbolicArgs a) {
             if (b == BIN_BUCKET) {
                 int64_t i = a.cand ? a.cand[c] : c;
                 int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
-                a.bucket_chunks[pos] = (xlen + kBucketChunk - 1) / kBucketChunk;
+                a.bucket_chunks[pos] = (xlen + a.tune.bucket_chunk - 1) / a.tune.bucket_chunk;
                 a.bucket_nop[pos] = nop;
             }
             if (b == BIN_DENSE) {
@@ -555,6 +555,28 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
 // ---------------------------------------------------------------------------
 // numeric: LDS hash, one workgroup per row
 
+// Block-wide bitonic sort of n (power of two) key/value pairs in LDS.
+__device__ void bitonic_sort_rt(int32_t *keys, unsigned long long *vals, int n) {
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                int b = a + j;
+                bool up = (a & k) == 0;
+                int32_t ka = keys[a], kb = keys[b];
+                if ((ka > kb) == up) {
+                    keys[a] = kb;
+                    keys[b] = ka;
+                    unsigned long long va = vals[a];
+                    vals[a] = vals[b];
+                    vals[b] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 template <int S, int NT>
 __device__ void bitonic_sort_block(int32_t *keys, unsigned long long *vals) {
     for (int k = 2; k <= S; k <<= 1) {
@@ -582,17 +604,14 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
     __shared__ int32_t keys[S];
     __shared__ unsigned long long vals[S];
     __shared__ uint32_t satw[S / 32];
-    __shared__ int cnt;
+    __shared__ int64_t sw[NT / 64];
     __shared__ int any_sat;
     for (int t = threadIdx.x; t < S; t += NT) {
         keys[t] = kEmptyKey;
         vals[t] = 0;
     }
     for (int t = threadIdx.x; t < S / 32; t += NT) satw[t] = 0;
-    if (threadIdx.x == 0) {
-        cnt = 0;
-        any_sat = 0;
-    }
+    if (threadIdx.x == 0) any_sat = 0;
     __syncthreads();
     for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
         const int32_t c = list[r];
@@ -604,18 +623,38 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
         const int gpw = 64 / g;  // groups per wave
         accumulate_hash<S>(a.X, a.Y, xb, xe, wave * gpw + lane / g, (NT / 64) * gpw, lane % g, g, keys, vals, satw);
         __syncthreads();
-        int local = 0;
-        for (int t = threadIdx.x; t < S; t += NT) {
-            if (keys[t] != kEmptyKey) {
+        // compact the occupied slots to the front (each thread's slots pass
+        // through registers), then sort only the next power of two of them
+        constexpr int PER = S / NT;
+        int32_t kk[PER];
+        unsigned long long vv[PER];
+        int64_t local = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int t = q * NT + threadIdx.x;
+            kk[q] = keys[t];
+            vv[q] = vals[t];
+            if (kk[q] != kEmptyKey) {
                 ++local;
-                if ((satw[t >> 5] >> (t & 31)) & 1u) vals[t] = kSat;
+                if ((satw[t >> 5] >> (t & 31)) & 1u) vv[q] = kSat;
             }
         }
-        for (int d = 32; d > 0; d >>= 1) local += __shfl_xor(local, d, 64);
-        if (lane == 0 && local) atomicAdd(&cnt, local);
+        int64_t tot64;
+        int64_t pos = block_inclusive_scan(local, sw, &tot64) - local;  // its barriers order reads before writes
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (kk[q] != kEmptyKey) {
+                keys[pos] = kk[q];
+                vals[pos] = vv[q];
+                ++pos;
+            }
+        }
+        const int total = (int)tot64;
+        int p2 = 1;
+        while (p2 < total) p2 <<= 1;
+        for (int t = total + threadIdx.x; t < p2; t += NT) keys[t] = kEmptyKey;
         __syncthreads();
-        bitonic_sort_block<S, NT>(keys, vals);
-        const int total = cnt;
+        bitonic_sort_rt(keys, vals, p2);
         const int64_t off = a.slot_off[c];
         bool sat = false;
         for (int t = threadIdx.x; t < total; t += NT) {
@@ -623,6 +662,9 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
             unsigned long long v = vals[t];
             a.slot_val[off + t] = v;
             sat |= (v & kSat) != 0;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < S; t += NT) {  // the whole table back to empty
             keys[t] = kEmptyKey;
             vals[t] = 0;
         }
@@ -635,7 +677,6 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
             a.seg_src[sb] = off;
             a.row_nnz[i] = total;
             if (any_sat) atomicOr(&a.hdr->saturated, 1);
-            cnt = 0;
             any_sat = 0;
         }
         __syncthreads();
@@ -844,37 +885,17 @@ __device__ __forceinline__ uint32_t hash_find_rt(int32_t *keys, int32_t j, int l
     }
 }
 
-// Block-wide bitonic sort of n (power of two) key/value pairs in LDS.
-__device__ void bitonic_sort_rt(int32_t *keys, unsigned long long *vals, int n) {
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
-                int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                int b = a + j;
-                bool up = (a & k) == 0;
-                int32_t ka = keys[a], kb = keys[b];
-                if ((ka > kb) == up) {
-                    keys[a] = kb;
-                    keys[b] = ka;
-                    unsigned long long va = vals[a];
-                    vals[a] = vals[b];
-                    vals[b] = va;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // One task = one row and a part of m consecutive column tiles.  Each left
-// entry's segment of its right row inside the part is located (binary search,
-// or the row start), the segment lengths are block-scanned, and:
-//  * a part with at most kPartHashCap products is accumulated in an LDS hash
-//    overlaid on the tile memory, bitonic-sorted, and emitted as one segment;
+// entry's segment of its right row inside the part is located (from the right
+// operand's tile index when there is one, else by binary search or the row
+// start), the segment lengths are block-scanned, and:
+//  * a part with at most part_hash_cap products is accumulated in an LDS hash
+//    overlaid on the tile memory, with a presence bitmap over the part's
+//    columns; emission walks the bitmap in column order;
 //  * otherwise the part is walked tile by tile: per tile the segments are
 //    found again (cursors carried between tiles when the row's entries fit one
-//    batch), and the flattened products are shared evenly by the threads
-//    (each walks 4 consecutive products) into a dense LDS tile.
+//    batch and there is no tile index), and the flattened products are shared
+//    evenly by the wavefronts into a dense LDS tile.
 // Left entries are taken in batches of kDenseThreads.
 __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, int64_t n_list, const int64_t *task_base,
                                                          int64_t n_tasks, NumericArgs a) {
@@ -1314,7 +1335,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, N
         const int32_t c = b.list[p];
         const int64_t i = a.cand ? a.cand[c] : c;
         const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
-        const int64_t e0 = xb + q * kBucketChunk, e1 = e0 + kBucketChunk < xe ? e0 + kBucketChunk : xe;
+        const int64_t bc = a.tune.bucket_chunk;
+        const int64_t e0 = xb + q * bc, e1 = e0 + bc < xe ? e0 + bc : xe;
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
         __syncthreads();
         if (b.g >= kRunMinLanes)
@@ -1363,7 +1385,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
         const int32_t c = b.list[p];
         const int64_t i = a.cand ? a.cand[c] : c;
         const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
-        const int64_t e0 = xb + q * kBucketChunk, e1 = e0 + kBucketChunk < xe ? e0 + kBucketChunk : xe;
+        const int64_t bc = a.tune.bucket_chunk;
+        const int64_t e0 = xb + q * bc, e1 = e0 + bc < xe ? e0 + bc : xe;
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
         __syncthreads();
         if (b.g >= kRunMinLanes)

@@ -215,12 +215,13 @@ def test_tuning_get_set_and_autotune(atp, net, mixed):
     ctx.load_hin(net)
     t0 = ctx.tuning()
     assert t0["bucket_pct"] == 400 and t0["part_hash_cap"] == 2048
-    for bad in ({"part_target": 0}, {"part_hash_cap": 4096}, {"bucket_pct": -1}, {"split_ops": 10}):
+    for bad in ({"part_target": 0}, {"part_hash_cap": 4096}, {"bucket_pct": -1}, {"split_ops": 10},
+                {"bucket_chunk": 8}):
         with pytest.raises(atp.AtpError) as e:
             ctx.set_tuning(**bad)
         assert e.value.status == atp.ATP_EINVAL
     assert ctx.tuning() == t0
-    ctx.set_tuning(bucket_pct=0, part_target=64, split_ops=1024, task_ops=1)
+    ctx.set_tuning(bucket_pct=0, part_target=64, split_ops=1024, task_ops=1, bucket_chunk=64)
     for q, want in zip(qs[:20], ref[:20]):
         assert same(host(ctx.eval_query(q)), want)
     ctx.set_tuning(**t0)
@@ -228,6 +229,7 @@ def test_tuning_get_set_and_autotune(atp, net, mixed):
     assert got["bucket_pct"] in (25, 50, 100, 200, 400, 800)
     assert got["part_target"] in (300, 600, 1200, 2400)
     assert got["part_hash_cap"] in (512, 1024, 2048)
+    assert got["bucket_chunk"] in (1024, 2048, 4096, 8192)
     assert got["ms_after"] <= got["ms_before"] * 1.0001
     assert {k: ctx.tuning()[k] for k in atp.TUNABLES} == {k: got[k] for k in atp.TUNABLES}
     for q, want in zip(qs, ref):
