@@ -362,6 +362,31 @@ atp_status atp_plan_chain(int32_t n_mats, const int64_t *dims, const int64_t *nn
                           double beta, double gamma, int32_t dense, char *plan, size_t plan_cap,
                           double *cost);
 
+/* --- cost model of the planner (Eq. 2) -------------------------------------
+ *
+ * Eq. 2 prices one multiplication Z = X*Y as alpha*nnz(X) + beta*N_op +
+ * gamma*nnz(Z); the paper fits alpha, beta, gamma by least squares on measured
+ * multiplications.  The engine adds delta per multiplication (launches and
+ * host synchronisation).  coeffs = {alpha, beta, gamma, delta}, all >= 0.
+ * Coefficients change plans only, never results. */
+
+/* Host-only least squares over n measured multiplications (t_ms ~ alpha *
+ * nnz_x + beta * n_op + gamma * nnz_z + delta); a coefficient that would be
+ * negative is fixed at 0 and the others refit.  *r2 = coefficient of
+ * determination (may be NULL). */
+atp_status atp_cost_fit(int32_t n, const double *nnz_x, const double *n_op, const double *nnz_z, const double *t_ms,
+                        double coeffs[4], double *r2);
+atp_status atp_get_cost_model(const atp_ctx *ctx, double coeffs[4]);
+/* ATP_EINVAL for a negative or non-finite value, or alpha = beta = gamma = 0. */
+atp_status atp_set_cost_model(atp_ctx *ctx, const double coeffs[4]);
+/* Evaluate the sample queries once, timing every multiplication with HIP
+ * events on the context's stream (nnz(X) of a base relation is the planner's
+ * masked estimate), fit the coefficients and install them.  ATP_EINVAL with
+ * fewer than four multiplications in the sample; ATP_ESTATE while a server
+ * runs or when the fit leaves alpha = beta = gamma = 0 (the model is kept). */
+atp_status atp_calibrate_cost_model(atp_ctx *ctx, const atp_query *sample, int32_t n, double coeffs[4], double *r2,
+                                    int32_t *n_products);
+
 /* --- diagnostics ------------------------------------------------------------ */
 
 /* Replace the context's ATP_OPT_* flags (between queries). */

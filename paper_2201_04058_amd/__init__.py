@@ -28,7 +28,8 @@ EXPORTS = [
     "atp_device_bytes", "atp_status_str", "atp_cache_configure", "atp_cache_get_stats", "atp_otree_create",
     "atp_otree_destroy", "atp_otree_insert", "atp_otree_frequency", "atp_otree_shape", "atp_cache_simulate",
     "atp_eval_batch", "atp_server_start", "atp_submit", "atp_poll", "atp_server_pending", "atp_server_stop",
-    "atp_get_tuning", "atp_set_tuning", "atp_autotune",
+    "atp_get_tuning", "atp_set_tuning", "atp_autotune", "atp_cost_fit", "atp_get_cost_model", "atp_set_cost_model",
+    "atp_calibrate_cost_model",
 ]
 TUNABLES = ("part_target", "part_hash_cap", "task_ops", "bucket_pct", "split_ops", "bucket_chunk")
 ATP_CACHE_OFF, ATP_CACHE_OTREE, ATP_CACHE_PGDS, ATP_CACHE_LRU, ATP_CACHE_CBS1, ATP_CACHE_CBS2 = 0, 1, 2, 3, 4, 5
@@ -152,6 +153,10 @@ def lib() -> ctypes.CDLL:
         "atp_get_tuning": ([vp, P(atp_tuning)], i32),
         "atp_set_tuning": ([vp, P(atp_tuning)], i32),
         "atp_autotune": ([vp, vp, i32, i32, P(atp_tuning), P(ctypes.c_double), P(ctypes.c_double)], i32),
+        "atp_cost_fit": ([i32, vp, vp, vp, vp, vp, P(ctypes.c_double)], i32),
+        "atp_get_cost_model": ([vp, vp], i32),
+        "atp_set_cost_model": ([vp, vp], i32),
+        "atp_calibrate_cost_model": ([vp, vp, i32, vp, P(ctypes.c_double), P(i32)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -227,6 +232,15 @@ def cache_simulate(policy: int, budget: float, sizes, costs, parents, requests) 
                                     len(rq), rq.ctypes.data, hit.ctypes.data, after.ctypes.data, fin.ctypes.data),
            "atp_cache_simulate")
     return hit.astype(bool), after.astype(bool), fin.astype(bool)
+
+
+def cost_fit(nnz_x, n_op, nnz_z, t_ms) -> tuple:
+    """Host-only fit of Eq. 2's coefficients -> ((alpha, beta, gamma, delta), r2)."""
+    cols = [np.ascontiguousarray(v, dtype=np.float64) for v in (nnz_x, n_op, nnz_z, t_ms)]
+    out = (ctypes.c_double * 4)()
+    r2 = ctypes.c_double()
+    _check(lib().atp_cost_fit(len(cols[3]), *[c.ctypes.data for c in cols], out, ctypes.byref(r2)), "atp_cost_fit")
+    return tuple(out), r2.value
 
 
 def torch_stream_handle(device: int = 0) -> int | None:
@@ -476,6 +490,32 @@ class Context:
         out = {n_: getattr(t, n_) for n_ in TUNABLES}
         out.update({"ms_before": b.value, "ms_after": a.value})
         return out
+
+    # --- cost model (Eq. 2) ---------------------------------------------------
+    def cost_model(self) -> tuple:
+        out = (ctypes.c_double * 4)()
+        _check(lib().atp_get_cost_model(self._h, out), "atp_get_cost_model")
+        return tuple(out)
+
+    def set_cost_model(self, coeffs) -> None:
+        c = (ctypes.c_double * 4)(*[float(x) for x in coeffs])
+        _check(lib().atp_set_cost_model(self._h, c), "atp_set_cost_model")
+
+    def calibrate_cost_model(self, sample) -> dict:
+        """Time every multiplication of the sample, fit Eq. 2 and install the fit."""
+        n = len(sample)
+        qs = (atp_query * max(1, n))()
+        keep = []
+        for i, q in enumerate(sample):
+            qs[i], k = self._query(q)
+            keep.append(k)
+        out = (ctypes.c_double * 4)()
+        r2 = ctypes.c_double()
+        np_ = ctypes.c_int32()
+        _check(lib().atp_calibrate_cost_model(self._h, qs, n, out, ctypes.byref(r2), ctypes.byref(np_)),
+               "atp_calibrate_cost_model")
+        del keep
+        return {"coeffs": tuple(out), "r2": r2.value, "products": np_.value}
 
     def server_pending(self) -> int:
         return int(lib().atp_server_pending(self._h))

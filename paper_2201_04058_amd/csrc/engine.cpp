@@ -4,6 +4,8 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <array>
+#include <cmath>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -802,7 +804,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
             ch.push_back(it->second);
             csel.push_back(sel_of(k + 1));
         }
-        CostCoeffs cc;
+        const CostCoeffs cc = c->cost;
         PlanResult pr = plan_chain(lst, js, jsel, ch, csel, uniform ? Estimator::Uniform : Estimator::Sketch, cc,
                                    caching ? &cached_stats : nullptr);
         plan_str = pr.plan;
@@ -881,6 +883,18 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         return ATP_OK;
     };
     std::vector<KeptMat> kept;  // products kept for the cache's insertion policy
+    struct CostRecord {
+        double nnz_x = 0, n_op = 0, nnz_z = 0;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+    };
+    struct CostRecords : std::vector<CostRecord> {
+        ~CostRecords() {
+            for (auto &r : *this) {
+                if (r.e0) (void)hipEventDestroy(r.e0);
+                if (r.e1) (void)hipEventDestroy(r.e1);
+            }
+        }
+    } cost_recs;
     std::vector<int64_t> used_items;
     // post-order evaluation of node v into outm; rs restricts v's rows; cost =
     // seconds to compute it from the base relations in this query
@@ -952,7 +966,22 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         bool sat = false;
         if (c->step_names) L->timer.suffix = "#" + std::to_string(n_products);
         const auto t_0 = std::chrono::steady_clock::now();
+        CostRecord rec;
+        if (c->cost_sink) {  // device time of this multiplication, for the cost-model fit
+            rec.nnz_x = X.leaf ? lst[l0].nnz : (double)X.nnz;
+            rec.n_op = (double)st.n_op;
+            HIPTRY(hipEventCreate(&rec.e0));
+            HIPTRY(hipEventCreate(&rec.e1));
+            HIPTRY(hipEventRecord(rec.e0, s));
+        }
         TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat));
+        if (c->cost_sink) {
+            HIPTRY(hipEventRecord(rec.e1, s));
+            rec.n_op = (double)st.n_op - rec.n_op;
+            rec.nnz_z = (double)outm.nnz;
+            cost_recs.push_back(rec);
+            rec.e0 = rec.e1 = nullptr;
+        }
         cost = cx + cy + std::chrono::duration<double>(std::chrono::steady_clock::now() - t_0).count();
         L->timer.suffix.clear();
         ++n_products;
@@ -1020,6 +1049,14 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     }
     HIPTRY(hipStreamSynchronize(s));
     if (t) t->flush();
+    if (c->cost_sink && !cost_recs.empty()) {
+        std::lock_guard<std::mutex> g(c->stat_mu);
+        for (auto &r : cost_recs) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess)
+                c->cost_sink->push_back({r.nnz_x, r.n_op, r.nnz_z, (double)ms});
+        }
+    }
     if (overflow) return ATP_EOVERFLOW;
     atp_result *res = new atp_result();
     res->ctx = c;
@@ -1535,6 +1572,88 @@ atp_status atp_autotune(atp_ctx *c, const atp_query *sample, int32_t n, int32_t 
     if (chosen) *chosen = to_abi(c->tune);
     if (ms_before) *ms_before = before;
     if (ms_after) *ms_after = best;
+    return ATP_OK;
+}
+
+// ---- cost model (Eq. 2) ----
+
+atp_status atp_cost_fit(int32_t n, const double *nnz_x, const double *n_op, const double *nnz_z, const double *t_ms,
+                        double coeffs[4], double *r2) {
+    if (n < 1 || !nnz_x || !n_op || !nnz_z || !t_ms || !coeffs) return ATP_EINVAL;
+    CostCoeffs cc;
+    const double q = fit_cost(std::vector<double>(nnz_x, nnz_x + n), std::vector<double>(n_op, n_op + n),
+                              std::vector<double>(nnz_z, nnz_z + n), std::vector<double>(t_ms, t_ms + n), cc);
+    coeffs[0] = cc.alpha;
+    coeffs[1] = cc.beta;
+    coeffs[2] = cc.gamma;
+    coeffs[3] = cc.delta;
+    if (r2) *r2 = q;
+    return ATP_OK;
+}
+
+atp_status atp_get_cost_model(const atp_ctx *c, double coeffs[4]) {
+    if (!c || !coeffs) return ATP_EINVAL;
+    coeffs[0] = c->cost.alpha;
+    coeffs[1] = c->cost.beta;
+    coeffs[2] = c->cost.gamma;
+    coeffs[3] = c->cost.delta;
+    return ATP_OK;
+}
+
+atp_status atp_set_cost_model(atp_ctx *c, const double coeffs[4]) {
+    if (!c || !coeffs) return ATP_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (!(coeffs[k] >= 0) || !std::isfinite(coeffs[k])) return ATP_EINVAL;
+    if (coeffs[0] + coeffs[1] + coeffs[2] <= 0) return ATP_EINVAL;
+    c->cost.alpha = coeffs[0];
+    c->cost.beta = coeffs[1];
+    c->cost.gamma = coeffs[2];
+    c->cost.delta = coeffs[3];
+    return ATP_OK;
+}
+
+atp_status atp_calibrate_cost_model(atp_ctx *c, const atp_query *sample, int32_t n, double coeffs[4], double *r2,
+                                    int32_t *n_products) {
+    if (!c || !sample || n < 1) return ATP_EINVAL;
+    if (c->server) return ATP_ESTATE;
+    (void)hipSetDevice(c->device);
+    std::vector<std::array<double, 4>> recs;
+    {
+        std::lock_guard<std::mutex> g(c->stat_mu);
+        c->cost_sink = &recs;
+    }
+    atp_status st = ATP_OK;
+    for (int32_t i = 0; i < n && st == ATP_OK; ++i) {
+        const atp_query &q = sample[i];
+        atp_result *r = nullptr;
+        st = eval_impl(c, &c->main, q.types, q.n_types, q.rel_ids, q.cons, q.n_cons, nullptr, 1, &r);
+        if (st == ATP_OK) atp_result_free(r);
+    }
+    {
+        std::lock_guard<std::mutex> g(c->stat_mu);
+        c->cost_sink = nullptr;
+    }
+    if (st != ATP_OK) return st;
+    if (recs.size() < 4) return ATP_EINVAL;  // too few multiplications to fit four coefficients
+    std::vector<double> x(recs.size()), o(recs.size()), z(recs.size()), t(recs.size());
+    for (size_t k = 0; k < recs.size(); ++k) {
+        x[k] = recs[k][0];
+        o[k] = recs[k][1];
+        z[k] = recs[k][2];
+        t[k] = recs[k][3];
+    }
+    CostCoeffs cc;
+    const double q = fit_cost(x, o, z, t, cc);
+    if (cc.alpha + cc.beta + cc.gamma <= 0) return ATP_ESTATE;  // the fit explains nothing: keep the model
+    c->cost = cc;
+    if (coeffs) {
+        coeffs[0] = cc.alpha;
+        coeffs[1] = cc.beta;
+        coeffs[2] = cc.gamma;
+        coeffs[3] = cc.delta;
+    }
+    if (r2) *r2 = q;
+    if (n_products) *n_products = (int32_t)recs.size();
     return ATP_OK;
 }
 

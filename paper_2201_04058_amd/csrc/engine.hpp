@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -397,6 +398,8 @@ struct atp_ctx {
     std::map<std::pair<int, int>, atp::JunctionSketch> sketches;
     std::map<int, atp::ColumnHist> col_hists;
     std::map<std::string, int64_t> pop_memo;  // mask popcount by (type, position constraint key)
+    atp::CostCoeffs cost;                     // Eq. 2 coefficients of the planner
+    std::vector<std::array<double, 4>> *cost_sink = nullptr;  // (nnz(X), N_op, nnz(Z), ms) per multiplication
     atp::CacheState cache;
     std::mutex results_mu;
     std::set<atp_result *> results;

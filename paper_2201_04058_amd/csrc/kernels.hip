@@ -473,11 +473,12 @@ __global__ void k_bin_rows(SymbolicArgs a) {
 // ---------------------------------------------------------------------------
 // numeric: LDS hash, one wavefront per row
 
-template <int S>
-__device__ void bitonic_sort_wave(int32_t *keys, unsigned long long *vals, int lane) {
-    for (int k = 2; k <= S; k <<= 1) {
+
+// Wavefront bitonic sort of the first n (power of two) pairs.
+__device__ void bitonic_sort_wave_rt(int32_t *keys, unsigned long long *vals, int n, int lane) {
+    for (int k = 2; k <= n; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = lane; t < S / 2; t += 64) {
+            for (int t = lane; t < n / 2; t += 64) {
                 int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
                 int b = a + j;
                 bool up = (a & k) == 0;
@@ -520,16 +521,31 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
         const int g = group_size(a.nop[c] / (xlen > 0 ? xlen : 1));
         accumulate_hash<S>(a.X, a.Y, xb, xe, lane / g, 64 / g, lane % g, g, keys, vals, satw);
         wave_sync();
+        // compact the occupied slots to the front in one pass (a slot is read
+        // before any write can reach it: positions written stay below the
+        // current group of 64), then sort the next power of two of them
         int local = 0;
-        for (int t = lane; t < S; t += 64) {
-            if (keys[t] != kEmptyKey) {
-                ++local;
-                if ((satw[t >> 5] >> (t & 31)) & 1u) vals[t] = kSat;
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        for (int t0 = 0; t0 < S; t0 += 64) {
+            const int t = t0 + lane;
+            const int32_t kk = keys[t];
+            unsigned long long vv = vals[t];
+            const bool occ = kk != kEmptyKey;
+            if (occ && ((satw[t >> 5] >> (t & 31)) & 1u)) vv = kSat;
+            const uint64_t m = __ballot(occ);
+            if (occ) {
+                const int pos = local + __popcll(m & lt);
+                keys[pos] = kk;
+                vals[pos] = vv;
             }
+            local += __popcll(m);
+            wave_sync();
         }
-        for (int d = 32; d > 0; d >>= 1) local += __shfl_xor(local, d, 64);
+        int p2 = 1;
+        while (p2 < local) p2 <<= 1;
+        for (int t = local + lane; t < p2; t += 64) keys[t] = kEmptyKey;
         wave_sync();
-        bitonic_sort_wave<S>(keys, vals, lane);
+        bitonic_sort_wave_rt(keys, vals, p2, lane);
         const int64_t off = a.slot_off[c];
         bool sat = false;
         for (int t = lane; t < local; t += 64) {
@@ -537,6 +553,9 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
             unsigned long long v = vals[t];
             a.slot_val[off + t] = v;
             sat |= (v & kSat) != 0;
+        }
+        wave_sync();
+        for (int t = lane; t < S; t += 64) {  // the whole table back to empty
             keys[t] = kEmptyKey;
             vals[t] = 0;
         }
@@ -577,27 +596,6 @@ __device__ void bitonic_sort_rt(int32_t *keys, unsigned long long *vals, int n) 
     }
 }
 
-template <int S, int NT>
-__device__ void bitonic_sort_block(int32_t *keys, unsigned long long *vals) {
-    for (int k = 2; k <= S; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < S / 2; t += NT) {
-                int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                int b = a + j;
-                bool up = (a & k) == 0;
-                int32_t ka = keys[a], kb = keys[b];
-                if ((ka > kb) == up) {
-                    keys[a] = kb;
-                    keys[b] = ka;
-                    unsigned long long va = vals[a];
-                    vals[a] = vals[b];
-                    vals[b] = va;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
 
 template <int S, int NT>
 __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t n, NumericArgs a) {

@@ -305,4 +305,79 @@ bool parse_plan(const char *s, int p, std::vector<PlanTree> &nodes, int &root) {
     return ps.ok && s[ps.pos] == '\0' && ps.next_leaf == p;
 }
 
+double fit_cost(const std::vector<double> &nnz_x, const std::vector<double> &n_op, const std::vector<double> &nnz_z,
+                const std::vector<double> &t, CostCoeffs &out) {
+    const size_t n = t.size();
+    constexpr int K = 4;
+    bool active[K] = {true, true, true, true};
+    double coef[K] = {0, 0, 0, 0};
+    auto feat = [&](size_t i, int k) {
+        return k == 0 ? nnz_x[i] : k == 1 ? n_op[i] : k == 2 ? nnz_z[i] : 1.0;
+    };
+    for (int round = 0; round < K; ++round) {
+        std::vector<int> idx;
+        for (int k = 0; k < K; ++k)
+            if (active[k]) idx.push_back(k);
+        const int m = (int)idx.size();
+        if (m == 0 || n == 0) break;
+        // normal equations over the active features, columns scaled to unit norm
+        std::vector<double> scale(m, 0.0);
+        for (int a = 0; a < m; ++a) {
+            for (size_t i = 0; i < n; ++i) scale[a] += feat(i, idx[a]) * feat(i, idx[a]);
+            scale[a] = scale[a] > 0 ? std::sqrt(scale[a]) : 1.0;
+        }
+        std::vector<double> A(m * (m + 1), 0.0);
+        for (size_t i = 0; i < n; ++i)
+            for (int a = 0; a < m; ++a) {
+                const double fa = feat(i, idx[a]) / scale[a];
+                for (int b = 0; b < m; ++b) A[a * (m + 1) + b] += fa * feat(i, idx[b]) / scale[b];
+                A[a * (m + 1) + m] += fa * t[i];
+            }
+        for (int a = 0; a < m; ++a) A[a * (m + 1) + a] += 1e-12;  // keeps a rank-deficient system solvable
+        for (int col = 0; col < m; ++col) {  // Gauss-Jordan with partial pivoting
+            int piv = col;
+            for (int r = col + 1; r < m; ++r)
+                if (std::fabs(A[r * (m + 1) + col]) > std::fabs(A[piv * (m + 1) + col])) piv = r;
+            for (int q = 0; q <= m; ++q) std::swap(A[col * (m + 1) + q], A[piv * (m + 1) + q]);
+            const double d = A[col * (m + 1) + col];
+            if (std::fabs(d) < 1e-300) continue;
+            for (int q = 0; q <= m; ++q) A[col * (m + 1) + q] /= d;
+            for (int r = 0; r < m; ++r) {
+                if (r == col) continue;
+                const double f = A[r * (m + 1) + col];
+                for (int q = 0; q <= m; ++q) A[r * (m + 1) + q] -= f * A[col * (m + 1) + q];
+            }
+        }
+        int worst = -1;
+        double wv = 0;
+        for (int k = 0; k < K; ++k) coef[k] = 0;
+        for (int a = 0; a < m; ++a) {
+            coef[idx[a]] = A[a * (m + 1) + m] / scale[a];
+            if (coef[idx[a]] < wv) {
+                wv = coef[idx[a]];
+                worst = idx[a];
+            }
+        }
+        if (worst < 0) break;
+        active[worst] = false;
+        coef[worst] = 0;
+    }
+    for (int k = 0; k < K; ++k)
+        if (coef[k] < 0) coef[k] = 0;
+    out.alpha = coef[0];
+    out.beta = coef[1];
+    out.gamma = coef[2];
+    out.delta = coef[3];
+    double mean = 0, ss_tot = 0, ss_res = 0;
+    for (size_t i = 0; i < n; ++i) mean += t[i];
+    mean = n ? mean / n : 0;
+    for (size_t i = 0; i < n; ++i) {
+        double pred = 0;
+        for (int k = 0; k < K; ++k) pred += coef[k] * feat(i, k);
+        ss_res += (t[i] - pred) * (t[i] - pred);
+        ss_tot += (t[i] - mean) * (t[i] - mean);
+    }
+    return ss_tot > 0 ? 1.0 - ss_res / ss_tot : 1.0;
+}
+
 }  // namespace atp

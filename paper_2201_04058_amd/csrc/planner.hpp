@@ -85,4 +85,11 @@ struct PlanTree {
 };
 bool parse_plan(const char *s, int p, std::vector<PlanTree> &nodes, int &root);
 
+// Least-squares fit of Eq. 2's coefficients (plus the per-product constant
+// delta) to measured multiplications: t ~ alpha*nnz(X) + beta*N_op +
+// gamma*nnz(Z) + delta, every coefficient >= 0 (a coefficient that comes out
+// negative is fixed at 0 and the rest refit).  Returns R^2 of the fit.
+double fit_cost(const std::vector<double> &nnz_x, const std::vector<double> &n_op, const std::vector<double> &nnz_z,
+                const std::vector<double> &t, CostCoeffs &out);
+
 }  // namespace atp

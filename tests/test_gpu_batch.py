@@ -239,3 +239,27 @@ def test_tuning_get_set_and_autotune(atp, net, mixed):
         ctx.autotune(qs[:2])
     assert e.value.status == atp.ATP_ESTATE
     ctx.close()
+
+
+def test_cost_model_calibration_keeps_results(atp, net, mixed):
+    """Eq. 2 refit on timed multiplications: non-negative coefficients,
+    installed in the planner, results unchanged."""
+    qs, ref = mixed
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    start = ctx.cost_model()
+    assert all(v >= 0 for v in start)
+    with pytest.raises(atp.AtpError) as e:
+        ctx.set_cost_model((-1.0, 1.0, 1.0, 0.0))
+    assert e.value.status == atp.ATP_EINVAL
+    with pytest.raises(atp.AtpError):
+        ctx.set_cost_model((0.0, 0.0, 0.0, 1.0))
+    fit = ctx.calibrate_cost_model(qs[:24])
+    assert fit["products"] >= 4
+    assert all(v >= 0 for v in fit["coeffs"]) and sum(fit["coeffs"][:3]) > 0
+    assert ctx.cost_model() == pytest.approx(fit["coeffs"])
+    for q, want in zip(qs, ref):
+        assert same(host(ctx.eval_query(q)), want)
+    ctx.set_cost_model(start)
+    assert ctx.cost_model() == pytest.approx(start)
+    ctx.close()
