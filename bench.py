@@ -185,7 +185,11 @@ def batch_mode(args) -> int:
         lat.append((time.perf_counter() - tq) * 1e3)
     t_plain = time.perf_counter() - t0
     log(f"one at a time: {len(qs)} queries in {t_plain:.2f} s")
-    tuned = None
+    tuned = fitted = None
+    if args.calibrate:  # Eq. 2 coefficients fitted on walks of another seed
+        fitted = ctx.calibrate_cost_model(
+            workload.random_walk_batch(hin, 21, args.tune_queries, start_sizes=(args.start_min, args.start_max)))
+        log(f"cost model: {fitted}")
     if args.autotune:  # on queries of another seed, not the measured ones
         sample = workload.random_walk_batch(hin, 13, args.tune_queries, start_sizes=(args.start_min, args.start_max))
         tuned = ctx.autotune(sample)
@@ -207,7 +211,8 @@ def batch_mode(args) -> int:
                       "start_set": [args.start_min, args.start_max], "selectivity": [0.01, 0.20],
                       "lanes": args.lanes, "max_batch": args.max_batch, "admit_gb": args.admit_gb},
            "one_at_a_time": {"qps": round(len(qs) / t_plain, 3), "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99)},
-           "vs_one_at_a_time": round(t_plain / t_batch, 3), "result_mismatches": len(bad), "autotuned": tuned}
+           "vs_one_at_a_time": round(t_plain / t_batch, 3), "result_mismatches": len(bad), "autotuned": tuned,
+           "cost_model": fitted}
     print(json.dumps(out), flush=True)
     return 0 if not bad else 1
 
@@ -284,7 +289,12 @@ def serve_mode(args) -> int:
         log(f"plain path: {len(qs)} queries at {args.qps} QPS")
         plain, dp = _serve(atp, ctx, arrivals, qs, 1, 1, 0, args.cap_s)
         log(f"plain: {plain}")
-    tuned = None
+    tuned = fitted = None
+    if args.calibrate:  # Eq. 2 coefficients fitted on a stream of another seed
+        _, sample = workload.serving_stream(hin, 6, args.tune_queries, start_sizes=(args.start_min, args.start_max),
+                                            pool=args.pool)
+        fitted = ctx.calibrate_cost_model(sample)
+        log(f"cost model: {fitted}")
     if args.autotune:  # on a stream of another seed, not the measured one
         _, sample = workload.serving_stream(hin, 5, args.tune_queries, start_sizes=(args.start_min, args.start_max),
                                             pool=args.pool)
@@ -311,7 +321,7 @@ def serve_mode(args) -> int:
            "served": served, "plain": plain,
            "vs_plain_qps": round(served["qps"] / max(plain["qps"], 1e-9), 3),
            "vs_plain_p99": round(plain["p99_ms"] / max(served["p99_ms"], 1e-9), 3) if plain["p99_ms"] else None,
-           "result_mismatches": len(bad), "autotuned": tuned}
+           "result_mismatches": len(bad), "autotuned": tuned, "cost_model": fitted}
     print(json.dumps(out), flush=True)
     return 0 if not bad else 1
 
@@ -387,6 +397,7 @@ def main() -> int:
     ap.add_argument("--cap-s", type=float, default=120.0, help="serve: stop submitting after this many seconds")
     ap.add_argument("--pool", type=int, default=16, help="serve: start sets per type and windows in the pools")
     ap.add_argument("--autotune", action="store_true", help="batch/serve: autotune the tunables first")
+    ap.add_argument("--calibrate", action="store_true", help="batch/serve: refit Eq. 2's coefficients first")
     ap.add_argument("--tune-queries", type=int, default=24)
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain-path run")
     ap.add_argument("--stream", default="walks", choices=["walks", "sessions"],

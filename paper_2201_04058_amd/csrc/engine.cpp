@@ -503,6 +503,88 @@ struct KeptMat {
     Mat m;
 };
 
+// The relation of every step of a metapath (Def. 2): the given ids, checked
+// against the types, or the unique relation between each pair of types.
+atp_status resolve_rels(const atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                        std::vector<int> &rel) {
+    const int ntypes_reg = (int)c->types.size();
+    for (int i = 0; i < n_types; ++i)
+        if (types[i] < 0 || types[i] >= ntypes_reg) return ATP_EINVAL;
+    const int p = n_types - 1;
+    rel.assign(p, -1);
+    for (int i = 0; i < p; ++i) {
+        if (rel_ids) {
+            int r = rel_ids[i];
+            if (r < 0 || r >= (int)c->rels.size()) return ATP_EINVAL;
+            if (c->rels[r]->src != types[i] || c->rels[r]->dst != types[i + 1]) return ATP_ESCHEMA;
+            rel[i] = r;
+        } else {
+            int found = -1, nfound = 0;
+            for (int r = 0; r < (int)c->rels.size(); ++r)
+                if (c->rels[r]->src == types[i] && c->rels[r]->dst == types[i + 1]) {
+                    found = r;
+                    ++nfound;
+                }
+            if (nfound != 1) return ATP_ESCHEMA;
+            rel[i] = found;
+        }
+    }
+    return ATP_OK;
+}
+
+// Bookkeeping of one insertion attempt (Sec. 3.4.1): find or create the item
+// of `key`, count the attempt and let the policy admit it, evicting as it
+// decides.  Returns the item id to store, or -1 (already cached / refused).
+// The caller holds cs.mu.
+int64_t admit_item(CacheState &cs, const std::string &key, const std::vector<int32_t> &ty,
+                   const std::vector<int32_t> &rl, const std::vector<std::string> &ps, double bytes, double cost) {
+    int64_t id;
+    auto it = cs.item_by_key.find(key);
+    if (it != cs.item_by_key.end()) {
+        id = it->second;
+        if (cs.payload.count(id)) return -1;  // already cached
+    } else {
+        id = cs.pol->add_item(bytes, std::max(cost, 1e-9));
+        const int node = cs.tree->find(ty);
+        cs.info[id] = CacheItemInfo{node, ty, rl, ps};
+        cs.item_by_key[key] = id;
+        if (node >= 0) cs.tree->node(node).keys[key].item = id;
+    }
+    cs.stats.insert_attempts += 1;
+    std::vector<int64_t> ev;
+    const bool ok = cs.pol->request(id, ev);
+    for (int64_t e : ev) {
+        cs.payload.erase(e);  // a query still using it holds its own reference
+        cs.stats.evictions += 1;
+    }
+    return ok ? id : -1;
+}
+
+// Store a copy of a CSR result as item id's payload (the caller holds cs.mu).
+atp_status store_copy(CacheState &cs, Lane *L, int64_t id, int64_t rows, int64_t cols, int64_t nnz, const void *rp,
+                      const void *col, const void *val) {
+    hipStream_t s = L->stream;
+    auto P = std::make_shared<CachePayload>();
+    P->rows = rows;
+    P->cols = cols;
+    P->nnz = nnz;
+    P->bytes = cs.pol->item(id).size;
+    TRY(P->rp.alloc(&L->pool, 8 * (size_t)(rows + 1)));
+    TRY(P->col.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(nnz, 1)));
+    TRY(P->val.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(nnz, 1)));
+    HIPTRY(hipMemcpyAsync(P->rp.p, rp, 8 * (rows + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz) {
+        HIPTRY(hipMemcpyAsync(P->col.p, col, 4 * nnz, hipMemcpyDeviceToDevice, s));
+        HIPTRY(hipMemcpyAsync(P->val.p, val, 8 * nnz, hipMemcpyDeviceToDevice, s));
+    }
+    P->n_active = -1;
+    HIPTRY(hipEventCreateWithFlags(&P->ready, hipEventDisableTiming));
+    HIPTRY(hipEventRecord(P->ready, s));
+    cs.payload[id] = std::move(P);
+    cs.stats.inserts += 1;
+    return ATP_OK;
+}
+
 // Cache insertion after a query (Sec. 3.4.1): record the hits on cached
 // sub-results, then try to insert the policy's candidates -- the whole query
 // and, for the Overlap-Tree policies, the longest computed sub-metapath whose
@@ -544,51 +626,24 @@ atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std
         const std::vector<int32_t> ty(types + cd.lo, types + cd.hi + 2);
         const std::vector<int32_t> rl(rel.begin() + cd.lo, rel.begin() + cd.hi + 1);
         const std::vector<std::string> ps(pkeys.begin() + cd.lo, pkeys.begin() + cd.hi + 2);
-        const std::string key = item_key(ty, rl, ps);
         const Mat &m = *cd.m;
-        int64_t id;
-        auto it = cs.item_by_key.find(key);
-        if (it != cs.item_by_key.end()) {
-            id = it->second;
-            if (cs.payload.count(id)) continue;  // already cached
-        } else {
-            const double bytes = 8.0 * (m.rows + 1) + 12.0 * m.nnz + (m.n_active >= 0 ? 4.0 * m.n_active : 0.0);
-            id = cs.pol->add_item(bytes, std::max(cd.cost, 1e-9));
-            const int node = cs.tree->find(ty);
-            cs.info[id] = CacheItemInfo{node, ty, rl, ps};
-            cs.item_by_key[key] = id;
-            if (node >= 0) cs.tree->node(node).keys[key].item = id;
+        const double bytes = 8.0 * (m.rows + 1) + 12.0 * m.nnz + (m.n_active >= 0 ? 4.0 * m.n_active : 0.0);
+        const int64_t id = admit_item(cs, item_key(ty, rl, ps), ty, rl, ps, bytes, cd.cost);
+        if (id < 0) continue;
+        if (cd.root) {  // the caller keeps R: copy it
+            TRY(store_copy(cs, L, id, m.rows, m.cols, m.nnz, m.rp.p, m.col.p, m.val.p));
+            continue;
         }
-        cs.stats.insert_attempts += 1;
-        std::vector<int64_t> ev;
-        const bool ok = cs.pol->request(id, ev);
-        for (int64_t e : ev) {
-            cs.payload.erase(e);  // a query still using it holds its own reference
-            cs.stats.evictions += 1;
-        }
-        if (!ok) continue;
         auto P = std::make_shared<CachePayload>();
         P->rows = m.rows;
         P->cols = m.cols;
         P->nnz = m.nnz;
         P->bytes = cs.pol->item(id).size;
-        if (cd.root) {  // the caller keeps R: copy it
-            TRY(P->rp.alloc(&L->pool, 8 * (size_t)(m.rows + 1)));
-            TRY(P->col.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(m.nnz, 1)));
-            TRY(P->val.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(m.nnz, 1)));
-            HIPTRY(hipMemcpyAsync(P->rp.p, m.rp.p, 8 * (m.rows + 1), hipMemcpyDeviceToDevice, s));
-            if (m.nnz) {
-                HIPTRY(hipMemcpyAsync(P->col.p, m.col.p, 4 * m.nnz, hipMemcpyDeviceToDevice, s));
-                HIPTRY(hipMemcpyAsync(P->val.p, m.val.p, 8 * m.nnz, hipMemcpyDeviceToDevice, s));
-            }
-            P->n_active = -1;
-        } else {
-            P->rp = std::move(cd.m->rp);
-            P->col = std::move(cd.m->col);
-            P->val = std::move(cd.m->val);
-            P->n_active = cd.m->n_active;
-            if (cd.m->n_active >= 0) P->active = std::move(cd.m->active);
-        }
+        P->rp = std::move(cd.m->rp);
+        P->col = std::move(cd.m->col);
+        P->val = std::move(cd.m->val);
+        P->n_active = cd.m->n_active;
+        if (cd.m->n_active >= 0) P->active = std::move(cd.m->active);
         // other lanes order their reads after this lane's writes through the event
         HIPTRY(hipEventCreateWithFlags(&P->ready, hipEventDisableTiming));
         HIPTRY(hipEventRecord(P->ready, s));
@@ -605,29 +660,10 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     if (c->broken) return ATP_EDEVICE;
     if (n_types < 2) return ATP_EINVAL;
     if (n_cons < 0 || (n_cons > 0 && !cons)) return ATP_EINVAL;
-    const int ntypes_reg = (int)c->types.size();
-    for (int i = 0; i < n_types; ++i)
-        if (types[i] < 0 || types[i] >= ntypes_reg) return ATP_EINVAL;
     // relations of every step (Def. 2; one matrix per edge type)
     const int p = n_types - 1;
-    std::vector<int> rel(p);
-    for (int i = 0; i < p; ++i) {
-        if (rel_ids) {
-            int r = rel_ids[i];
-            if (r < 0 || r >= (int)c->rels.size()) return ATP_EINVAL;
-            if (c->rels[r]->src != types[i] || c->rels[r]->dst != types[i + 1]) return ATP_ESCHEMA;
-            rel[i] = r;
-        } else {
-            int found = -1, nfound = 0;
-            for (int r = 0; r < (int)c->rels.size(); ++r)
-                if (c->rels[r]->src == types[i] && c->rels[r]->dst == types[i + 1]) {
-                    found = r;
-                    ++nfound;
-                }
-            if (nfound != 1) return ATP_ESCHEMA;
-            rel[i] = found;
-        }
-    }
+    std::vector<int> rel;
+    TRY(resolve_rels(c, types, n_types, rel_ids, rel));
     for (int q = 0; q < n_cons; ++q) {
         const atp_constraint &k = cons[q];
         if (k.position < 0 || k.position >= n_types) return ATP_EINVAL;
@@ -1094,6 +1130,49 @@ atp_status eval_query(atp_ctx *c, Lane *L, const QueryRef &q, const char *plan, 
 void release_pool_caches(atp_ctx *c) {
     c->main.pool.release_cache();
     for (auto &ln : c->lanes) ln->pool.release_cache();
+}
+
+// Whole-query cache key of q, or "" when q does not resolve.
+static std::string whole_key(atp_ctx *c, const QueryRef &q, std::vector<int32_t> &ty, std::vector<int32_t> &rl,
+                             std::vector<std::string> &ps) {
+    if (!q.types || q.n_types < 2) return "";
+    std::vector<int> rel;
+    if (resolve_rels(c, q.types, q.n_types, q.rel_ids, rel) != ATP_OK) return "";
+    ty.assign(q.types, q.types + q.n_types);
+    rl.assign(rel.begin(), rel.end());
+    ps = position_keys(q.n_types, q.cons, q.n_cons);
+    return item_key(ty, rl, ps);
+}
+
+bool cache_has_whole(atp_ctx *c, const QueryRef &q) {
+    CacheState &cs = c->cache;
+    {
+        std::lock_guard<std::mutex> g(cs.mu);
+        if (cs.policy == ATP_CACHE_OFF) return false;
+    }
+    std::vector<int32_t> ty, rl;
+    std::vector<std::string> ps;
+    const std::string key = whole_key(c, q, ty, rl, ps);
+    if (key.empty()) return false;
+    std::lock_guard<std::mutex> g(cs.mu);
+    auto it = cs.item_by_key.find(key);
+    return it != cs.item_by_key.end() && cs.payload.count(it->second) > 0;
+}
+
+atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, const atp_result &r, double cost_s) {
+    std::vector<int32_t> ty, rl;
+    std::vector<std::string> ps;
+    const std::string key = whole_key(c, q, ty, rl, ps);
+    if (key.empty()) return ATP_OK;
+    CacheState &cs = c->cache;
+    std::lock_guard<std::mutex> g(cs.mu);
+    if (cs.policy == ATP_CACHE_OFF || !cs.pol) return ATP_OK;
+    const int node = cs.tree->find(ty);
+    if (node >= 0) cs.tree->node(node).keys[key].f += 1;
+    const double bytes = 8.0 * (r.rows + 1) + 12.0 * r.nnz;
+    const int64_t id = admit_item(cs, key, ty, rl, ps, bytes, cost_s);
+    if (id < 0) return ATP_OK;
+    return store_copy(cs, L, id, r.rows, r.cols, r.nnz, r.rp.p, r.col.p, r.val.p);
 }
 
 atp_status lane_init(atp_ctx *c, Lane *L, int id) {

@@ -441,6 +441,10 @@ atp_status eval_query(atp_ctx *c, Lane *L, const QueryRef &q, const char *plan, 
 atp_status lane_init(atp_ctx *c, Lane *L, int id);
 void lane_destroy(Lane *L);
 void register_result(atp_ctx *c, atp_result *r);
+// workload cache, whole-query items (used by the batch layer): is q's result
+// cached; offer a result computed elsewhere (a fused batch member)
+bool cache_has_whole(atp_ctx *c, const QueryRef &q);
+atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, const atp_result &r, double cost_s);
 void release_pool_caches(atp_ctx *c);
 void server_shutdown(atp_ctx *c);
 

@@ -149,8 +149,30 @@ atp_result *new_result(atp_ctx *c, Lane *L, const atp_result &R) {
     return r;
 }
 
-// Evaluate one fusion group on lane L.
+void run_fused(atp_ctx *c, Lane *L, std::vector<Member *> &g);
+
+// Evaluate one fusion group on lane L.  With a cache, members whose whole
+// result is cached are answered from it; the others are fused.
 void run_group(atp_ctx *c, Lane *L, std::vector<Member *> &g) {
+    if (g.size() > 1) {
+        std::vector<Member *> rest;
+        for (Member *m : g) {
+            if (cache_has_whole(c, m->q)) {
+                m->batch = 1;
+                m->st = eval_query(c, L, m->q, nullptr, 1, &m->res);
+            } else {
+                rest.push_back(m);
+            }
+        }
+        if (rest.size() != g.size()) {
+            if (!rest.empty()) run_fused(c, L, rest);
+            return;
+        }
+    }
+    run_fused(c, L, g);
+}
+
+void run_fused(atp_ctx *c, Lane *L, std::vector<Member *> &g) {
     for (Member *m : g) m->batch = (int)g.size();
     auto alone = [&]() {
         for (Member *m : g) {
@@ -162,6 +184,7 @@ void run_group(atp_ctx *c, Lane *L, std::vector<Member *> &g) {
         alone();
         return;
     }
+    const auto t_0 = std::chrono::steady_clock::now();
     // the union of the start sets
     std::vector<int32_t> uni;
     for (Member *m : g) {
@@ -249,6 +272,9 @@ void run_group(atp_ctx *c, Lane *L, std::vector<Member *> &g) {
             register_result(c, outs[z]);
             g[z]->st = ATP_OK;
         }
+        // each member's result is a whole-query cache candidate of its own
+        const double share = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_0).count() / ng;
+        for (size_t z = 0; z < ng; ++z) (void)cache_offer_whole(c, L, g[z]->q, *outs[z], share);
     }
     if (t) t->flush();
     atp_result_free(R);

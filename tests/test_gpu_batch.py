@@ -263,3 +263,29 @@ def test_cost_model_calibration_keeps_results(atp, net, mixed):
     ctx.set_cost_model(start)
     assert ctx.cost_model() == pytest.approx(start)
     ctx.close()
+
+
+def test_fused_members_are_cached_as_whole_queries(atp, oracle_mod, net):
+    """With a cache, each fused member's rows are offered as that query's own
+    whole result; repeating the batch is answered from the cache."""
+    rng = np.random.default_rng(9)
+    qs = []
+    for z in range(8):
+        ids = np.array([int(rng.integers(net.counts["A"]))], np.int32)
+        qs.append(Query("A-P-V", ["A", "P", "V"],
+                        [Constraint(0, "idset", ids=ids), Constraint(1, "range", prop="year", lo=2010, hi=32767)]))
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    ctx.cache_configure(atp.ATP_CACHE_OTREE, 1 << 30)
+    first = [host(r) for r in ctx.eval_batch(qs, lanes=1, max_batch=8)]
+    st1 = ctx.cache_stats()
+    assert st1["inserts"] >= len({int(q.constraints[0].ids[0]) for q in qs})
+    again = [host(r) for r in ctx.eval_batch(qs, lanes=2, max_batch=8)]
+    st2 = ctx.cache_stats()
+    assert st2["whole_hits"] - st1["whole_hits"] == len(qs)
+    for q, a, b in zip(qs, first, again):
+        want = oracle_mod.eval_full(net, q)
+        assert same(a, b)
+        assert np.array_equal(a[0], want[0]) and np.array_equal(a[1], want[1])
+        assert np.array_equal(a[2], want[2].astype(np.int64))
+    ctx.close()
