@@ -1227,13 +1227,12 @@ __device__ __forceinline__ void bucket_chunk(const int64_t *chunk_base, int64_t 
     *q = id - chunk_base[lo];
 }
 
-// Products of X entries [e0, e1) of one row, eight lanes per X entry (short
-// right rows); f(tile, col, value) for each.
+// Products of X entries [e0, e1) of one row, g lanes per X entry (short
+// right rows; g a power of two); f(tile, col, value) for each.
 template <typename F>
-__device__ __forceinline__ void for_products(const Operand &X, const Operand &Y, int64_t e0, int64_t e1, F f) {
+__device__ __forceinline__ void for_products(const Operand &X, const Operand &Y, int64_t e0, int64_t e1, int g, F f) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int g = 8;  // lanes per X entry
-    const int gid = wave * (64 / g) + lane / g, ng = (blockDim.x / 64) * (64 / g), li = lane % g;
+    const int gid = wave * (64 / g) + lane / g, ng = (blockDim.x / 64) * (64 / g), li = lane & (g - 1);
     for (int64_t e = e0 + gid; e < e1; e += ng) {
         int32_t k = X.col[e];
         if (X.cmask && !bit_test(X.cmask, k)) continue;
@@ -1342,7 +1341,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, N
                 if (r.head) atomicAdd(&hist[tile], r.len);
             });
         else
-            for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+            for_products(a.X, a.Y, e0, e1, b.g, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
         __syncthreads();
         int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x)
@@ -1392,7 +1391,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
                 if (r.head) atomicAdd(&hist[tile], r.len);
             });
         else
-            for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+            for_products(a.X, a.Y, e0, e1, b.g, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
         __syncthreads();
         int64_t *cur = b.tile_cnt + p * (b.ntiles + 1);
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
@@ -1415,7 +1414,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
                 }
             });
         else
-            for_products(a.X, a.Y, e0, e1, [&](int64_t tile, int32_t j, uint64_t v) {
+            for_products(a.X, a.Y, e0, e1, b.g, [&](int64_t tile, int32_t j, uint64_t v) {
                 const int64_t pos = base[tile] + atomicAdd(&hist[tile], 1);
                 b.prod_col[pos] = j;
                 if (valued) b.prod_val[pos] = v;
