@@ -533,11 +533,17 @@ def main() -> int:
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "alg_bytes_per_launch": round(alg_bytes / launches, 1) if launches else None,
-                     "avg_launch_ms": round(ms_total / launches, 5) if launches else None},
+                     "avg_launch_ms": round(ms_total / launches, 5) if launches else None,
+                     # HBM traffic (counters) over the same launch time, and its share of peak
+                     "traffic_GBps": round(traffic / (ms_total / launches * 1e-3) / 1e9, 1)
+                     if traffic and launches else None,
+                     "traffic_frac": round(traffic / (ms_total / launches * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                     if traffic and launches else None},
         "kernels": per_kernel,
         "kernel_ms_per_step": round(kernel_ms / args.steps, 3),
         "plans": {k: v["plan"] for k, v in plans.items()},
         "n_op_per_step": int(sum(v["n_op"] for v in plans.values())),
+        "products_per_s": round(sum(v["n_op"] for v in plans.values()) / (elapsed / args.steps), 1),
         "nnz_result_per_step": int(sum(v["nnz"] for v in plans.values())),
     }
     if not args.no_cpu_baseline:
