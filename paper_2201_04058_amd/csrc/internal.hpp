@@ -172,7 +172,6 @@ void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row
                          hipStream_t s, KernelTimer *t);
 void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
                            hipStream_t s, KernelTimer *t);
-void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s);
 
 // row restriction: columns used by a left operand -> bitmap -> ascending list
 void launch_cols_to_bits(const int32_t *col, int64_t nnz, uint32_t *bits, hipStream_t s, KernelTimer *t);

@@ -1501,8 +1501,6 @@ __global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int6
     if (scan[c + 1] != scan[c]) active[scan[c]] = cand ? cand[c] : (int32_t)c;
 }
 
-__global__ void k_copy_i64(const int64_t *src, int64_t *dst) { *dst = *src; }
-
 // ---------------------------------------------------------------------------
 // rows of a fused batch result handed to one member query
 
@@ -1873,9 +1871,6 @@ void launch_bits_scatter(const uint32_t *bits, int64_t words, const int64_t *sca
                scan, list);
 }
 
-void launch_set_header_from_scan(const int64_t *scan_total, int64_t *dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, scan_total, dst);
-}
 
 void launch_gather_count(const int64_t *rrp, const int32_t *ids, int64_t n, int64_t *cnt, hipStream_t s,
                          KernelTimer *t) {
