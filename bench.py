@@ -177,12 +177,14 @@ def batch_mode(args) -> int:
         ctx.eval_query(q).free()
     t0 = time.perf_counter()
     plain_nnz, lat = [], []
-    for q in qs:
+    for z, q in enumerate(qs):
         tq = time.perf_counter()
         r = ctx.eval_query(q)
         plain_nnz.append(r.shape()[2])
         r.free()
         lat.append((time.perf_counter() - tq) * 1e3)
+        if (z + 1) % args.batch_chunk == 0:
+            log(f"  one at a time: {z + 1} of {len(qs)} done, {time.perf_counter() - t0:.1f} s")
     t_plain = time.perf_counter() - t0
     log(f"one at a time: {len(qs)} queries in {t_plain:.2f} s")
     tuned = fitted = None
@@ -196,20 +198,25 @@ def batch_mode(args) -> int:
         log(f"autotuned: {tuned}")
     ctx.eval_batch(qs[:8], lanes=args.lanes, max_batch=args.max_batch)
     t0 = time.perf_counter()
-    res = ctx.eval_batch(qs, lanes=args.lanes, max_batch=args.max_batch,
-                         mem_budget_bytes=int(args.admit_gb * (1 << 30)))
+    bad = []
+    for c0 in range(0, len(qs), args.batch_chunk):  # batches of batch_chunk queries, one after another
+        res = ctx.eval_batch(qs[c0:c0 + args.batch_chunk], lanes=args.lanes, max_batch=args.max_batch,
+                             mem_budget_bytes=int(args.admit_gb * (1 << 30)))
+        for z, r in enumerate(res, start=c0):
+            if isinstance(r, Exception) or r.shape()[2] != plain_nnz[z]:
+                bad.append(z)
+            if not isinstance(r, Exception):
+                r.free()
+        log(f"  batch: {min(c0 + args.batch_chunk, len(qs))} of {len(qs)} done, {time.perf_counter() - t0:.1f} s")
     t_batch = time.perf_counter() - t0
-    bad = [z for z, r in enumerate(res) if isinstance(r, Exception) or r.shape()[2] != plain_nnz[z]]
-    for r in res:
-        if not isinstance(r, Exception):
-            r.free()
     log(f"batch: {len(qs)} queries in {t_batch:.2f} s, mismatches {bad}")
     ctx.close()
     out = {"metric": "metapath queries/s (batch)", "value": round(len(qs) / t_batch, 3), "unit": "queries/s",
            "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
            "config": {"workload": args.workload + "-random-walks", "queries": len(qs), "lengths": [3, 7],
                       "start_set": [args.start_min, args.start_max], "selectivity": [0.01, 0.20],
-                      "lanes": args.lanes, "max_batch": args.max_batch, "admit_gb": args.admit_gb},
+                      "lanes": args.lanes, "max_batch": args.max_batch, "admit_gb": args.admit_gb,
+                      "batch_chunk": args.batch_chunk},
            "one_at_a_time": {"qps": round(len(qs) / t_plain, 3), "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99)},
            "vs_one_at_a_time": round(t_plain / t_batch, 3), "result_mismatches": len(bad), "autotuned": tuned,
            "cost_model": fitted}
@@ -400,6 +407,7 @@ def main() -> int:
     ap.add_argument("--calibrate", action="store_true", help="batch/serve: refit Eq. 2's coefficients first")
     ap.add_argument("--tune-queries", type=int, default=24)
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain-path run")
+    ap.add_argument("--batch-chunk", type=int, default=256, help="batch: queries per eval_batch call")
     ap.add_argument("--stream", default="walks", choices=["walks", "sessions"],
                     help="serve: extended schema walks with pooled constraints, or session queries")
     ap.add_argument("--queries", type=int, default=500, help="workload/batch/serve: queries")
