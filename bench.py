@@ -179,9 +179,12 @@ def batch_mode(args) -> int:
     plain_nnz, lat = [], []
     for z, q in enumerate(qs):
         tq = time.perf_counter()
-        r = ctx.eval_query(q)
-        plain_nnz.append(r.shape()[2])
-        r.free()
+        try:
+            r = ctx.eval_query(q)
+            plain_nnz.append(r.shape()[2])
+            r.free()
+        except atp.AtpError as e:  # e.g. a result larger than the device memory
+            plain_nnz.append(("error", e.status))
         lat.append((time.perf_counter() - tq) * 1e3)
         if (z + 1) % args.batch_chunk == 0:
             log(f"  one at a time: {z + 1} of {len(qs)} done, {time.perf_counter() - t0:.1f} s")
@@ -203,7 +206,8 @@ def batch_mode(args) -> int:
         res = ctx.eval_batch(qs[c0:c0 + args.batch_chunk], lanes=args.lanes, max_batch=args.max_batch,
                              mem_budget_bytes=int(args.admit_gb * (1 << 30)))
         for z, r in enumerate(res, start=c0):
-            if isinstance(r, Exception) or r.shape()[2] != plain_nnz[z]:
+            got = ("error", r.status) if isinstance(r, Exception) else r.shape()[2]
+            if got != plain_nnz[z]:
                 bad.append(z)
             if not isinstance(r, Exception):
                 r.free()
@@ -219,6 +223,8 @@ def batch_mode(args) -> int:
                       "batch_chunk": args.batch_chunk},
            "one_at_a_time": {"qps": round(len(qs) / t_plain, 3), "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99)},
            "vs_one_at_a_time": round(t_plain / t_batch, 3), "result_mismatches": len(bad), "autotuned": tuned,
+           "errors": sorted({int(x[1]) for x in plain_nnz if isinstance(x, tuple)}),
+           "n_errors": sum(1 for x in plain_nnz if isinstance(x, tuple)),
            "cost_model": fitted}
     print(json.dumps(out), flush=True)
     return 0 if not bad else 1
