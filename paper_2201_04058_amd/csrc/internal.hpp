@@ -15,7 +15,7 @@ constexpr int kTileShift = 13;
 constexpr int kTileW = 1 << kTileShift;
 constexpr int kDenseThreads = 512;
 constexpr int kCursorCap = 512;     // X entries whose cursors fit in LDS (multi-tile chunks)
-constexpr int64_t kTaskOps = 32768; // target products per dense task
+constexpr int64_t kTaskOps = 8192;  // target products per dense task
 constexpr int64_t kPartTarget = 1200;  // expected products per part of a sparse long row
 constexpr int64_t kPartHashCap = 2048; // a part with at most this many products uses an LDS hash
 constexpr int kPartMaxTiles = 16;      // ... if it spans at most this many tiles (its presence bitmap)
