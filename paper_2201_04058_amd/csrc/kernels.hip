@@ -313,24 +313,30 @@ __global__ void k_popcount(const uint32_t *bits, int64_t words, int64_t *out) {
 // ---------------------------------------------------------------------------
 // symbolic pass
 
-__global__ void k_symbolic(SymbolicArgs a) {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t nop = 0;
-    if (c < a.n_cand) {
+// Eight lanes per candidate row (they stride over its entries); rows longer
+// than kLongRow are left to the chunked pass.
+constexpr int kSymLanes = 8;
+__global__ __launch_bounds__(256) void k_symbolic(SymbolicArgs a) {
+    const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSymLanes;
+    const int li = threadIdx.x & (kSymLanes - 1);
+    int64_t nop = 0, deferred = 0;
+    if (c < a.n_cand) {  // uniform within the group
         const int64_t i = a.cand ? a.cand[c] : c;
-        int64_t deferred = 0;
         if (!(a.X.rmask && !bit_test(a.X.rmask, i))) {
             const int64_t b = a.X.rp[i], e = a.X.rp[i + 1];
             if (e - b > kLongRow) {
                 deferred = (e - b + kSymChunk - 1) / kSymChunk;
             } else {
-                for (int64_t p = b; p < e; ++p) {
+                for (int64_t p = b + li; p < e; p += kSymLanes) {
                     int32_t k = a.X.col[p];
                     if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
                     nop += a.Y.rp[k + 1] - a.Y.rp[k];
                 }
             }
         }
+    }
+    for (int d = kSymLanes / 2; d > 0; d >>= 1) nop += __shfl_xor(nop, d, kSymLanes);
+    if (c < a.n_cand && li == 0) {
         a.nop[c] = nop;
         a.long_len[c] = deferred;  // chunks left to the long-row pass
         // per-bin-list-position counts that the binning fills sparsely (scanned over all n_cand)
@@ -338,7 +344,7 @@ __global__ void k_symbolic(SymbolicArgs a) {
         a.bucket_chunks[c] = 0;
         a.bucket_nop[c] = 0;
     }
-    int64_t wsum = nop;
+    int64_t wsum = li == 0 ? nop : 0;
     for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
     if ((threadIdx.x & 63) == 0 && wsum) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)wsum);
 }
@@ -1734,8 +1740,9 @@ void launch_popcount(const uint32_t *bits, int64_t words, int64_t *out, hipStrea
 
 void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
     if (a.n_cand <= 0) return;
-    if ((a.n_cand + 255) / 256 > 0x7FFFFFFF) return;
-    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic, dim3((unsigned)((a.n_cand + 255) / 256)), dim3(256), 0, s, a);
+    const int64_t threads = a.n_cand * kSymLanes;
+    if ((threads + 255) / 256 > 0x7FFFFFFF) return;
+    ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
     launch_scan_i64(a.long_len, a.long_off, a.n_cand, a.scan_tmp, s, t);
     ATP_LAUNCH("symbolic", 0, 0, s, k_symbolic_long, dim3(device_cus() * 8), dim3(256), 0, s, a,
                (const int64_t *)a.long_off);
