@@ -889,6 +889,64 @@ __device__ __forceinline__ uint32_t hash_find_rt(int32_t *keys, int32_t j, int l
     }
 }
 
+// Emit a sparse part of row i (candidate c), columns [c0p, c1p): values in
+// an LDS hash of 2^log2s slots and presence in a bitmap over the part's
+// columns, both overlaid on the tile memory acc (keys, then values, then the
+// bitmap).  The bitmap is walked in column order and each column looked up;
+// the part becomes one segment at tile t0; the memory is cleared again.
+// Every thread of the block calls it.
+template <int NT>
+__device__ void emit_hash_part(const NumericArgs &a, int32_t c, int64_t i, int64_t t0, int64_t c0p, int64_t c1p,
+                               int log2s, unsigned long long *acc, uint32_t *satw, int64_t *sw, int64_t *s_base,
+                               int *s_sat) {
+    const int tid = threadIdx.x;
+    const int S = 1 << log2s;
+    int32_t *keys = reinterpret_cast<int32_t *>(acc);
+    unsigned long long *vals = acc + S / 2;
+    uint32_t *bm = reinterpret_cast<uint32_t *>(acc + S / 2 + S);
+    const int nwords = (int)((c1p - c0p + 31) / 32);
+    const int wpt = (nwords + NT - 1) / NT;  // words per thread, contiguous
+    const int w0 = tid * wpt, w1 = (w0 + wpt < nwords) ? w0 + wpt : nwords;
+    int64_t local = 0;
+    for (int w = w0; w < w1; ++w) local += __popc(bm[w]);
+    int64_t cnt;
+    const int64_t incl = block_inclusive_scan(local, sw, &cnt);
+    if (tid == 0) *s_base = (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)cnt);
+    __syncthreads();
+    const int64_t off = a.slot_off[c] + *s_base;
+    int64_t pos = off + incl - local;
+    bool sat = false;
+    const uint32_t hmask = (uint32_t)S - 1u;
+    for (int w = w0; w < w1; ++w) {
+        uint32_t bits = bm[w];
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1;
+            const int32_t col = (int32_t)(c0p + (int64_t)w * 32 + b);
+            uint32_t h = hash_of(col, log2s);
+            while (keys[h] != col) h = (h + 1) & hmask;
+            const bool sb = (satw[h >> 5] >> (h & 31)) & 1u;
+            sat |= sb;
+            a.slot_col[pos] = col;
+            a.slot_val[pos] = sb ? kSat : vals[h];
+            ++pos;
+        }
+    }
+    if (sat) *s_sat = 1;
+    if (tid == 0) {
+        const int64_t sg = a.seg_base[c] + t0;
+        a.seg_cnt[sg] = cnt;
+        a.seg_src[sg] = off;
+        atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)cnt);
+    }
+    __syncthreads();
+    // restore the all-zero tile memory and bitmaps
+    const int zero_words = S / 2 + S + (nwords + 1) / 2;
+    for (int t = tid; t < zero_words; t += NT) acc[t] = 0;
+    for (int t = tid; t < (S + 31) / 32; t += NT) satw[t] = 0;
+    __syncthreads();
+}
+
 // One task = one row and a part of m consecutive column tiles.  Each left
 // entry's segment of its right row inside the part is located (from the right
 // operand's tile index when there is one, else by binary search or the row
@@ -1089,7 +1147,6 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
             int32_t *keys = reinterpret_cast<int32_t *>(acc);
             unsigned long long *vals = acc + S / 2;
             uint32_t *bm = reinterpret_cast<uint32_t *>(acc + S / 2 + S);
-            const int nwords = (int)((c1p - c0p + 31) / 32);
             for (int t = tid; t < S; t += NT) keys[t] = kEmptyKey;  // vals and bm are already zero
             __syncthreads();
             for (int64_t eb = 0; eb < xlen; eb += NT) {
@@ -1103,46 +1160,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
                 });
                 __syncthreads();
             }
-            const int wpt = (nwords + NT - 1) / NT;  // words per thread, contiguous
-            const int w0 = tid * wpt, w1 = (w0 + wpt < nwords) ? w0 + wpt : nwords;
-            int64_t local = 0;
-            for (int w = w0; w < w1; ++w) local += __popc(bm[w]);
-            int64_t cnt;
-            const int64_t incl = block_inclusive_scan(local, sw, &cnt);
-            if (tid == 0) s_base = (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)cnt);
-            __syncthreads();
-            const int64_t off = a.slot_off[c] + s_base;
-            int64_t pos = off + incl - local;
-            bool sat = false;
-            const uint32_t hmask = (uint32_t)S - 1u;
-            for (int w = w0; w < w1; ++w) {
-                uint32_t bits = bm[w];
-                while (bits) {
-                    const int b = __builtin_ctz(bits);
-                    bits &= bits - 1;
-                    const int32_t col = (int32_t)(c0p + (int64_t)w * 32 + b);
-                    uint32_t h = hash_of(col, log2s);
-                    while (keys[h] != col) h = (h + 1) & hmask;
-                    const bool sb = (satw[h >> 5] >> (h & 31)) & 1u;
-                    sat |= sb;
-                    a.slot_col[pos] = col;
-                    a.slot_val[pos] = sb ? kSat : vals[h];
-                    ++pos;
-                }
-            }
-            if (sat) s_sat = 1;
-            if (tid == 0) {
-                const int64_t sg = a.seg_base[c] + t0;
-                a.seg_cnt[sg] = cnt;
-                a.seg_src[sg] = off;
-                atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)cnt);
-            }
-            __syncthreads();
-            // restore the all-zero tile memory and bitmaps
-            const int zero_words = S / 2 + S + (nwords + 1) / 2;
-            for (int t = tid; t < zero_words; t += NT) acc[t] = 0;
-            for (int t = tid; t < (S + 31) / 32; t += NT) satw[t] = 0;
-            __syncthreads();
+            emit_hash_part<NT>(a, c, i, t0, c0p, c1p, log2s, acc, satw, sw, &s_base, &s_sat);
             continue;
         }
 
@@ -1448,28 +1466,65 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
     if (tid == 0) s_sat = 0;
     __syncthreads();
     const int64_t n_tasks = b.n_list * b.ntiles;
+    const bool valued = b.prod_val != nullptr;
     for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
         const int64_t p = task / b.ntiles, t = task % b.ntiles;
+        // parts of m consecutive tiles, m from the row's mean products per tile
+        const int64_t nop = b.prod_base[p + 1] - b.prod_base[p];
+        const int64_t per_tile = nop / b.ntiles;
+        int64_t m = 1;
+        if (per_tile < a.tune.part_target) {
+            m = a.tune.part_target / (per_tile > 0 ? per_tile : 1);
+            m = m > kPartMaxTiles ? kPartMaxTiles : (m < 1 ? 1 : m);
+        }
+        if (t % m) continue;  // the task of the part's first tile does the part
+        const int64_t t1 = (t + m < b.ntiles) ? t + m : b.ntiles;
         const int64_t *off = b.tile_off + p * (b.ntiles + 1);
-        const int64_t lo = off[t], hi = off[t + 1];
-        if (lo == hi) continue;  // uniform across the block
+        if (off[t] == off[t1]) continue;  // uniform across the block
         const int32_t c = b.list[p];
         const int64_t i = a.cand ? a.cand[c] : c;
-        const int64_t c0 = t * W;
-        const bool valued = b.prod_val != nullptr;
-        const bool sparse = (hi - lo) < (int64_t)(W / 4);  // block-uniform
-        for (int64_t e = lo + tid; e < hi; e += kDenseThreads) {
-            const uint32_t slot = (uint32_t)(b.prod_col[e] - c0);
-            const uint64_t v = valued ? b.prod_val[e] : 1ull;
-            if (sparse) atomicOr(&pres[slot >> 5], 1u << (slot & 31));
-            acc_add(&acc[slot], satw, slot, v);
+        if (t1 - t > 1 && off[t1] - off[t] <= a.tune.part_hash_cap) {
+            // a sparse part: one LDS hash over its columns (as the dense kernel's hash parts)
+            const int64_t c0p = t * W, c1p = (t1 * W < a.ycols) ? t1 * W : a.ycols;
+            const int64_t ltot = off[t1] - off[t];
+            int log2s = 6;
+            while ((int64_t(1) << log2s) < 2 * ltot) ++log2s;
+            const int S = 1 << log2s;
+            int32_t *keys = reinterpret_cast<int32_t *>(acc);
+            unsigned long long *vals = acc + S / 2;
+            uint32_t *bm = reinterpret_cast<uint32_t *>(acc + S / 2 + S);
+            for (int q = tid; q < S; q += kDenseThreads) keys[q] = kEmptyKey;  // vals and bm are zero
+            __syncthreads();
+            for (int64_t e = off[t] + tid; e < off[t1]; e += kDenseThreads) {
+                const int32_t j = b.prod_col[e];
+                const uint64_t v = valued ? b.prod_val[e] : 1ull;
+                const uint32_t h = hash_find_rt(keys, j, log2s);
+                acc_add(&vals[h], satw, h, v);
+                const int64_t r = j - c0p;
+                atomicOr(&bm[r >> 5], 1u << (r & 31));
+            }
+            __syncthreads();
+            emit_hash_part<kDenseThreads>(a, c, i, t, c0p, c1p, log2s, acc, satw, sw, &s_base, &s_sat);
+            continue;
         }
-        __syncthreads();
-        if (sparse)
-            emit_sparse_tile(a, c, i, t, c0, acc, pres, satw, sw, &s_base, &s_sat);
-        else
-            emit_dense_tile(a, c, i, t, c0, acc, satw, gcnt, sw, &s_base, &s_sat);
-        __syncthreads();
+        for (int64_t tt = t; tt < t1; ++tt) {  // tile by tile
+            const int64_t lo = off[tt], hi = off[tt + 1];
+            if (lo == hi) continue;  // uniform across the block
+            const int64_t c0 = tt * W;
+            const bool sparse = (hi - lo) < (int64_t)(W / 4);  // block-uniform
+            for (int64_t e = lo + tid; e < hi; e += kDenseThreads) {
+                const uint32_t slot = (uint32_t)(b.prod_col[e] - c0);
+                const uint64_t v = valued ? b.prod_val[e] : 1ull;
+                if (sparse) atomicOr(&pres[slot >> 5], 1u << (slot & 31));
+                acc_add(&acc[slot], satw, slot, v);
+            }
+            __syncthreads();
+            if (sparse)
+                emit_sparse_tile(a, c, i, tt, c0, acc, pres, satw, sw, &s_base, &s_sat);
+            else
+                emit_dense_tile(a, c, i, tt, c0, acc, satw, gcnt, sw, &s_base, &s_sat);
+            __syncthreads();
+        }
     }
     __syncthreads();
     if (tid == 0 && s_sat) atomicOr(&a.hdr->saturated, 1);
