@@ -1828,7 +1828,7 @@ void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const Nume
             ATP_LAUNCH("hash_block", 0, 0, s, (k_hash_block<4096, 512>), waves(1), dim3(512), 0, s, list, n, a);
             break;
         case BIN_B8192:
-            ATP_LAUNCH("hash_block", 0, 0, s, (k_hash_block<8192, 512>), waves(1), dim3(512), 0, s, list, n, a);
+            ATP_LAUNCH("hash_block", 0, 0, s, (k_hash_block<8192, 1024>), waves(1), dim3(1024), 0, s, list, n, a);
             break;
         default: break;
     }
