@@ -189,7 +189,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     TRY(bucket_nop.alloc(pool, 8 * n_cand));
     TRY(chunk_base.alloc(pool, 8 * (n_cand + 1)));
     TRY(prod_base.alloc(pool, 8 * (n_cand + 1)));
-    const int64_t tmp_n = std::max(5 * scan_tmp_elems(n_cand), scan_tmp_elems(Z.rows));
+    const int64_t tmp_n = 5 * scan_tmp_elems(n_cand);
     TRY(tmp.alloc(pool, 8 * tmp_n));
 
     StepHeader *d_hdr = hdr.as<StepHeader>();
@@ -217,12 +217,12 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     sa.tune = c->tune;
     launch_symbolic(sa, s, t);
     launch_bin_rows(sa, s, t);
-    const ScanJob jobs[5] = {{ub.as<int64_t>(), slot_off.as<int64_t>(), &d_hdr->slots_total},
-                             {nseg.as<int64_t>(), seg_base.as<int64_t>(), &d_hdr->segs_total},
-                             {dense_chunks.as<int64_t>(), task_base.as<int64_t>(), &d_hdr->dense_tasks},
-                             {bucket_chunks.as<int64_t>(), chunk_base.as<int64_t>(), &d_hdr->bucket_chunks},
-                             {bucket_nop.as<int64_t>(), prod_base.as<int64_t>(), &d_hdr->bucket_products}};
-    launch_scan_multi(jobs, 5, n_cand, tmp.as<int64_t>(), s, t);
+    const ScanJob jobs[5] = {{ub.as<int64_t>(), slot_off.as<int64_t>(), &d_hdr->slots_total, n_cand},
+                             {nseg.as<int64_t>(), seg_base.as<int64_t>(), &d_hdr->segs_total, n_cand},
+                             {dense_chunks.as<int64_t>(), task_base.as<int64_t>(), &d_hdr->dense_tasks, n_cand},
+                             {bucket_chunks.as<int64_t>(), chunk_base.as<int64_t>(), &d_hdr->bucket_chunks, n_cand},
+                             {bucket_nop.as<int64_t>(), prod_base.as<int64_t>(), &d_hdr->bucket_products, n_cand}};
+    launch_scan_multi(jobs, 5, tmp.as<int64_t>(), s, t);
     TRY(read_header(L, d_hdr));
     const StepHeader h1 = *L->h_hdr;
     st.n_op += h1.n_op_total;
@@ -243,9 +243,9 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     TRY(seg_dst.alloc(pool, 8 * ((size_t)h1.segs_total + 1)));
     TRY(row_cursor.alloc(pool, 8 * n_cand));
     TRY(row_nnz.alloc(pool, 8 * (size_t)Z.rows));
-    launch_fill_i64(seg_cnt.as<int64_t>(), h1.segs_total, 0, s, t);
-    launch_fill_i64(row_cursor.as<int64_t>(), n_cand, 0, s, t);
-    launch_fill_i64(row_nnz.as<int64_t>(), Z.rows, 0, s, t);
+    const FillJob zero[3] = {{seg_cnt.as<int64_t>(), h1.segs_total, 0}, {row_cursor.as<int64_t>(), n_cand, 0},
+                             {row_nnz.as<int64_t>(), Z.rows, 0}};
+    launch_fill_multi(zero, 3, s, t);
 
     NumericArgs na{};
     na.X = X.op;
@@ -314,19 +314,22 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     if (c->flags & ATP_OPT_COUNT_BYTES) TRY(count_bytes(c, L, X, Y, cand, bin_lists.as<int32_t>(), n_cand, h1,
                                                        row_nnz.as<int64_t>()));
 
-    // row pointers over every row of X; segment destinations in (row, tile) order
-    launch_scan_i64(row_nnz.as<int64_t>(), Z.rp.as<int64_t>(), Z.rows, tmp.as<int64_t>(), s, t, &d_hdr->nnz_total);
-    Buf tmp_seg;
-    TRY(tmp_seg.alloc(pool, 8 * (size_t)scan_tmp_elems(h1.segs_total)));
-    launch_scan_i64(seg_cnt.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total, tmp_seg.as<int64_t>(), s, t);
+    // row pointers over every row of X, segment destinations in (row, tile)
+    // order and (for a left operand) the non-empty rows: one scan sequence
     Buf flags, flags_scan;
+    ScanJob jobs2[3] = {{row_nnz.as<int64_t>(), Z.rp.as<int64_t>(), &d_hdr->nnz_total, Z.rows},
+                        {seg_cnt.as<int64_t>(), seg_dst.as<int64_t>(), nullptr, h1.segs_total},
+                        {nullptr, nullptr, nullptr, 0}};
+    int n_jobs2 = 2;
     if (need_active) {
         TRY(flags.alloc(pool, 8 * n_cand));
         TRY(flags_scan.alloc(pool, 8 * (n_cand + 1)));
         launch_active_flags(cand, n_cand, row_nnz.as<int64_t>(), flags.as<int64_t>(), s, t);
-        launch_scan_i64(flags.as<int64_t>(), flags_scan.as<int64_t>(), n_cand, tmp.as<int64_t>(), s, t,
-                        &d_hdr->n_active);
+        jobs2[n_jobs2++] = ScanJob{flags.as<int64_t>(), flags_scan.as<int64_t>(), &d_hdr->n_active, n_cand};
     }
+    Buf tmp2;
+    TRY(tmp2.alloc(pool, 8 * (size_t)scan_multi_tmp_elems(jobs2, n_jobs2)));
+    launch_scan_multi(jobs2, n_jobs2, tmp2.as<int64_t>(), s, t);
     TRY(read_header(L, d_hdr));
     const StepHeader h2 = *L->h_hdr;
     saturated = h2.saturated != 0;

@@ -87,17 +87,27 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s, KernelTi
 int64_t scan_tmp_elems(int64_t n);
 void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s,
                      KernelTimer *t, int64_t *total = nullptr);
-// up to kMaxScanJobs scans of the same length in one launch sequence; tmp
-// holds n_jobs * scan_tmp_elems(n) int64.  Arrays of at most
-// kSmallScanTiles * 2048 elements take a single launch.
+// up to kMaxScanJobs scans in one launch sequence; tmp holds
+// scan_multi_tmp_elems(jobs) int64.  When every array has at most
+// kSmallScanTiles * 2048 elements the sequence is a single launch.
 constexpr int kMaxScanJobs = 8;
 constexpr int64_t kSmallScanTiles = 8;
 struct ScanJob {
     const int64_t *in;
-    int64_t *out;
+    int64_t *out;    // n + 1 entries
     int64_t *total;  // optional
+    int64_t n;
 };
-void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t);
+int64_t scan_multi_tmp_elems(const ScanJob *jobs, int n_jobs);
+void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t *tmp, hipStream_t s, KernelTimer *t);
+// up to kMaxFillJobs int64 fills in one launch
+constexpr int kMaxFillJobs = 4;
+struct FillJob {
+    int64_t *p;
+    int64_t n;
+    int64_t v;
+};
+void launch_fill_multi(const FillJob *jobs, int n_jobs, hipStream_t s, KernelTimer *t);
 
 // masks
 void launch_mask_range(const void *prop, int32_t dtype, int64_t n, int64_t lo, int64_t hi,

@@ -185,20 +185,26 @@ __device__ int64_t block_inclusive_scan(int64_t x, int64_t *smem_waves, int64_t 
 // Several scans of the same length in one launch sequence: job = blockIdx.y.
 struct ScanJobs {
     ScanJob job[kMaxScanJobs];
-    int64_t n;
     int64_t stride;  // tmp entries per job
 };
 
+__device__ __forceinline__ int64_t scan_blocks(int64_t n) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return nb > 0 ? nb : 1;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(ScanJobs sj, int64_t *tmp) {
     __shared__ int64_t sw[kScanThreads / 64];
-    const int64_t *in = sj.job[blockIdx.y].in;
+    const ScanJob &j = sj.job[blockIdx.y];
+    if ((int64_t)blockIdx.x >= scan_blocks(j.n)) return;  // uniform: this job has fewer tiles
+    const int64_t *in = j.in;
     int64_t *t = tmp + blockIdx.y * sj.stride;
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     int64_t s = 0;
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         int64_t i = base + (int64_t)r * kScanThreads + threadIdx.x;
-        if (i < sj.n) s += in[i];
+        if (i < j.n) s += in[i];
     }
     int64_t tot;
     block_inclusive_scan(s, sw, &tot);
@@ -206,9 +212,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(ScanJobs sj, int64
 }
 
 // exclusive scan of tmp[0..nb) in place, tmp[nb] = total; one block per job
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *tmp, int64_t nb, int64_t stride) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(ScanJobs sj, int64_t *tmp) {
     __shared__ int64_t sw[kScanThreads / 64];
-    int64_t *t = tmp + blockIdx.x * stride;
+    const int64_t nb = scan_blocks(sj.job[blockIdx.x].n);
+    int64_t *t = tmp + blockIdx.x * sj.stride;
     int64_t carry = 0;
     for (int64_t base = 0; base < nb; base += kScanThreads) {
         int64_t i = base + threadIdx.x;
@@ -246,13 +253,15 @@ __device__ __forceinline__ int64_t scan_tile(const ScanJob &j, int64_t n, int64_
 }
 
 // per block: exclusive scan of its tile with offset tmp[block]
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(ScanJobs sj, const int64_t *tmp, int64_t nb) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(ScanJobs sj, const int64_t *tmp) {
     __shared__ int64_t sw[kScanThreads / 64];
     const ScanJob &j = sj.job[blockIdx.y];
+    const int64_t nb = scan_blocks(j.n);
+    if ((int64_t)blockIdx.x >= nb) return;  // uniform
     const int64_t *t = tmp + blockIdx.y * sj.stride;
-    scan_tile(j, sj.n, (int64_t)blockIdx.x * kScanTile, t[blockIdx.x], sw);
+    scan_tile(j, j.n, (int64_t)blockIdx.x * kScanTile, t[blockIdx.x], sw);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        j.out[sj.n] = t[nb];
+        j.out[j.n] = t[nb];
         if (j.total) *j.total = t[nb];
     }
 }
@@ -262,9 +271,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_small(ScanJobs sj) {
     __shared__ int64_t sw[kScanThreads / 64];
     const ScanJob &j = sj.job[blockIdx.x];
     int64_t carry = 0;
-    for (int64_t base = 0; base < sj.n; base += kScanTile) carry += scan_tile(j, sj.n, base, carry, sw);
+    for (int64_t base = 0; base < j.n; base += kScanTile) carry += scan_tile(j, j.n, base, carry, sw);
     if (threadIdx.x == 0) {
-        j.out[sj.n] = carry;
+        j.out[j.n] = carry;
         if (j.total) *j.total = carry;
     }
 }
@@ -1737,11 +1746,21 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s, KernelTi
 
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 2; }
 
-void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t) {
-    if (n_jobs < 1 || n_jobs > kMaxScanJobs || n < 0) return;
+int64_t scan_multi_tmp_elems(const ScanJob *jobs, int n_jobs) {
+    int64_t n = 0;
+    for (int z = 0; z < n_jobs; ++z) n = std::max(n, jobs[z].n);
+    return n_jobs * scan_tmp_elems(n);
+}
+
+void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t *tmp, hipStream_t s, KernelTimer *t) {
+    if (n_jobs < 1 || n_jobs > kMaxScanJobs) return;
     ScanJobs sj{};
-    for (int z = 0; z < n_jobs; ++z) sj.job[z] = jobs[z];
-    sj.n = n;
+    int64_t n = 0;
+    for (int z = 0; z < n_jobs; ++z) {
+        if (jobs[z].n < 0) return;
+        sj.job[z] = jobs[z];
+        n = std::max(n, jobs[z].n);
+    }
     sj.stride = scan_tmp_elems(n);
     const int64_t nb = std::max<int64_t>((n + kScanTile - 1) / kScanTile, 1);
     if (nb <= kSmallScanTiles) {
@@ -1750,15 +1769,37 @@ void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t n, int64_t *tmp,
     }
     ATP_LAUNCH("scan", 0, 0, s, k_scan_reduce, dim3((unsigned)nb, (unsigned)n_jobs), dim3(kScanThreads), 0, s, sj,
                tmp);
-    ATP_LAUNCH("scan", 0, 0, s, k_scan_top, dim3((unsigned)n_jobs), dim3(kScanThreads), 0, s, tmp, nb, sj.stride);
+    ATP_LAUNCH("scan", 0, 0, s, k_scan_top, dim3((unsigned)n_jobs), dim3(kScanThreads), 0, s, sj, tmp);
     ATP_LAUNCH("scan", 0, 0, s, k_scan_down, dim3((unsigned)nb, (unsigned)n_jobs), dim3(kScanThreads), 0, s, sj,
-               (const int64_t *)tmp, nb);
+               (const int64_t *)tmp);
 }
 
 void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s, KernelTimer *t,
                      int64_t *total) {
-    const ScanJob j{in, out, total};
-    launch_scan_multi(&j, 1, n, tmp, s, t);
+    const ScanJob j{in, out, total, n};
+    launch_scan_multi(&j, 1, tmp, s, t);
+}
+
+// several int64 fills in one launch (job = blockIdx.y)
+struct FillJobs {
+    FillJob job[kMaxFillJobs];
+};
+__global__ void k_fill_multi(FillJobs fj) {
+    const FillJob &j = fj.job[blockIdx.y];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < j.n; i += (int64_t)gridDim.x * blockDim.x)
+        j.p[i] = j.v;
+}
+
+void launch_fill_multi(const FillJob *jobs, int n_jobs, hipStream_t s, KernelTimer *t) {
+    if (n_jobs < 1 || n_jobs > kMaxFillJobs) return;
+    FillJobs fj{};
+    int64_t n = 0;
+    for (int z = 0; z < n_jobs; ++z) {
+        fj.job[z] = jobs[z];
+        n = std::max(n, jobs[z].n);
+    }
+    if (n <= 0) return;
+    ATP_LAUNCH("fill", 0, 0, s, k_fill_multi, dim3(grid_for(n, 256, 4096), (unsigned)n_jobs), dim3(256), 0, s, fj);
 }
 
 void launch_mask_range(const void *prop, int32_t dtype, int64_t n, int64_t lo, int64_t hi, uint32_t *bits,
