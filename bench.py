@@ -340,10 +340,11 @@ def serve_mode(args) -> int:
 
 
 def costfit_mode(args) -> int:
-    """Eq. 2 refit: time every multiplication of a calibration sample (random
-    schema walks of another seed), fit alpha, beta, gamma, delta, and compare
-    plans and times of the workload's queries and of a held-out sample under
-    the default and the fitted coefficients."""
+    """Planner ablations: the paper's E_ac estimator against the degree-sketch
+    estimator, and the Eq. 2 refit -- time every multiplication of a
+    calibration sample (random schema walks of another seed), fit alpha,
+    beta, gamma, delta, and compare plans and times of the workload's queries
+    and of a held-out sample under the default and the fitted coefficients."""
     import paper_2201_04058_amd as atp
     from synth import configs, workload
 
@@ -368,6 +369,10 @@ def costfit_mode(args) -> int:
         return best * 1e3, plans
 
     default = ctx.cost_model()
+    ctx.set_flags(plan_eac=True)  # the paper's uniform E_ac estimator (Sec. 3.2)
+    we, wpe = run(queries)
+    he, hpe = run(held, reps=1)
+    ctx.set_flags()
     w0, wp0 = run(queries)
     h0, hp0 = run(held, reps=1)
     fit = ctx.calibrate_cost_model(calib)
@@ -383,7 +388,10 @@ def costfit_mode(args) -> int:
            "workload_ms": {"default": round(w0, 3), "fitted": round(w1, 3)},
            "workload_plans": {q.name: [a, b] for q, a, b in zip(queries, wp0, wp1)},
            "held_out_ms": {"default": round(h0, 3), "fitted": round(h1, 3)},
-           "held_out_plans_changed": sum(1 for a, b in zip(hp0, hp1) if a != b)}
+           "held_out_plans_changed": sum(1 for a, b in zip(hp0, hp1) if a != b),
+           "estimators": {"eac": {"workload_ms": round(we, 3), "held_out_ms": round(he, 3),
+                                  "workload_plans": {q.name: p for q, p in zip(queries, wpe)}},
+                          "sketch": {"workload_ms": round(w0, 3), "held_out_ms": round(h0, 3)}}}
     print(json.dumps(out), flush=True)
     return 0
 
