@@ -81,6 +81,11 @@ struct Mat {
     bool view = false;                    // a cached result, not owned
     const int32_t *cand = nullptr;  // leaf: candidate rows from an id-set constraint
     int64_t n_cand = 0;
+    // a product whose size was not read back: nnz is an upper bound (the
+    // arrays' capacity), the true count is at nnz_dev in the kept header, and
+    // the active list holds every candidate row, non-empty ones first
+    Buf hdr;
+    const int64_t *nnz_dev = nullptr;
 };
 
 struct PosMask {
@@ -134,8 +139,11 @@ atp_status count_bytes(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, const in
 // Z = X * Y, one product of the plan (Sec. 3.2).  ycols_eff bounds the
 // columns that can occur (mask popcount of Y's last position, or Y's width).
 // need_active: Z will be the left operand of a later product.
+// defer: Z is an intermediate (not the result, no cache): its sizes are not
+// read back (no host synchronisation after the numeric phase); its true
+// nonzero count is added to *nnz_acc on the device.
 atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols_eff, bool need_active, Mat &Z,
-                  StepStats &st, bool &saturated) {
+                  StepStats &st, bool &saturated, bool defer, int64_t *nnz_acc) {
     Pool *pool = &L->pool;
     hipStream_t s = L->stream;
     KernelTimer *t = c->kt(L);
@@ -330,21 +338,40 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     Buf tmp2;
     TRY(tmp2.alloc(pool, 8 * (size_t)scan_multi_tmp_elems(jobs2, n_jobs2)));
     launch_scan_multi(jobs2, n_jobs2, tmp2.as<int64_t>(), s, t);
-    TRY(read_header(L, d_hdr));
-    const StepHeader h2 = *L->h_hdr;
-    saturated = h2.saturated != 0;
-    Z.nnz = h2.nnz_total;
-    st.nnz += Z.nnz;
-    TRY(Z.col.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.nnz, 1)));
-    TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
-    launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
-                         slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
-                         Z.val.as<uint64_t>(), s, t);
-    if (need_active) {
-        Z.n_active = h2.n_active;
-        TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.n_active, 1)));
-        Z.active_ptr = Z.active.as<int32_t>();
-        launch_active_scatter(cand, n_cand, flags_scan.as<int64_t>(), Z.active.as<int32_t>(), s, t);
+    if (defer) {
+        // capacities from the symbolic bounds; the counts stay on the device
+        Z.nnz = h1.slots_total;
+        TRY(Z.col.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.nnz, 1)));
+        TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
+        launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
+                             slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
+                             Z.val.as<uint64_t>(), s, t);
+        if (need_active) {
+            Z.n_active = n_cand;
+            TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(n_cand, 1)));
+            Z.active_ptr = Z.active.as<int32_t>();
+            launch_active_scatter(cand, n_cand, flags_scan.as<int64_t>(), Z.active.as<int32_t>(), true, s, t);
+        }
+        if (nnz_acc) launch_accum_i64(&d_hdr->nnz_total, nnz_acc, s);
+        Z.nnz_dev = &d_hdr->nnz_total;
+        Z.hdr = std::move(hdr);
+    } else {
+        TRY(read_header(L, d_hdr));
+        const StepHeader h2 = *L->h_hdr;
+        saturated = h2.saturated != 0;
+        Z.nnz = h2.nnz_total;
+        st.nnz += Z.nnz;
+        TRY(Z.col.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.nnz, 1)));
+        TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
+        launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
+                             slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
+                             Z.val.as<uint64_t>(), s, t);
+        if (need_active) {
+            Z.n_active = h2.n_active;
+            TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.n_active, 1)));
+            Z.active_ptr = Z.active.as<int32_t>();
+            launch_active_scatter(cand, n_cand, flags_scan.as<int64_t>(), Z.active.as<int32_t>(), false, s, t);
+        }
     }
     Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
                    Z.rows, Z.cols, Z.nnz};
@@ -884,6 +911,22 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         if (nd.block_lo >= 0) return {nd.block_lo, nd.block_hi};
         return {span(nd.left).first, span(nd.right).second};
     };
+    // a product whose right operand is itself a product: its rows can be
+    // restricted to the left operand's columns (a base relation's rows are
+    // only read where the left operand points, so it gains nothing)
+    auto internal = [&](int v) { return tree[v].leaf < 0 && tree[v].block_lo < 0; };
+    std::vector<char> feeds_restriction(tree.size(), 0);
+    for (size_t v = 0; v < tree.size(); ++v)
+        if (restrict_rows && internal((int)v) && internal(tree[v].right)) feeds_restriction[tree[v].left] = 1;
+    // intermediates whose sizes stay on the device (no read-back per product):
+    // not the result, not kept by the cache, not timed or byte-counted, and not
+    // a left operand whose size decides a restriction
+    const bool may_defer = !caching && !(c->flags & ATP_OPT_COUNT_BYTES) && !c->cost_sink;
+    Buf nnz_acc;
+    if (may_defer && p >= 3) {
+        TRY(nnz_acc.alloc(&L->pool, 8));
+        launch_fill_i64(nnz_acc.as<int64_t>(), 1, 0, s, t);
+    }
     // Rows of a right sub-chain that can matter: the columns its left neighbour uses.
     struct Restriction {
         const uint32_t *bits = nullptr;
@@ -906,7 +949,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
             launch_leaf_cols_to_bits(X.op, X.cand, X.n_cand, len.as<int64_t>(), off.as<int64_t>(), tmpc.as<int64_t>(),
                                      bits.as<uint32_t>(), s, t);
         } else
-            launch_cols_to_bits(X.op.col, X.nnz, bits.as<uint32_t>(), s, t);
+            launch_cols_to_bits(X.op.col, X.nnz, X.nnz_dev, bits.as<uint32_t>(), s, t);
         launch_bits_count(bits.as<uint32_t>(), words, cnt.as<int64_t>(), scan.as<int64_t>(), tmpb.as<int64_t>(), s, t);
         int64_t n = 0;
         HIPTRY(hipMemcpyAsync(&n, scan.as<int64_t>() + words, 8, hipMemcpyDeviceToHost, s));
@@ -993,7 +1036,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         // query) is computed on all its rows so that its result can be kept
         const std::pair<int, int> ysp = span(nd.right);
         const bool keep_whole = caching && ysp.second > ysp.first && freq[ysp.first][ysp.second] >= 2;
-        if (restrict_rows && x_small && !keep_whole) {
+        if (restrict_rows && x_small && !keep_whole && internal(nd.right)) {
             TRY(make_restriction(X, y_rows, r2));
             rp = &r2;
         }
@@ -1013,7 +1056,8 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
             HIPTRY(hipEventCreate(&rec.e1));
             HIPTRY(hipEventRecord(rec.e0, s));
         }
-        TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat));
+        const bool defer = may_defer && v != forced_root && !feeds_restriction[v];
+        TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat, defer, nnz_acc.as<int64_t>()));
         if (c->cost_sink) {
             HIPTRY(hipEventRecord(rec.e1, s));
             rec.n_op = (double)st.n_op - rec.n_op;
@@ -1047,7 +1091,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         X.n_cand = leaves[0].n_cand;
         ident.op.cmask = leaves[0].op.cmask;
         bool sat = false;
-        stt = spgemm(c, L, X, ident, ycols_eff, false, R, st, sat);
+        stt = spgemm(c, L, X, ident, ycols_eff, false, R, st, sat, false, nullptr);
         n_products = 1;
         overflow = sat;
     } else if (caching && tree[forced_root].block_lo == 0 && tree[forced_root].block_hi == p - 1) {
@@ -1086,7 +1130,11 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         (void)hipStreamSynchronize(s);
         return stt;
     }
+    // the deferred count comes back through the lane's pinned header, which
+    // the last product has finished reading
+    if (nnz_acc.p) HIPTRY(hipMemcpyAsync(L->h_hdr, nnz_acc.p, 8, hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
+    if (nnz_acc.p) st.nnz += *(const int64_t *)L->h_hdr;
     if (t) t->flush();
     if (c->cost_sink && !cost_recs.empty()) {
         std::lock_guard<std::mutex> g(c->stat_mu);

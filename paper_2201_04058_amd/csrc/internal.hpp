@@ -180,11 +180,17 @@ void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const 
                           hipStream_t s, KernelTimer *t);
 void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row_nnz, int64_t *flags,
                          hipStream_t s, KernelTimer *t);
+// the non-empty candidate rows in order; with partition the empty ones
+// follow, so that `active` holds n_cand rows
 void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
-                           hipStream_t s, KernelTimer *t);
+                           bool partition, hipStream_t s, KernelTimer *t);
+// *dst += *src on the stream
+void launch_accum_i64(const int64_t *src, int64_t *dst, hipStream_t s);
 
 // row restriction: columns used by a left operand -> bitmap -> ascending list
-void launch_cols_to_bits(const int32_t *col, int64_t nnz, uint32_t *bits, hipStream_t s, KernelTimer *t);
+// nnz_dev (optional) holds the true entry count on the device, nnz its upper bound
+void launch_cols_to_bits(const int32_t *col, int64_t nnz, const int64_t *nnz_dev, uint32_t *bits, hipStream_t s,
+                         KernelTimer *t);
 // len/off hold n_cand (+1) int64, tmp scan_tmp_elems(n_cand)
 void launch_leaf_cols_to_bits(const Operand &X, const int32_t *cand, int64_t n_cand, int64_t *len, int64_t *off,
                               int64_t *tmp, uint32_t *bits, hipStream_t s, KernelTimer *t);

@@ -1565,11 +1565,21 @@ __global__ void k_active_flags(const int32_t *cand, int64_t n_cand, const int64_
     flags[c] = row_nnz[i] > 0 ? 1 : 0;
 }
 
-__global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *scan, int32_t *active) {
+// non-empty rows first (ascending); with `partition` the empty ones follow
+// (ascending), so the list has n_cand entries
+__global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *scan, int32_t *active,
+                                 int partition) {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= n_cand) return;
-    if (scan[c + 1] != scan[c]) active[scan[c]] = cand ? cand[c] : (int32_t)c;
+    const int32_t row = cand ? cand[c] : (int32_t)c;
+    if (scan[c + 1] != scan[c])
+        active[scan[c]] = row;
+    else if (partition)
+        active[scan[n_cand] + (c - scan[c])] = row;
 }
+
+// *dst += *src (one value; per-query statistics kept on the device)
+__global__ void k_accum_i64(const int64_t *src, int64_t *dst) { *dst += *src; }
 
 // ---------------------------------------------------------------------------
 // rows of a fused batch result handed to one member query
@@ -1602,8 +1612,10 @@ __global__ __launch_bounds__(256) void k_gather_copy(const int64_t *rrp, const i
 // row restriction of a right subtree: the columns that a left operand uses
 
 // bits |= columns of every stored entry of a product (all entries are live)
-__global__ void k_cols_to_bits(const int32_t *col, int64_t nnz, uint32_t *bits) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+// nnz_dev (when given) holds the true entry count, nnz its upper bound
+__global__ void k_cols_to_bits(const int32_t *col, int64_t nnz, const int64_t *nnz_dev, uint32_t *bits) {
+    const int64_t n = nnz_dev ? *nnz_dev : nnz;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t j = col[e];
         atomicOr(&bits[j >> 5], 1u << (j & 31));
     }
@@ -1926,10 +1938,14 @@ void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row
 }
 
 void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
-                           hipStream_t s, KernelTimer *t) {
+                           bool partition, hipStream_t s, KernelTimer *t) {
     if (n_cand <= 0) return;
     ATP_LAUNCH("active", 0, 0, s, k_active_scatter, dim3((unsigned)((n_cand + 255) / 256)), dim3(256), 0, s, cand,
-               n_cand, flags_scan, active);
+               n_cand, flags_scan, active, partition ? 1 : 0);
+}
+
+void launch_accum_i64(const int64_t *src, int64_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_accum_i64, dim3(1), dim3(1), 0, s, src, dst);
 }
 
 void launch_bin_stats(const int32_t *list, int64_t n, const Operand &X, const int32_t *cand, const int64_t *row_nnz,
@@ -1945,9 +1961,11 @@ void launch_mark_bytes(const uint32_t *ymark, const int64_t *yrp, int64_t yrows,
                        (unsigned long long *)acc);
 }
 
-void launch_cols_to_bits(const int32_t *col, int64_t nnz, uint32_t *bits, hipStream_t s, KernelTimer *t) {
+void launch_cols_to_bits(const int32_t *col, int64_t nnz, const int64_t *nnz_dev, uint32_t *bits, hipStream_t s,
+                         KernelTimer *t) {
     if (nnz <= 0) return;
-    ATP_LAUNCH("restrict", 0, 0, s, k_cols_to_bits, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, col, nnz, bits);
+    ATP_LAUNCH("restrict", 0, 0, s, k_cols_to_bits, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, col, nnz, nnz_dev,
+               bits);
 }
 
 void launch_leaf_cols_to_bits(const Operand &X, const int32_t *cand, int64_t n_cand, int64_t *len, int64_t *off,
