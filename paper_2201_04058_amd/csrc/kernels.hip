@@ -25,6 +25,7 @@ namespace atp {
 namespace {
 
 constexpr int kLongRow = 128;     // X rows longer than this go to the chunked symbolic pass
+constexpr int kProdUnroll = 4;    // products per lane per step of the dense kernel's walk
 constexpr int64_t kSymChunk = 4096;
 
 __device__ __forceinline__ bool bit_test(const uint32_t *b, int64_t i) {
@@ -32,6 +33,10 @@ __device__ __forceinline__ bool bit_test(const uint32_t *b, int64_t i) {
 }
 
 __device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b) {
+    if (((a | b) >> 32) == 0) {  // both below 2^32: one 32x32->64 product
+        const uint64_t p = (uint64_t)(uint32_t)a * (uint32_t)b;
+        return (p & kSat) ? kSat : p;
+    }
     if ((a | b) & kSat) return kSat;
     uint64_t hi = __umul64hi(a, b);
     uint64_t lo = a * b;
@@ -699,6 +704,77 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
 // ---------------------------------------------------------------------------
 // numeric: dense LDS tiles over column ranges
 
+// Visit the flattened products of a batch of left entries: entry e's
+// segment is right-operand entries [seg_s[e], seg_s[e] + len) and its items
+// are [seg_o[e], seg_o[e+1]) of the batch's tot items (tot < 2^31: segments
+// are bounded by a part's columns).  f(column, value) per product whose column
+// passes Y's column mask.  Each wavefront takes a contiguous chunk of items,
+// kProdUnroll items per lane per step (unit stride between lanes), and tracks
+// its entry with a forward walk; the step's gathers of the right operand are
+// all issued before the first is used, so their latencies overlap.  XV / YV:
+// the left / right operand carries values (else every value is 1).
+template <bool XV, bool YV, int NT, typename F>
+__device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
+                                              int32_t tot, const uint64_t *xval, F f) {
+    constexpr int U = kProdUnroll;
+    constexpr int NWV = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int32_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~63;
+    const int32_t beg = wave * chunk;
+    const int32_t end = (beg + chunk < tot) ? beg + chunk : tot;
+    if (beg >= end) return;
+    int32_t item = beg + lane;
+    const int32_t first = item < end ? item : end - 1;
+    int lo = 0, hi = NT;  // last entry with seg_o <= first
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg_o[mid] <= first)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    int ent = lo;
+    int32_t o0 = seg_o[ent], o1 = seg_o[ent + 1];
+    int64_t s0 = seg_s[ent];
+    uint64_t xv = XV ? xval[ent] : 1ull;
+    for (; item < end; item += 64 * U) {
+        // an item past the chunk repeats the lane's previous one (loads stay
+        // in bounds and unconditional) and is skipped when applied
+        int64_t fpos[U];
+        uint64_t xs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t it = item + 64 * u;
+            if (u == 0 || it < end) {
+                while (it >= o1) {
+                    ++ent;
+                    o0 = o1;
+                    o1 = seg_o[ent + 1];
+                    s0 = seg_s[ent];
+                    if (XV) xv = xval[ent];
+                }
+                fpos[u] = s0 + (it - o0);
+            } else {
+                fpos[u] = fpos[u - 1];
+            }
+            if (XV) xs[u] = xv;
+        }
+        int32_t js[U];
+        uint64_t ys[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            js[u] = Y.col[fpos[u]];
+            if (YV) ys[u] = Y.val[fpos[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (item + 64 * u >= end) break;
+            if (Y.cmask && !bit_test(Y.cmask, js[u])) continue;
+            f(js[u], YV ? (XV ? sat_mul(xs[u], ys[u]) : ys[u]) : (XV ? xs[u] : 1ull));
+        }
+    }
+}
+
 // Write one dense LDS tile (columns c0 .. c0+kTileW) of row i in column order
 // into the row's slots, then clear it.  A slot is present when its
 // accumulator is non-zero or its saturation bit is set (every contribution is
@@ -1070,41 +1146,18 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
         __syncthreads();
         return tot;
     };
-    // visit the flattened products of the current batch: f(column, value).
-    // Each wavefront takes a contiguous chunk of items, one item per lane per
-    // step (unit stride), and tracks its entry with a forward walk.
+    // visit the flattened products of the current batch: f(column, value)
     auto products = [&](int64_t tot, const uint64_t *xval, auto f) {
-        const int lane = tid & 63, wave = tid >> 6;
-        constexpr int NWV = NT / 64;
-        const int64_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~int64_t(63);
-        const int64_t beg = wave * chunk;
-        const int64_t end = (beg + chunk < tot) ? beg + chunk : tot;
-        if (beg >= end) return;
-        int64_t item = beg + lane;
-        const int64_t first = item < end ? item : end - 1;
-        int lo = 0, hi = NT;  // last entry with seg_o <= first
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (seg_o[mid] <= first)
-                lo = mid;
+        if (xval) {
+            if (a.Y.val)
+                walk_products<true, true, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
             else
-                hi = mid;
-        }
-        int ent = lo;
-        int64_t o0 = seg_o[ent], o1 = seg_o[ent + 1], s0 = seg_s[ent];
-        uint64_t xv = xval ? xval[ent] : 1ull;
-        for (; item < end; item += 64) {
-            while (item >= o1) {
-                ++ent;
-                o0 = o1;
-                o1 = seg_o[ent + 1];
-                s0 = seg_s[ent];
-                if (xval) xv = xval[ent];
-            }
-            const int64_t fpos = s0 + (item - o0);
-            const int32_t j = a.Y.col[fpos];
-            if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
-            f(j, a.Y.val ? sat_mul(xv, a.Y.val[fpos]) : xv);
+                walk_products<true, false, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
+        } else {
+            if (a.Y.val)
+                walk_products<false, true, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
+            else
+                walk_products<false, false, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
         }
     };
 
