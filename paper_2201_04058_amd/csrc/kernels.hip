@@ -490,6 +490,135 @@ __global__ void k_bin_rows(SymbolicArgs a) {
     }
 }
 
+// Visit the flattened products of a batch of at most NT left entries (NT
+// threads cooperate: a block, or one wavefront when NT = 64): entry e's
+// segment is right-operand entries [seg_s[e], seg_s[e] + len) and its items
+// are [seg_o[e], seg_o[e+1]) of the batch's tot items (tot < 2^31; seg_o has
+// NT + 1 entries).  f(column, value) per product whose column passes Y's
+// column mask.  Each wavefront takes a contiguous chunk of items,
+// kProdUnroll items per lane per step (unit stride between lanes), and tracks
+// its entry with a forward walk; the step's gathers of the right operand are
+// all issued before the first is used, so their latencies overlap.  XV / YV:
+// the left / right operand carries values (else every value is 1).
+template <bool XV, bool YV, int NT, typename F>
+__device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
+                                              int32_t tot, const uint64_t *xval, F f) {
+    constexpr int U = kProdUnroll;
+    constexpr int NWV = NT / 64;
+    const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) & (NWV - 1);
+    const int32_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~63;
+    const int32_t beg = wave * chunk;
+    const int32_t end = (beg + chunk < tot) ? beg + chunk : tot;
+    if (beg >= end) return;
+    int32_t item = beg + lane;
+    const int32_t first = item < end ? item : end - 1;
+    int lo = 0, hi = NT;  // last entry with seg_o <= first
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg_o[mid] <= first)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    int ent = lo;
+    int32_t o0 = seg_o[ent], o1 = seg_o[ent + 1];
+    int64_t s0 = seg_s[ent];
+    uint64_t xv = XV ? xval[ent] : 1ull;
+    for (; item < end; item += 64 * U) {
+        // an item past the chunk repeats the lane's previous one (loads stay
+        // in bounds and unconditional) and is skipped when applied
+        int64_t fpos[U];
+        uint64_t xs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t it = item + 64 * u;
+            if (u == 0 || it < end) {
+                while (it >= o1) {
+                    ++ent;
+                    o0 = o1;
+                    o1 = seg_o[ent + 1];
+                    s0 = seg_s[ent];
+                    if (XV) xv = xval[ent];
+                }
+                fpos[u] = s0 + (it - o0);
+            } else {
+                fpos[u] = fpos[u - 1];
+            }
+            if (XV) xs[u] = xv;
+        }
+        int32_t js[U];
+        uint64_t ys[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            js[u] = Y.col[fpos[u]];
+            if (YV) ys[u] = Y.val[fpos[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (item + 64 * u >= end) break;
+            if (Y.cmask && !bit_test(Y.cmask, js[u])) continue;
+            f(js[u], YV ? (XV ? sat_mul(xs[u], ys[u]) : ys[u]) : (XV ? xs[u] : 1ull));
+        }
+    }
+}
+
+// walk_products for whichever operands carry values
+template <int NT, typename F>
+__device__ __forceinline__ void walk_products_any(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
+                                                  int32_t tot, const uint64_t *xval, F f) {
+    if (xval) {
+        if (Y.val)
+            walk_products<true, true, NT>(Y, seg_o, seg_s, tot, xval, f);
+        else
+            walk_products<true, false, NT>(Y, seg_o, seg_s, tot, xval, f);
+    } else {
+        if (Y.val)
+            walk_products<false, true, NT>(Y, seg_o, seg_s, tot, xval, f);
+        else
+            walk_products<false, false, NT>(Y, seg_o, seg_s, tot, xval, f);
+    }
+}
+
+// A batch's products are walked flattened when they number below this.
+constexpr int64_t kWalkMax = (int64_t)1 << 30;
+
+// Segments of left entries [e0, e0 + nb) (nb <= NT): each entry's whole right
+// row (empty when the column mask excludes it).  NT = blockDim.x threads, or
+// one wavefront (NT = 64).  Returns the batch's product count (uniform).
+template <int NT>
+__device__ __forceinline__ int64_t row_segments(const Operand &X, const Operand &Y, int64_t e0, int64_t nb,
+                                                int64_t *seg_s, int32_t *seg_o, int64_t *sw) {
+    const int tid = NT == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+    int64_t len = 0;
+    if (tid < nb) {
+        const int32_t k = X.col[e0 + tid];
+        if (!X.cmask || bit_test(X.cmask, k)) {
+            const int64_t yb = Y.rp[k];
+            len = Y.rp[k + 1] - yb;
+            seg_s[tid] = yb;
+        }
+    }
+    int64_t tot, inc;
+    if (NT == 64) {
+        inc = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t o = __shfl_up(inc, d, 64);
+            if (tid >= d) inc += o;
+        }
+        tot = __shfl(inc, 63, 64);
+    } else {
+        inc = block_inclusive_scan(len, sw, &tot);
+    }
+    seg_o[tid] = (int32_t)(inc - len);
+    if (tid == NT - 1) seg_o[NT] = (int32_t)inc;
+    if (NT == 64)
+        wave_sync();
+    else
+        __syncthreads();
+    return tot;
+}
+
 // ---------------------------------------------------------------------------
 // numeric: LDS hash, one wavefront per row
 
@@ -522,10 +651,14 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
     __shared__ unsigned long long vals_all[4][S];
     __shared__ uint32_t sat_all[4][(S + 31) / 32];
     __shared__ int cnt_all[4];
+    __shared__ int64_t segs_all[4][64];
+    __shared__ int32_t sego_all[4][65];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t *keys = keys_all[wave];
     unsigned long long *vals = vals_all[wave];
     uint32_t *satw = sat_all[wave];
+    int64_t *seg_s = segs_all[wave];
+    int32_t *seg_o = sego_all[wave];
     for (int t = lane; t < S; t += 64) {
         keys[t] = kEmptyKey;
         vals[t] = 0;
@@ -537,10 +670,20 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
         const int32_t c = list[r];
         const int64_t i = a.cand ? a.cand[c] : c;
         const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
-        const int64_t xlen = xe - xb;
-        const int g = group_size(a.nop[c] / (xlen > 0 ? xlen : 1));
-        accumulate_hash<S>(a.X, a.Y, xb, xe, lane / g, 64 / g, lane % g, g, keys, vals, satw);
-        wave_sync();
+        // batches of 64 left entries, their products walked flattened
+        for (int64_t eb = xb; eb < xe; eb += 64) {
+            const int64_t nb = (xe - eb < 64) ? xe - eb : 64;
+            const int64_t tot = row_segments<64>(a.X, a.Y, eb, nb, seg_s, seg_o, nullptr);
+            if (tot < kWalkMax)
+                walk_products_any<64>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
+                                      [&](int32_t j, uint64_t v) {
+                                          const uint32_t h = hash_find<S>(keys, j);
+                                          acc_add(&vals[h], satw, h, v);
+                                      });
+            else
+                accumulate_hash<S>(a.X, a.Y, eb, eb + nb, 0, 1, lane, 64, keys, vals, satw);
+            wave_sync();
+        }
         // compact the occupied slots to the front in one pass (a slot is read
         // before any write can reach it: positions written stay below the
         // current group of 64), then sort the next power of two of them
@@ -623,6 +766,8 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
     __shared__ unsigned long long vals[S];
     __shared__ uint32_t satw[S / 32];
     __shared__ int64_t sw[NT / 64];
+    __shared__ int64_t seg_s[NT];
+    __shared__ int32_t seg_o[NT + 1];
     __shared__ int any_sat;
     for (int t = threadIdx.x; t < S; t += NT) {
         keys[t] = kEmptyKey;
@@ -635,12 +780,21 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
         const int32_t c = list[r];
         const int64_t i = a.cand ? a.cand[c] : c;
         const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
-        const int64_t xlen = xe - xb;
-        const int g = group_size(a.nop[c] / (xlen > 0 ? xlen : 1));
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        const int gpw = 64 / g;  // groups per wave
-        accumulate_hash<S>(a.X, a.Y, xb, xe, wave * gpw + lane / g, (NT / 64) * gpw, lane % g, g, keys, vals, satw);
-        __syncthreads();
+        // batches of NT left entries, their products walked flattened
+        for (int64_t eb = xb; eb < xe; eb += NT) {
+            const int64_t nb = (xe - eb < NT) ? xe - eb : NT;
+            const int64_t tot = row_segments<NT>(a.X, a.Y, eb, nb, seg_s, seg_o, sw);
+            if (tot < kWalkMax)
+                walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
+                                      [&](int32_t j, uint64_t v) {
+                                          const uint32_t h = hash_find<S>(keys, j);
+                                          acc_add(&vals[h], satw, h, v);
+                                      });
+            else
+                accumulate_hash<S>(a.X, a.Y, eb, eb + nb, threadIdx.x >> 6, NT / 64, threadIdx.x & 63, 64, keys,
+                                   vals, satw);
+            __syncthreads();
+        }
         // compact the occupied slots to the front (each thread's slots pass
         // through registers), then sort only the next power of two of them
         constexpr int PER = S / NT;
@@ -703,77 +857,6 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
 
 // ---------------------------------------------------------------------------
 // numeric: dense LDS tiles over column ranges
-
-// Visit the flattened products of a batch of left entries: entry e's
-// segment is right-operand entries [seg_s[e], seg_s[e] + len) and its items
-// are [seg_o[e], seg_o[e+1]) of the batch's tot items (tot < 2^31: segments
-// are bounded by a part's columns).  f(column, value) per product whose column
-// passes Y's column mask.  Each wavefront takes a contiguous chunk of items,
-// kProdUnroll items per lane per step (unit stride between lanes), and tracks
-// its entry with a forward walk; the step's gathers of the right operand are
-// all issued before the first is used, so their latencies overlap.  XV / YV:
-// the left / right operand carries values (else every value is 1).
-template <bool XV, bool YV, int NT, typename F>
-__device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
-                                              int32_t tot, const uint64_t *xval, F f) {
-    constexpr int U = kProdUnroll;
-    constexpr int NWV = NT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int32_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~63;
-    const int32_t beg = wave * chunk;
-    const int32_t end = (beg + chunk < tot) ? beg + chunk : tot;
-    if (beg >= end) return;
-    int32_t item = beg + lane;
-    const int32_t first = item < end ? item : end - 1;
-    int lo = 0, hi = NT;  // last entry with seg_o <= first
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (seg_o[mid] <= first)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    int ent = lo;
-    int32_t o0 = seg_o[ent], o1 = seg_o[ent + 1];
-    int64_t s0 = seg_s[ent];
-    uint64_t xv = XV ? xval[ent] : 1ull;
-    for (; item < end; item += 64 * U) {
-        // an item past the chunk repeats the lane's previous one (loads stay
-        // in bounds and unconditional) and is skipped when applied
-        int64_t fpos[U];
-        uint64_t xs[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int32_t it = item + 64 * u;
-            if (u == 0 || it < end) {
-                while (it >= o1) {
-                    ++ent;
-                    o0 = o1;
-                    o1 = seg_o[ent + 1];
-                    s0 = seg_s[ent];
-                    if (XV) xv = xval[ent];
-                }
-                fpos[u] = s0 + (it - o0);
-            } else {
-                fpos[u] = fpos[u - 1];
-            }
-            if (XV) xs[u] = xv;
-        }
-        int32_t js[U];
-        uint64_t ys[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            js[u] = Y.col[fpos[u]];
-            if (YV) ys[u] = Y.val[fpos[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (item + 64 * u >= end) break;
-            if (Y.cmask && !bit_test(Y.cmask, js[u])) continue;
-            f(js[u], YV ? (XV ? sat_mul(xs[u], ys[u]) : ys[u]) : (XV ? xs[u] : 1ull));
-        }
-    }
-}
 
 // Write one dense LDS tile (columns c0 .. c0+kTileW) of row i in column order
 // into the row's slots, then clear it.  A slot is present when its
@@ -1148,17 +1231,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
     };
     // visit the flattened products of the current batch: f(column, value)
     auto products = [&](int64_t tot, const uint64_t *xval, auto f) {
-        if (xval) {
-            if (a.Y.val)
-                walk_products<true, true, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
-            else
-                walk_products<true, false, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
-        } else {
-            if (a.Y.val)
-                walk_products<false, true, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
-            else
-                walk_products<false, false, NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
-        }
+        walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
     };
 
     for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
@@ -1313,26 +1386,6 @@ __device__ __forceinline__ void bucket_chunk(const int64_t *chunk_base, int64_t 
     *q = id - chunk_base[lo];
 }
 
-// Products of X entries [e0, e1) of one row, g lanes per X entry (short
-// right rows; g a power of two); f(tile, col, value) for each.
-template <typename F>
-__device__ __forceinline__ void for_products(const Operand &X, const Operand &Y, int64_t e0, int64_t e1, int g, F f) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int gid = wave * (64 / g) + lane / g, ng = (blockDim.x / 64) * (64 / g), li = lane & (g - 1);
-    for (int64_t e = e0 + gid; e < e1; e += ng) {
-        int32_t k = X.col[e];
-        if (X.cmask && !bit_test(X.cmask, k)) continue;
-        uint64_t xv = X.val ? X.val[e] : 1ull;
-        int64_t yb = Y.rp[k], ye = Y.rp[k + 1];
-        for (int64_t fpos = yb + li; fpos < ye; fpos += g) {
-            int32_t j = Y.col[fpos];
-            if (Y.cmask && !bit_test(Y.cmask, j)) continue;
-            uint64_t v = Y.val ? sat_mul(xv, Y.val[fpos]) : xv;
-            f(j >> kTileShift, j, v);
-        }
-    }
-}
-
 // Runs of one lane group: consecutive active lanes whose products fall into
 // the same column tile (the lanes of a group read consecutive entries of one
 // sorted right-operand row, so a row's products in one tile are adjacent).
@@ -1410,8 +1463,38 @@ struct BucketArgs {
     int g;                      // lanes per left entry (power of two <= 64)
 };
 
+// Products of X entries [e0, e1) of one row in batches of kBucketThreads
+// entries, walked flattened: f(column, value) for each.
+template <typename F>
+__device__ __forceinline__ void walk_entry_range(const NumericArgs &a, int64_t e0, int64_t e1, int64_t *seg_s,
+                                                 int32_t *seg_o, int64_t *sw, F f) {
+    for (int64_t eb = e0; eb < e1; eb += kBucketThreads) {
+        const int64_t nb = (e1 - eb < kBucketThreads) ? e1 - eb : kBucketThreads;
+        const int64_t tot = row_segments<kBucketThreads>(a.X, a.Y, eb, nb, seg_s, seg_o, sw);
+        if (tot < kWalkMax) {
+            walk_products_any<kBucketThreads>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr, f);
+        } else {
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            for (int64_t e = eb + wave; e < eb + nb; e += kBucketThreads / 64) {
+                const int32_t k = a.X.col[e];
+                if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
+                const uint64_t xv = a.X.val ? a.X.val[e] : 1ull;
+                for (int64_t fpos = a.Y.rp[k] + lane; fpos < a.Y.rp[k + 1]; fpos += 64) {
+                    const int32_t j = a.Y.col[fpos];
+                    if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
+                    f(j, a.Y.val ? sat_mul(xv, a.Y.val[fpos]) : xv);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, NumericArgs a) {
     __shared__ int32_t hist[kMaxBucketTiles];
+    __shared__ int64_t seg_s[kBucketThreads];
+    __shared__ int32_t seg_o[kBucketThreads + 1];
+    __shared__ int64_t sw[kBucketThreads / 64];
     for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
         int64_t p, q;
         bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
@@ -1427,7 +1510,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, N
                 if (r.head) atomicAdd(&hist[tile], r.len);
             });
         else
-            for_products(a.X, a.Y, e0, e1, b.g, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+            walk_entry_range(a, e0, e1, seg_s, seg_o, sw,
+                             [&](int32_t j, uint64_t) { atomicAdd(&hist[j >> kTileShift], 1); });
         __syncthreads();
         int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x)
@@ -1462,6 +1546,9 @@ __global__ __launch_bounds__(256) void k_bucket_scan(BucketArgs b) {
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b, NumericArgs a) {
     __shared__ int32_t hist[kMaxBucketTiles];
     __shared__ int64_t base[kMaxBucketTiles];
+    __shared__ int64_t seg_s[kBucketThreads];
+    __shared__ int32_t seg_o[kBucketThreads + 1];
+    __shared__ int64_t sw[kBucketThreads / 64];
     for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
         int64_t p, q;
         bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
@@ -1477,7 +1564,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
                 if (r.head) atomicAdd(&hist[tile], r.len);
             });
         else
-            for_products(a.X, a.Y, e0, e1, b.g, [&](int64_t tile, int32_t, uint64_t) { atomicAdd(&hist[tile], 1); });
+            walk_entry_range(a, e0, e1, seg_s, seg_o, sw,
+                             [&](int32_t j, uint64_t) { atomicAdd(&hist[j >> kTileShift], 1); });
         __syncthreads();
         int64_t *cur = b.tile_cnt + p * (b.ntiles + 1);
         for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
@@ -1500,7 +1588,8 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
                 }
             });
         else
-            for_products(a.X, a.Y, e0, e1, b.g, [&](int64_t tile, int32_t j, uint64_t v) {
+            walk_entry_range(a, e0, e1, seg_s, seg_o, sw, [&](int32_t j, uint64_t v) {
+                const int32_t tile = j >> kTileShift;
                 const int64_t pos = base[tile] + atomicAdd(&hist[tile], 1);
                 b.prod_col[pos] = j;
                 if (valued) b.prod_val[pos] = v;
