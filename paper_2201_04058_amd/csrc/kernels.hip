@@ -25,7 +25,8 @@ namespace atp {
 namespace {
 
 constexpr int kLongRow = 128;     // X rows longer than this go to the chunked symbolic pass
-constexpr int kProdUnroll = 4;    // products per lane per step of the dense kernel's walk
+constexpr int kProdUnroll = 4;    // products per lane per step of a flattened product walk
+constexpr int kHashUnroll = 2;    // ... in the hash kernels
 constexpr int64_t kSymChunk = 4096;
 
 __device__ __forceinline__ bool bit_test(const uint32_t *b, int64_t i) {
@@ -496,14 +497,13 @@ __global__ void k_bin_rows(SymbolicArgs a) {
 // are [seg_o[e], seg_o[e+1]) of the batch's tot items (tot < 2^31; seg_o has
 // NT + 1 entries).  f(column, value) per product whose column passes Y's
 // column mask.  Each wavefront takes a contiguous chunk of items,
-// kProdUnroll items per lane per step (unit stride between lanes), and tracks
+// U items per lane per step (unit stride between lanes), and tracks
 // its entry with a forward walk; the step's gathers of the right operand are
 // all issued before the first is used, so their latencies overlap.  XV / YV:
 // the left / right operand carries values (else every value is 1).
-template <bool XV, bool YV, int NT, typename F>
+template <bool XV, bool YV, int NT, int U, typename F>
 __device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
                                               int32_t tot, const uint64_t *xval, F f) {
-    constexpr int U = kProdUnroll;
     constexpr int NWV = NT / 64;
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) & (NWV - 1);
     const int32_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~63;
@@ -563,19 +563,19 @@ __device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *s
 }
 
 // walk_products for whichever operands carry values
-template <int NT, typename F>
+template <int NT, int U = kProdUnroll, typename F>
 __device__ __forceinline__ void walk_products_any(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
                                                   int32_t tot, const uint64_t *xval, F f) {
     if (xval) {
         if (Y.val)
-            walk_products<true, true, NT>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<true, true, NT, U>(Y, seg_o, seg_s, tot, xval, f);
         else
-            walk_products<true, false, NT>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<true, false, NT, U>(Y, seg_o, seg_s, tot, xval, f);
     } else {
         if (Y.val)
-            walk_products<false, true, NT>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<false, true, NT, U>(Y, seg_o, seg_s, tot, xval, f);
         else
-            walk_products<false, false, NT>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<false, false, NT, U>(Y, seg_o, seg_s, tot, xval, f);
     }
 }
 
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
             const int64_t nb = (xe - eb < 64) ? xe - eb : 64;
             const int64_t tot = row_segments<64>(a.X, a.Y, eb, nb, seg_s, seg_o, nullptr);
             if (tot < kWalkMax)
-                walk_products_any<64>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
+                walk_products_any<64, kHashUnroll>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
                                       [&](int32_t j, uint64_t v) {
                                           const uint32_t h = hash_find<S>(keys, j);
                                           acc_add(&vals[h], satw, h, v);
@@ -785,7 +785,7 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
             const int64_t nb = (xe - eb < NT) ? xe - eb : NT;
             const int64_t tot = row_segments<NT>(a.X, a.Y, eb, nb, seg_s, seg_o, sw);
             if (tot < kWalkMax)
-                walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
+                walk_products_any<NT, kHashUnroll>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
                                       [&](int32_t j, uint64_t v) {
                                           const uint32_t h = hash_find<S>(keys, j);
                                           acc_add(&vals[h], satw, h, v);
