@@ -328,6 +328,38 @@ __global__ void k_popcount(const uint32_t *bits, int64_t words, int64_t *out) {
 // ---------------------------------------------------------------------------
 // symbolic pass
 
+// Sum of |Y row k| over the X entries k at positions p0, p0 + stride, ...
+// below e that pass X's column mask; four entries' loads are in flight
+// together (column ids, then mask words, then row-pointer pairs).
+__device__ __forceinline__ int64_t sum_right_rows(const Operand &X, const Operand &Y, int64_t p0, int64_t e,
+                                                  int stride) {
+    int64_t s = 0;
+    for (int64_t p = p0; p < e; p += 4 * (int64_t)stride) {
+        int32_t k[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = p + (int64_t)u * stride;
+            ok[u] = q < e;
+            k[u] = ok[u] ? X.col[q] : 0;
+        }
+        if (X.cmask) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (ok[u]) ok[u] = bit_test(X.cmask, k[u]);
+        }
+        int64_t lo[4], hi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            lo[u] = ok[u] ? Y.rp[k[u]] : 0;
+            hi[u] = ok[u] ? Y.rp[k[u] + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += hi[u] - lo[u];
+    }
+    return s;
+}
+
 // Eight lanes per candidate row (they stride over its entries); rows longer
 // than kLongRow are left to the chunked pass.
 constexpr int kSymLanes = 8;
@@ -342,11 +374,7 @@ __global__ __launch_bounds__(256) void k_symbolic(SymbolicArgs a) {
             if (e - b > kLongRow) {
                 deferred = (e - b + kSymChunk - 1) / kSymChunk;
             } else {
-                for (int64_t p = b + li; p < e; p += kSymLanes) {
-                    int32_t k = a.X.col[p];
-                    if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
-                    nop += a.Y.rp[k + 1] - a.Y.rp[k];
-                }
+                nop = sum_right_rows(a.X, a.Y, b + li, e, kSymLanes);
             }
         }
     }
@@ -382,12 +410,7 @@ __global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a, const int
         const int64_t q = id - long_off[c];
         const int64_t b = a.X.rp[i] + q * kSymChunk;
         const int64_t e = (b + kSymChunk < a.X.rp[i + 1]) ? b + kSymChunk : a.X.rp[i + 1];
-        int64_t s = 0;
-        for (int64_t p = b + threadIdx.x; p < e; p += blockDim.x) {
-            const int32_t k = a.X.col[p];
-            if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
-            s += a.Y.rp[k + 1] - a.Y.rp[k];
-        }
+        const int64_t s = sum_right_rows(a.X, a.Y, b + threadIdx.x, e, blockDim.x);
         int64_t tot;
         block_inclusive_scan(s, sw, &tot);
         if (threadIdx.x == 0 && tot) {
