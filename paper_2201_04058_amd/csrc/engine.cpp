@@ -300,6 +300,17 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
             na.ytile = ytile.as<int32_t>();
         }
     }
+    Buf dorder, dqueue;
+    na.dense_order = nullptr;
+    na.dense_queue = nullptr;
+    if (h1.bin_count[BIN_DENSE] > 0 && Y.cols > kTileW && h1.dense_tasks >= kOrderMinTasks &&
+        h1.dense_tasks < ((int64_t)1 << 31)) {
+        // tasks grouped by column tile, one group per die
+        TRY(dorder.alloc(pool, 4 * (size_t)h1.dense_tasks));
+        TRY(dqueue.alloc(pool, 8 * 3 * kXcds));
+        na.dense_order = dorder.as<int32_t>();
+        na.dense_queue = dqueue.as<int64_t>();
+    }
     if (h1.bin_count[BIN_DENSE] > 0)
         launch_numeric_dense(bin_lists.as<int32_t>() + (int64_t)BIN_DENSE * n_cand, h1.bin_count[BIN_DENSE],
                              task_base.as<int64_t>(), h1.dense_tasks, na, s, t);
