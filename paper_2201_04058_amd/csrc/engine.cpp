@@ -243,7 +243,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     const int64_t ntiles_y = (Y.cols + kTileW - 1) / kTileW;
     GateHold hold(&c->gate, 12ull * (uint64_t)h1.slots_total +
                                 (uint64_t)h1.n_split * (uint64_t)ntiles_y * (uint64_t)kTileW * 9ull);
-    Buf slot_col, slot_val, seg_cnt, seg_src, seg_dst, row_cursor, row_nnz;
+    Buf slot_col, slot_val, seg_cnt, seg_src, seg_dst, row_cursor, row_nnz, dqueue;
     TRY(slot_col.alloc(pool, 4 * (size_t)h1.slots_total));
     TRY(slot_val.alloc(pool, 8 * (size_t)h1.slots_total));
     TRY(seg_cnt.alloc(pool, 8 * (size_t)h1.segs_total));
@@ -251,9 +251,10 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     TRY(seg_dst.alloc(pool, 8 * ((size_t)h1.segs_total + 1)));
     TRY(row_cursor.alloc(pool, 8 * n_cand));
     TRY(row_nnz.alloc(pool, 8 * (size_t)Z.rows));
-    const FillJob zero[3] = {{seg_cnt.as<int64_t>(), h1.segs_total, 0}, {row_cursor.as<int64_t>(), n_cand, 0},
-                             {row_nnz.as<int64_t>(), Z.rows, 0}};
-    launch_fill_multi(zero, 3, s, t);
+    TRY(dqueue.alloc(pool, 8 * kQueues));
+    const FillJob zero[4] = {{seg_cnt.as<int64_t>(), h1.segs_total, 0}, {row_cursor.as<int64_t>(), n_cand, 0},
+                             {row_nnz.as<int64_t>(), Z.rows, 0}, {dqueue.as<int64_t>(), kQueues, 0}};
+    launch_fill_multi(zero, 4, s, t);
 
     NumericArgs na{};
     na.X = X.op;
@@ -272,6 +273,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     na.ycols = Y.cols;
     na.tune = c->tune;
     na.dense_split = dense_split.as<int64_t>();
+    na.dense_queue = dqueue.as<int64_t>();
     Buf split_acc, split_sat, split_done;
     if (h1.n_split > 0) {
         const int64_t ntiles = (Y.cols + kTileW - 1) / kTileW;
@@ -299,17 +301,6 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
             launch_tile_index(Y.op, ntiles, ytile.as<int32_t>(), s, t);
             na.ytile = ytile.as<int32_t>();
         }
-    }
-    Buf dorder, dqueue;
-    na.dense_order = nullptr;
-    na.dense_queue = nullptr;
-    if (h1.bin_count[BIN_DENSE] > 0 && Y.cols > kTileW && h1.dense_tasks >= kOrderMinTasks &&
-        h1.dense_tasks < ((int64_t)1 << 31)) {
-        // tasks grouped by column tile, one group per die
-        TRY(dorder.alloc(pool, 4 * (size_t)h1.dense_tasks));
-        TRY(dqueue.alloc(pool, 8 * 3 * kXcds));
-        na.dense_order = dorder.as<int32_t>();
-        na.dense_queue = dqueue.as<int64_t>();
     }
     if (h1.bin_count[BIN_DENSE] > 0)
         launch_numeric_dense(bin_lists.as<int32_t>() + (int64_t)BIN_DENSE * n_cand, h1.bin_count[BIN_DENSE],

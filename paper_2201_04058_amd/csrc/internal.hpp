@@ -21,8 +21,7 @@ constexpr int64_t kPartHashCap = 2048; // a part with at most this many products
 constexpr int kPartMaxTiles = 16;      // ... if it spans at most this many tiles (its presence bitmap)
 constexpr int64_t kSplitOps = 65536;   // products per (row, tile) beyond which the row's entries are split
 constexpr int kMaxSplit = 64;
-constexpr int kXcds = 8;               // accelerator dies; workgroup b runs on die b mod kXcds
-constexpr int64_t kOrderMinTasks = 1024;  // dense launches with fewer tasks keep the strided order
+constexpr int kQueues = 8;             // dense task queues (counters) shared out by the workgroups
 constexpr int kMaxBucketTiles = 4096;  // column tiles a bucketed row may span
 constexpr int kBucketThreads = 512;
 
@@ -162,10 +161,7 @@ struct NumericArgs {
     uint32_t *split_sat;               // [n_split * ntiles * kTileW / 32] (zeroed)
     int32_t *split_done;               // [n_split * ntiles] (zeroed)
     const int32_t *ytile;              // [Y.rows * (ntiles + 1)] tile index of Y, or nullptr
-    // dense tasks grouped by the column tile they start at (one group per XCD,
-    // so that an XCD's L2 holds one share of Y's columns), or nullptr
-    int32_t *dense_order;              // [n_dense_tasks]
-    int64_t *dense_queue;              // [3 * kXcds]: group sizes, fill cursors, take cursors (zeroed)
+    int64_t *dense_queue;              // [kQueues] task counters of the dense kernel (zeroed)
     Tuning tune;
 };
 void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const NumericArgs &a, hipStream_t s,

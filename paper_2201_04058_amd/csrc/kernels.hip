@@ -1138,53 +1138,6 @@ __device__ void emit_hash_part(const NumericArgs &a, int32_t c, int64_t i, int64
     __syncthreads();
 }
 
-// Dense task groups: group of a task = the first column tile of its part mod
-// kXcds.  pass 0 counts the groups, pass 1 lists each group's tasks after the
-// groups before it (order within a group follows the atomics).
-__global__ __launch_bounds__(256) void k_dense_order(const int64_t *task_base, int64_t n_list, int64_t n_tasks,
-                                                     int64_t ntiles, int pass, NumericArgs a) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // a wave-uniform loop: one atomic per (wavefront, group)
-    for (int64_t t0 = blockIdx.x * (int64_t)blockDim.x; t0 < n_tasks; t0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t t = t0 + threadIdx.x;
-        int g = -1;
-        if (t < n_tasks) {
-            int64_t lo = 0, hi = n_list;  // last p with task_base[p] <= t
-            while (hi - lo > 1) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (task_base[mid] <= t)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            const int64_t ks = a.dense_split[lo] & 255;
-            const int64_t nparts = (task_base[lo + 1] - task_base[lo]) / ks;
-            const int64_t q = (t - task_base[lo]) / ks;
-            const int64_t m = (ntiles + nparts - 1) / nparts;
-            g = (int)((q * m) & (kXcds - 1));
-        }
-        for (int gg = 0; gg < kXcds; ++gg) {
-            const uint64_t mk = __ballot(g == gg);
-            if (mk == 0) continue;
-            const int leader = __builtin_ctzll(mk);
-            if (pass == 0) {
-                if (lane == leader) atomicAdd((unsigned long long *)&a.dense_queue[gg], (unsigned long long)__popcll(mk));
-            } else {
-                unsigned long long pos = 0;
-                if (lane == leader)
-                    pos = atomicAdd((unsigned long long *)&a.dense_queue[kXcds + gg], (unsigned long long)__popcll(mk));
-                pos = __shfl(pos, leader, 64);
-                if (g == gg) {
-                    int64_t base = 0;
-                    for (int g2 = 0; g2 < gg; ++g2) base += a.dense_queue[g2];
-                    a.dense_order[base + (int64_t)pos + __popcll(mk & lt)] = (int32_t)t;
-                }
-            }
-        }
-    }
-}
-
 // One task = one row and a part of m consecutive column tiles.  Each left
 // entry's segment of its right row inside the part is located (from the right
 // operand's tile index when there is one, else by binary search or the row
@@ -1304,29 +1257,22 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
         walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
     };
 
-    // next task: from the task groups (this die's group first, then the
-    // others' leftovers), else task ids strided over the grid
-    int grp = blockIdx.x & (kXcds - 1), tried = 0;  // thread 0's position in the groups
-    int64_t seq = blockIdx.x;
+    // next task: task ids t = g + kQueues * i are handed out by queue g's
+    // counter; a workgroup starts at queue blockIdx.x mod kQueues and moves
+    // on to the next queue when one runs dry
+    int grp = blockIdx.x & (kQueues - 1), tried = 0;  // thread 0's position
     while (true) {
         if (tid == 0) {
             int64_t v = -1;
-            if (a.dense_order) {
-                while (tried < kXcds) {
-                    const int64_t idx =
-                        (int64_t)atomicAdd((unsigned long long *)&a.dense_queue[2 * kXcds + grp], 1ull);
-                    if (idx < a.dense_queue[grp]) {
-                        int64_t base = 0;
-                        for (int g2 = 0; g2 < grp; ++g2) base += a.dense_queue[g2];
-                        v = a.dense_order[base + idx];
-                        break;
-                    }
-                    grp = (grp + 1) & (kXcds - 1);
-                    ++tried;
+            while (tried < kQueues) {
+                const int64_t idx = (int64_t)atomicAdd((unsigned long long *)&a.dense_queue[grp], 1ull);
+                const int64_t cand_task = grp + kQueues * idx;
+                if (cand_task < n_tasks) {
+                    v = cand_task;
+                    break;
                 }
-            } else if (seq < n_tasks) {
-                v = seq;
-                seq += gridDim.x;
+                grp = (grp + 1) & (kQueues - 1);
+                ++tried;
             }
             s_task[3] = v;
         }
@@ -2132,15 +2078,6 @@ void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *ta
     if (n_tasks <= 0) return;
     const int cus = device_cus();
     int64_t g = n_tasks < (int64_t)cus * 2 ? n_tasks : (int64_t)cus * 2;
-    if (a.dense_order) {
-        const int64_t ntiles = (a.ycols + kTileW - 1) / kTileW;
-        const dim3 og((unsigned)grid_for(n_tasks, 256, (int64_t)cus * 8));
-        ATP_LAUNCH("dense_order", 0, 0, s, k_fill_i64, dim3(1), dim3(64), 0, s, a.dense_queue,
-                   (int64_t)(3 * kXcds), (int64_t)0);
-        for (int pass = 0; pass < 2; ++pass)
-            ATP_LAUNCH("dense_order", 0, 0, s, k_dense_order, og, dim3(256), 0, s, task_base, n_list, n_tasks, ntiles, pass,
-                       a);
-    }
     ATP_LAUNCH("dense", 0, 0, s, k_dense, dim3((unsigned)g), dim3(kDenseThreads), 0, s, list, n_list, task_base,
                n_tasks, a);
 }
