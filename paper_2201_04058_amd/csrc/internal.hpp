@@ -21,7 +21,7 @@ constexpr int64_t kPartHashCap = 2048; // a part with at most this many products
 constexpr int kPartMaxTiles = 16;      // ... if it spans at most this many tiles (its presence bitmap)
 constexpr int64_t kSplitOps = 65536;   // products per (row, tile) beyond which the row's entries are split
 constexpr int kMaxSplit = 64;
-constexpr int kQueues = 8;             // dense task queues (counters) shared out by the workgroups
+constexpr int kQueues = 8;             // task counters of the dense kernel
 constexpr int kMaxBucketTiles = 4096;  // column tiles a bucketed row may span
 constexpr int kBucketThreads = 512;
 

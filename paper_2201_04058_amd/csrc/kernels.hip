@@ -101,6 +101,36 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Task ids 0 .. n-1 handed out by kQueues counters q[0 .. kQueues) (zeroed
+// before the launch): counter g hands out g, g + kQueues, ...  A workgroup
+// starts at counter blockIdx.x mod kQueues and moves on to the next one when
+// a counter runs dry; -1 once all have.  Called by one thread, which keeps
+// the cursor.
+struct QueueCursor {
+    int grp, tried;
+};
+__device__ __forceinline__ QueueCursor queue_start() { return QueueCursor{(int)(blockIdx.x & (kQueues - 1)), 0}; }
+__device__ __forceinline__ int64_t queue_next(int64_t *q, int64_t n, QueueCursor &cur) {
+    while (cur.tried < kQueues) {
+        const int64_t idx = (int64_t)atomicAdd((unsigned long long *)&q[cur.grp], 1ull);
+        const int64_t t = cur.grp + (int64_t)kQueues * idx;
+        if (t < n) return t;
+        cur.grp = (cur.grp + 1) & (kQueues - 1);
+        ++cur.tried;
+    }
+    return -1;
+}
+
+// The workgroup's next task from the queue (every thread calls it; slot is
+// a __shared__ int64_t).
+__device__ __forceinline__ int64_t block_next_task(int64_t *q, int64_t n, QueueCursor &cur, int64_t *slot) {
+    if (threadIdx.x == 0) *slot = queue_next(q, n, cur);
+    __syncthreads();
+    const int64_t t = *slot;
+    __syncthreads();  // read by all before the next call writes it
+    return t;
+}
+
 // lanes per X entry: power of two near the average Y-row length, in [1, 64]
 __host__ __device__ inline int group_size(int64_t avg) {
     int g = 1;
@@ -1257,27 +1287,10 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
         walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
     };
 
-    // next task: task ids t = g + kQueues * i are handed out by queue g's
-    // counter; a workgroup starts at queue blockIdx.x mod kQueues and moves
-    // on to the next queue when one runs dry
-    int grp = blockIdx.x & (kQueues - 1), tried = 0;  // thread 0's position
+    // tasks from the dense queue (rows of very different cost stay balanced)
+    QueueCursor qc = queue_start();
     while (true) {
-        if (tid == 0) {
-            int64_t v = -1;
-            while (tried < kQueues) {
-                const int64_t idx = (int64_t)atomicAdd((unsigned long long *)&a.dense_queue[grp], 1ull);
-                const int64_t cand_task = grp + kQueues * idx;
-                if (cand_task < n_tasks) {
-                    v = cand_task;
-                    break;
-                }
-                grp = (grp + 1) & (kQueues - 1);
-                ++tried;
-            }
-            s_task[3] = v;
-        }
-        __syncthreads();
-        const int64_t task = s_task[3];
+        const int64_t task = block_next_task(a.dense_queue, n_tasks, qc, &s_task[3]);
         if (task < 0) break;
         if (tid < 64) {  // last p with task_base[p] <= task, by the first wavefront
             const int64_t pp = group_lower_bound(task_base, 0, n_list, task + 1, 64, tid, ~0ull) - 1;
