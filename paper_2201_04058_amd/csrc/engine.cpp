@@ -288,38 +288,75 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         na.split_sat = split_sat.as<uint32_t>();
         na.split_done = split_done.as<int32_t>();
     }
-    for (int b = BIN_W64; b <= BIN_B8192; ++b)
-        launch_numeric_hash(b, bin_lists.as<int32_t>() + (int64_t)b * n_cand, h1.bin_count[b], na, s, t);
     Buf ytile;
     na.ytile = nullptr;
+    const int64_t ntiles_z = (Y.cols + kTileW - 1) / kTileW;
     if (h1.bin_count[BIN_DENSE] > 0) {
         // segment bounds from a per-row tile index instead of searches, when it is small enough
-        const int64_t ntiles = (Y.cols + kTileW - 1) / kTileW;
-        const int64_t entries = (Y.rows) * (ntiles + 1);
-        if (ntiles > 1 && entries <= c->tile_index_cap && Y.nnz < ((int64_t)1 << 31)) {
+        const int64_t entries = (Y.rows) * (ntiles_z + 1);
+        if (ntiles_z > 1 && entries <= c->tile_index_cap && Y.nnz < ((int64_t)1 << 31)) {
             TRY(ytile.alloc(pool, 4 * (size_t)entries));
-            launch_tile_index(Y.op, ntiles, ytile.as<int32_t>(), s, t);
             na.ytile = ytile.as<int32_t>();
         }
     }
+    Buf tile_cnt, tile_off, prod_col, prod_val;
+    const int64_t nb = h1.bin_count[BIN_BUCKET];
+    const bool valued = X.op.val || Y.op.val;
+    if (nb > 0) {
+        TRY(tile_cnt.alloc(pool, 8 * (size_t)nb * (ntiles_z + 1)));
+        TRY(tile_off.alloc(pool, 8 * (size_t)nb * (ntiles_z + 1)));
+        TRY(prod_col.alloc(pool, 4 * (size_t)std::max<int64_t>(h1.bucket_products, 1)));
+        if (valued) TRY(prod_val.alloc(pool, 8 * (size_t)std::max<int64_t>(h1.bucket_products, 1)));
+    }
+    // The bins are independent (disjoint rows and slots): wavefront-hash rows,
+    // workgroup-hash rows and bucketed rows go to the lane's side streams and
+    // run beside the dense rows on the lane's stream.
+    bool any_wave = false, any_block = false;
+    for (int b = BIN_W64; b <= BIN_W512; ++b) any_wave |= h1.bin_count[b] > 0;
+    for (int b = BIN_B1024; b <= BIN_B8192; ++b) any_block |= h1.bin_count[b] > 0;
+    const int groups = (int)any_wave + (int)any_block + (int)(nb > 0) + (int)(h1.bin_count[BIN_DENSE] > 0);
+    hipStream_t s_wave = s, s_block = s, s_bucket = s;
+    struct Join {
+        Lane *L = nullptr;
+        hipStream_t s = nullptr;
+        bool pending = false;
+        atp_status run() {
+            if (!pending) return ATP_OK;
+            pending = false;
+            atp_status st = ATP_OK;
+            for (int i = 0; i < kSideStreams; ++i)
+                if (hipEventRecord(L->join[i], L->side[i]) != hipSuccess || hipStreamWaitEvent(s, L->join[i], 0) != hipSuccess)
+                    st = ATP_EDEVICE;
+            return st;
+        }
+        ~Join() { (void)run(); }
+    } join;
+    if (groups >= 2 && c->concurrent_bins) {
+        TRY(lane_sides(L));
+        HIPTRY(hipEventRecord(L->fork, s));
+        for (int i = 0; i < kSideStreams; ++i) HIPTRY(hipStreamWaitEvent(L->side[i], L->fork, 0));
+        join.L = L;
+        join.s = s;
+        join.pending = true;
+        s_wave = L->side[0];
+        s_block = L->side[1];
+        s_bucket = L->side[2];
+    }
+    for (int b = BIN_W64; b <= BIN_B8192; ++b)
+        launch_numeric_hash(b, bin_lists.as<int32_t>() + (int64_t)b * n_cand, h1.bin_count[b], na,
+                            b <= BIN_W512 ? s_wave : s_block, t);
+    if (nb > 0) {
+        launch_fill_i64(tile_cnt.as<int64_t>(), nb * (ntiles_z + 1), 0, s_bucket, t);
+        launch_numeric_bucket(bin_lists.as<int32_t>() + (int64_t)BIN_BUCKET * n_cand, nb, chunk_base.as<int64_t>(),
+                              h1.bucket_chunks, prod_base.as<int64_t>(), ntiles_z, tile_cnt.as<int64_t>(),
+                              tile_off.as<int64_t>(), prod_col.as<int32_t>(),
+                              valued ? prod_val.as<uint64_t>() : nullptr, na, s_bucket, t);
+    }
+    if (na.ytile) launch_tile_index(Y.op, ntiles_z, ytile.as<int32_t>(), s, t);
     if (h1.bin_count[BIN_DENSE] > 0)
         launch_numeric_dense(bin_lists.as<int32_t>() + (int64_t)BIN_DENSE * n_cand, h1.bin_count[BIN_DENSE],
                              task_base.as<int64_t>(), h1.dense_tasks, na, s, t);
-    Buf tile_cnt, tile_off, prod_col, prod_val;
-    if (h1.bin_count[BIN_BUCKET] > 0) {
-        const int64_t nb = h1.bin_count[BIN_BUCKET];
-        const int64_t ntiles = (Y.cols + kTileW - 1) / kTileW;
-        TRY(tile_cnt.alloc(pool, 8 * (size_t)nb * (ntiles + 1)));
-        TRY(tile_off.alloc(pool, 8 * (size_t)nb * (ntiles + 1)));
-        TRY(prod_col.alloc(pool, 4 * (size_t)std::max<int64_t>(h1.bucket_products, 1)));
-        const bool valued = X.op.val || Y.op.val;
-        if (valued) TRY(prod_val.alloc(pool, 8 * (size_t)std::max<int64_t>(h1.bucket_products, 1)));
-        launch_fill_i64(tile_cnt.as<int64_t>(), nb * (ntiles + 1), 0, s, t);
-        launch_numeric_bucket(bin_lists.as<int32_t>() + (int64_t)BIN_BUCKET * n_cand, nb, chunk_base.as<int64_t>(),
-                              h1.bucket_chunks, prod_base.as<int64_t>(), ntiles, tile_cnt.as<int64_t>(),
-                              tile_off.as<int64_t>(), prod_col.as<int32_t>(),
-                              valued ? prod_val.as<uint64_t>() : nullptr, na, s, t);
-    }
+    TRY(join.run());
 
     if (c->flags & ATP_OPT_COUNT_BYTES) TRY(count_bytes(c, L, X, Y, cand, bin_lists.as<int32_t>(), n_cand, h1,
                                                        row_nnz.as<int64_t>()));
@@ -1247,8 +1284,39 @@ atp_status lane_init(atp_ctx *c, Lane *L, int id) {
     return ATP_OK;
 }
 
+atp_status lane_sides(Lane *L) {
+    if (L->fork) return ATP_OK;
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (hipStreamCreateWithFlags(&L->side[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&L->join[i], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            lane_release_sides(L);
+            return ATP_EDEVICE;
+        }
+    }
+    if (hipEventCreateWithFlags(&L->fork, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        lane_release_sides(L);
+        return ATP_EDEVICE;
+    }
+    return ATP_OK;
+}
+void lane_release_sides(Lane *L) {
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (L->side[i]) {
+            (void)hipStreamSynchronize(L->side[i]);
+            (void)hipStreamDestroy(L->side[i]);
+        }
+        if (L->join[i]) (void)hipEventDestroy(L->join[i]);
+        L->side[i] = nullptr;
+        L->join[i] = nullptr;
+    }
+    if (L->fork) (void)hipEventDestroy(L->fork);
+    L->fork = nullptr;
+}
 void lane_destroy(Lane *L) {
     if (L->stream) (void)hipStreamSynchronize(L->stream);
+    lane_release_sides(L);
     L->timer.flush();
     L->pool.destroy();
     if (L->h_hdr) (void)hipHostFree(L->h_hdr);
@@ -1331,6 +1399,7 @@ atp_status atp_destroy(atp_ctx *c) {
     c->lanes.clear();
     c->rels.clear();
     c->props.clear();
+    lane_release_sides(&c->main);
     c->main.timer.flush();
     c->main.pool.destroy();
     if (c->main.h_hdr) (void)hipHostFree(c->main.h_hdr);

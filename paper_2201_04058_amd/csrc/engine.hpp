@@ -269,6 +269,9 @@ Tuning tuning_from_env();
 // One execution lane: a stream with its own memory pool, pinned header and
 // timers.  The context's main lane runs atp_eval; batch and serving workers
 // each own another, so their work overlaps on the device.
+// Side streams on which the numeric kernels of different bins run beside
+// the lane's stream (fork/join through events).
+constexpr int kSideStreams = 3;
 struct Lane {
     int id = 0;
     hipStream_t stream = nullptr;
@@ -276,7 +279,12 @@ struct Lane {
     Pool pool;
     StepHeader *h_hdr = nullptr;  // pinned
     KernelTimer timer;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr, join[kSideStreams] = {};
 };
+// creates the lane's side streams and events on first use
+atp_status lane_sides(Lane *L);
+void lane_release_sides(Lane *L);
 
 // Device-resident cached results and their bookkeeping (Sec. 3.3-3.4).
 struct CachePayload {
@@ -411,6 +419,8 @@ struct atp_ctx {
     int64_t heavy_ops = 64ll << 20;
     int64_t tile_index_cap = std::getenv("ATP_TILE_INDEX_CAP") ? std::atoll(std::getenv("ATP_TILE_INDEX_CAP"))
                                                                : (int64_t)256 << 20;  // entries (4 B each)
+    // the numeric bins of a product on the lane's side streams (ATP_SERIAL_BINS=1: all on one stream)
+    bool concurrent_bins = std::getenv("ATP_SERIAL_BINS") == nullptr;
     atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
     atp::KernelTimer *kt(atp::Lane *L) { return (flags & ATP_OPT_PROFILE) ? &L->timer : nullptr; }
 };
