@@ -60,6 +60,9 @@ typedef struct atp_result atp_result;
 #define ATP_OPT_COUNT_BYTES (1u << 2) /* count algorithmic bytes per kernel (extra passes; not for timing) */
 #define ATP_OPT_NO_RESTRICT (1u << 3) /* compute right sub-chains on all rows, not only on the rows the left
                                          operand reaches (same result; keeps sub-results start-independent) */
+#define ATP_OPT_SERIAL_BINS (1u << 4) /* run a product's numeric bins one after another on the context's
+                                         stream instead of beside each other on side streams (same result;
+                                         uncontended per-kernel times) */
 
 typedef struct {
     int device;                 /* HIP device ordinal */

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libatrapos.so")
 
 ATP_OK, ATP_EINVAL, ATP_ENOMEM, ATP_EOVERFLOW, ATP_ESCHEMA, ATP_EDEVICE, ATP_EBUDGET, ATP_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
-ATP_OPT_PROFILE, ATP_OPT_PLAN_EAC, ATP_OPT_COUNT_BYTES, ATP_OPT_NO_RESTRICT = 1, 2, 4, 8
+ATP_OPT_PROFILE, ATP_OPT_PLAN_EAC, ATP_OPT_COUNT_BYTES, ATP_OPT_NO_RESTRICT, ATP_OPT_SERIAL_BINS = 1, 2, 4, 8, 16
 ATP_REL_DEVICE_PTRS, ATP_REL_ADD_REVERSE = 1, 2
 ATP_I16, ATP_I32, ATP_I64 = 1, 2, 3
 ATP_C_RANGE, ATP_C_IDSET = 1, 2
@@ -525,9 +525,10 @@ class Context:
 
     # --- diagnostics -----------------------------------------------------
     def set_flags(self, profile: bool = False, plan_eac: bool = False, count_bytes: bool = False,
-                  no_restrict: bool = False) -> None:
+                  no_restrict: bool = False, serial_bins: bool = False) -> None:
         f = (ATP_OPT_PROFILE if profile else 0) | (ATP_OPT_PLAN_EAC if plan_eac else 0) | \
-            (ATP_OPT_COUNT_BYTES if count_bytes else 0) | (ATP_OPT_NO_RESTRICT if no_restrict else 0)
+            (ATP_OPT_COUNT_BYTES if count_bytes else 0) | (ATP_OPT_NO_RESTRICT if no_restrict else 0) | \
+            (ATP_OPT_SERIAL_BINS if serial_bins else 0)
         _check(lib().atp_set_flags(self._h, f), "atp_set_flags")
 
     def kernel_times(self) -> dict:
