@@ -331,7 +331,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         }
         ~Join() { (void)run(); }
     } join;
-    if (groups >= 2 && c->concurrent_bins && !(c->flags & ATP_OPT_SERIAL_BINS)) {
+    if (groups >= 2 && c->concurrent_bins && !(c->flags & ATP_OPT_SERIAL_BINS) && c->busy_lanes.load() <= 1) {
         TRY(lane_sides(L));
         HIPTRY(hipEventRecord(L->fork, s));
         for (int i = 0; i < kSideStreams; ++i) HIPTRY(hipStreamWaitEvent(L->side[i], L->fork, 0));

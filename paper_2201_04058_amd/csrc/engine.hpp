@@ -419,8 +419,11 @@ struct atp_ctx {
     int64_t heavy_ops = 64ll << 20;
     int64_t tile_index_cap = std::getenv("ATP_TILE_INDEX_CAP") ? std::atoll(std::getenv("ATP_TILE_INDEX_CAP"))
                                                                : (int64_t)256 << 20;  // entries (4 B each)
-    // the numeric bins of a product on the lane's side streams (ATP_SERIAL_BINS=1: all on one stream)
+    // the numeric bins of a product on the lane's side streams (ATP_SERIAL_BINS=1: all on one stream);
+    // only while at most one lane is busy (several lanes already keep the GPU busy, and their side
+    // streams would outnumber the hardware queues)
     bool concurrent_bins = std::getenv("ATP_SERIAL_BINS") == nullptr;
+    std::atomic<int> busy_lanes{0};  // lanes a batch or the server runs at once
     atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
     atp::KernelTimer *kt(atp::Lane *L) { return (flags & ATP_OPT_PROFILE) ? &L->timer : nullptr; }
 };

@@ -444,6 +444,7 @@ void server_shutdown(atp_ctx *c) {
     }
     c->server->cv_work.notify_all();
     for (auto &w : c->server->workers) w.join();
+    c->busy_lanes.store(0);
     for (auto &cp : c->server->done)
         if (cp.result) atp_result_free(cp.result);
     delete c->server;
@@ -491,9 +492,11 @@ atp_status atp_eval_batch(atp_ctx *c, const atp_query *queries, int32_t n, int32
         for (size_t gi; (gi = next.fetch_add(1)) < groups.size();) run_group_gated(c, L, groups[gi], gate, nl);
     };
     std::vector<std::thread> th;
+    c->busy_lanes.store(nl);
     for (int l = 1; l < nl; ++l) th.emplace_back(drain, c->lanes[l].get());
     drain(c->lanes[0].get());
     for (auto &x : th) x.join();
+    c->busy_lanes.store(0);
     {
         std::lock_guard<std::mutex> g(c->gate.mu);
         c->gate.budget = 0;
@@ -518,6 +521,7 @@ atp_status atp_server_start(atp_ctx *c, const atp_server_options *o) {
     c->server = new Server();
     c->server->max_batch = o->max_batch;
     c->server->lanes = o->lanes;
+    c->busy_lanes.store(o->lanes);
     for (int l = 0; l < o->lanes; ++l) c->server->workers.emplace_back(worker, c, c->lanes[l].get());
     return ATP_OK;
 }
