@@ -1322,14 +1322,18 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
         const int64_t c0p = t0 * W, c1p = (t1 * W < ycols) ? t1 * W : ycols;
         const bool single = xlen <= NT;
 
-        // part-level product count
+        // part-level product count, when the part may be sparse enough for the
+        // LDS hash (a row whose mean part holds more than twice the hash
+        // capacity goes straight to the dense tiles)
+        const bool may_hash = ks == 1 && (c1p - c0p) <= (int64_t)kPartMaxTiles * W &&
+                              a.nop[c] <= 2 * a.tune.part_hash_cap * nparts;
         int64_t ltot = 0;
-        if (ks == 1) {
+        if (may_hash) {
             for (int64_t eb = 0; eb < xlen; eb += NT) ltot += segments(xb, xlen, eb, c0p, c1p, false, false);
             if (ltot == 0) continue;
         }
 
-        if (ks == 1 && ltot <= a.tune.part_hash_cap && (c1p - c0p) <= (int64_t)kPartMaxTiles * W) {
+        if (may_hash && ltot <= a.tune.part_hash_cap) {
             // sparse part: values in an LDS hash, presence in a bitmap over the
             // part's columns (both overlaid on the tile memory); emission walks
             // the bitmap in column order and looks each column up.
