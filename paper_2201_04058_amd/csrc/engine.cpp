@@ -299,10 +299,13 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
             na.ytile = ytile.as<int32_t>();
         }
     }
-    Buf tile_cnt, tile_off, prod_col, prod_val;
+    Buf tile_cnt, tile_off, prod_col, prod_val, chunk_hist, parts;
     const int64_t nb = h1.bin_count[BIN_BUCKET];
     const bool valued = X.op.val || Y.op.val;
     if (nb > 0) {
+        TRY(parts.alloc(pool, 8 * (size_t)bucket_parts_elems(nb)));
+        if (h1.bucket_chunks * ntiles_z <= c->chunk_hist_cap)
+            TRY(chunk_hist.alloc(pool, 8 * (size_t)std::max<int64_t>(h1.bucket_chunks * ntiles_z, 1)));
         TRY(tile_cnt.alloc(pool, 8 * (size_t)nb * (ntiles_z + 1)));
         TRY(tile_off.alloc(pool, 8 * (size_t)nb * (ntiles_z + 1)));
         TRY(prod_col.alloc(pool, 4 * (size_t)std::max<int64_t>(h1.bucket_products, 1)));
@@ -350,7 +353,8 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         launch_numeric_bucket(bin_lists.as<int32_t>() + (int64_t)BIN_BUCKET * n_cand, nb, chunk_base.as<int64_t>(),
                               h1.bucket_chunks, prod_base.as<int64_t>(), ntiles_z, tile_cnt.as<int64_t>(),
                               tile_off.as<int64_t>(), prod_col.as<int32_t>(),
-                              valued ? prod_val.as<uint64_t>() : nullptr, na, s_bucket, t);
+                              valued ? prod_val.as<uint64_t>() : nullptr, chunk_hist.as<int64_t>(),
+                              parts.as<int64_t>(), na, s_bucket, t);
     }
     if (na.ytile) launch_tile_index(Y.op, ntiles_z, ytile.as<int32_t>(), s, t);
     if (h1.bin_count[BIN_DENSE] > 0)

@@ -424,6 +424,9 @@ struct atp_ctx {
     // streams would outnumber the hardware queues)
     bool concurrent_bins = std::getenv("ATP_SERIAL_BINS") == nullptr;
     std::atomic<int> busy_lanes{0};  // lanes a batch or the server runs at once
+    // per-chunk tile counts of the bucket path kept up to this many entries (ATP_CHUNK_HIST_CAP)
+    int64_t chunk_hist_cap = std::getenv("ATP_CHUNK_HIST_CAP") ? std::atoll(std::getenv("ATP_CHUNK_HIST_CAP"))
+                                                               : atp::kChunkHistCap;
     atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
     atp::KernelTimer *kt(atp::Lane *L) { return (flags & ATP_OPT_PROFILE) ? &L->timer : nullptr; }
 };

@@ -171,10 +171,15 @@ void launch_numeric_dense(const int32_t *list, int64_t n_list, const int64_t *ta
 
 // per-row column-tile offsets of Y (the dense kernel's segment bounds)
 void launch_tile_index(const Operand &Y, int64_t ntiles, int32_t *ytile, hipStream_t s, KernelTimer *t);
+// chunk_hist: [n_chunks * ntiles] int64 scratch (per-chunk tile counts, then bucket bases), or
+// nullptr (the scatter pass then counts its chunk's products again); parts: int64 scratch of
+// bucket_parts_elems(n_list) entries (accumulation parts per row, their scan and its temporaries)
 void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *chunk_base, int64_t n_chunks,
                            const int64_t *prod_base, int64_t ntiles, int64_t *tile_cnt, int64_t *tile_off,
-                           int32_t *prod_col, uint64_t *prod_val, const NumericArgs &a, hipStream_t s,
-                           KernelTimer *t);
+                           int32_t *prod_col, uint64_t *prod_val, int64_t *chunk_hist, int64_t *parts,
+                           const NumericArgs &a, hipStream_t s, KernelTimer *t);
+inline int64_t bucket_parts_elems(int64_t n_list) { return 2 * n_list + 1 + scan_tmp_elems(n_list); }
+constexpr int64_t kChunkHistCap = (int64_t)64 << 20;  // per-chunk tile counts kept up to this many entries
 
 // compaction
 void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,

@@ -1522,7 +1522,22 @@ struct BucketArgs {
     int32_t *prod_col;
     uint64_t *prod_val;
     int g;                      // lanes per left entry (power of two <= 64)
+    int64_t *chunk_hist;        // [n_chunks * ntiles] per-chunk tile counts, then bucket bases; or nullptr
+    int64_t *part_cnt;          // [n_list] parts per row
+    int64_t *part_base;         // [n_list + 1] exclusive scan of part_cnt
 };
+
+// tiles per accumulation part of a bucket row with nop products: the part
+// target over the row's mean products per tile, at most kPartMaxTiles
+__device__ __forceinline__ int64_t bucket_part_tiles(int64_t nop, int64_t ntiles, const Tuning &tune) {
+    const int64_t per_tile = nop / ntiles;
+    int64_t m = 1;
+    if (per_tile < tune.part_target) {
+        m = tune.part_target / (per_tile > 0 ? per_tile : 1);
+        m = m > kPartMaxTiles ? kPartMaxTiles : (m < 1 ? 1 : m);
+    }
+    return m;
+}
 
 // Products of X entries [e0, e1) of one row in batches of kBucketThreads
 // entries, walked flattened: f(column, value) for each.
@@ -1575,16 +1590,24 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, N
                              [&](int32_t j, uint64_t) { atomicAdd(&hist[j >> kTileShift], 1); });
         __syncthreads();
         int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
-        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x)
+        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
             if (hist[t]) atomicAdd((unsigned long long *)&cnt[t], (unsigned long long)hist[t]);
+            if (b.chunk_hist) b.chunk_hist[id * b.ntiles + t] = hist[t];
+        }
         __syncthreads();
     }
 }
 
-// per bucket row: tile_off = prod_base + exclusive scan of the tile counts; counts become cursors
-__global__ __launch_bounds__(256) void k_bucket_scan(BucketArgs b) {
+// per bucket row: tile_off = prod_base + exclusive scan of the tile counts; counts become cursors.
+// With per-chunk counts, each chunk's count of a tile becomes the chunk's base in that bucket (the
+// tile's offset plus the counts of the row's earlier chunks).
+__global__ __launch_bounds__(256) void k_bucket_scan(BucketArgs b, Tuning tune) {
     __shared__ int64_t sw[4];
     for (int64_t p = blockIdx.x; p < b.n_list; p += gridDim.x) {
+        if (threadIdx.x == 0) {
+            const int64_t m = bucket_part_tiles(b.prod_base[p + 1] - b.prod_base[p], b.ntiles, tune);
+            b.part_cnt[p] = (b.ntiles + m - 1) / m;
+        }
         int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
         int64_t *off = b.tile_off + p * (b.ntiles + 1);
         int64_t carry = b.prod_base[p];
@@ -1601,6 +1624,16 @@ __global__ __launch_bounds__(256) void k_bucket_scan(BucketArgs b) {
         }
         if (threadIdx.x == 0) off[b.ntiles] = carry;
         __syncthreads();
+        if (b.chunk_hist) {
+            for (int64_t t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
+                int64_t run = off[t];
+                for (int64_t q = b.chunk_base[p]; q < b.chunk_base[p + 1]; ++q) {
+                    const int64_t v = b.chunk_hist[q * b.ntiles + t];
+                    b.chunk_hist[q * b.ntiles + t] = run;
+                    run += v;
+                }
+            }
+        }
     }
 }
 
@@ -1618,23 +1651,32 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
         const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
         const int64_t bc = a.tune.bucket_chunk;
         const int64_t e0 = xb + q * bc, e1 = e0 + bc < xe ? e0 + bc : xe;
-        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
-        __syncthreads();
-        if (b.g >= kRunMinLanes)
-            for_product_runs(a.X, a.Y, e0, e1, b.g, [&](bool, int32_t tile, int32_t, uint64_t, const TileRun &r) {
-                if (r.head) atomicAdd(&hist[tile], r.len);
-            });
-        else
-            walk_entry_range(a, e0, e1, seg_s, seg_o, sw,
-                             [&](int32_t j, uint64_t) { atomicAdd(&hist[j >> kTileShift], 1); });
-        __syncthreads();
-        int64_t *cur = b.tile_cnt + p * (b.ntiles + 1);
-        for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
-            int32_t h = hist[t];
-            base[t] = h ? (int64_t)atomicAdd((unsigned long long *)&cur[t], (unsigned long long)h) : 0;
-            hist[t] = 0;
+        if (b.chunk_hist) {  // the chunk's bucket bases from the scan
+            for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
+                base[t] = b.chunk_hist[id * b.ntiles + t];
+                hist[t] = 0;
+            }
+            __syncthreads();
+        } else {  // count the chunk's products per tile again and reserve its ranges
+            for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) hist[t] = 0;
+            __syncthreads();
+            if (b.g >= kRunMinLanes)
+                for_product_runs(a.X, a.Y, e0, e1, b.g,
+                                 [&](bool, int32_t tile, int32_t, uint64_t, const TileRun &r) {
+                                     if (r.head) atomicAdd(&hist[tile], r.len);
+                                 });
+            else
+                walk_entry_range(a, e0, e1, seg_s, seg_o, sw,
+                                 [&](int32_t j, uint64_t) { atomicAdd(&hist[j >> kTileShift], 1); });
+            __syncthreads();
+            int64_t *cur = b.tile_cnt + p * (b.ntiles + 1);
+            for (int t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
+                int32_t h = hist[t];
+                base[t] = h ? (int64_t)atomicAdd((unsigned long long *)&cur[t], (unsigned long long)h) : 0;
+                hist[t] = 0;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const bool valued = b.prod_val != nullptr;
         if (b.g >= kRunMinLanes)
             for_product_runs(a.X, a.Y, e0, e1, b.g,
@@ -1677,19 +1719,22 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
     }
     if (tid == 0) s_sat = 0;
     __syncthreads();
-    const int64_t n_tasks = b.n_list * b.ntiles;
+    // one task per part of m consecutive tiles of a row (m from the row's
+    // mean products per tile); part_base enumerates them
+    const int64_t n_tasks = b.part_base[b.n_list];
     const bool valued = b.prod_val != nullptr;
     for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
-        const int64_t p = task / b.ntiles, t = task % b.ntiles;
-        // parts of m consecutive tiles, m from the row's mean products per tile
-        const int64_t nop = b.prod_base[p + 1] - b.prod_base[p];
-        const int64_t per_tile = nop / b.ntiles;
-        int64_t m = 1;
-        if (per_tile < a.tune.part_target) {
-            m = a.tune.part_target / (per_tile > 0 ? per_tile : 1);
-            m = m > kPartMaxTiles ? kPartMaxTiles : (m < 1 ? 1 : m);
+        int64_t lo = 0, hi = b.n_list;  // last p with part_base[p] <= task
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (b.part_base[mid] <= task)
+                lo = mid;
+            else
+                hi = mid;
         }
-        if (t % m) continue;  // the task of the part's first tile does the part
+        const int64_t p = lo;
+        const int64_t m = bucket_part_tiles(b.prod_base[p + 1] - b.prod_base[p], b.ntiles, a.tune);
+        const int64_t t = (task - b.part_base[p]) * m;
         const int64_t t1 = (t + m < b.ntiles) ? t + m : b.ntiles;
         const int64_t *off = b.tile_off + p * (b.ntiles + 1);
         if (off[t] == off[t1]) continue;  // uniform across the block
@@ -2108,16 +2153,18 @@ void launch_tile_index(const Operand &Y, int64_t ntiles, int32_t *ytile, hipStre
 
 void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *chunk_base, int64_t n_chunks,
                            const int64_t *prod_base, int64_t ntiles, int64_t *tile_cnt, int64_t *tile_off,
-                           int32_t *prod_col, uint64_t *prod_val, const NumericArgs &a, hipStream_t s,
-                           KernelTimer *t) {
+                           int32_t *prod_col, uint64_t *prod_val, int64_t *chunk_hist, int64_t *parts,
+                           const NumericArgs &a, hipStream_t s, KernelTimer *t) {
     if (n_list <= 0 || n_chunks <= 0) return;
     const int64_t yavg = a.Y.rows > 0 ? a.Y.nnz / a.Y.rows : 1;
     BucketArgs b{list, n_list, chunk_base, n_chunks, prod_base, ntiles, tile_cnt, tile_off, prod_col, prod_val,
-                 group_size(yavg)};
+                 group_size(yavg), chunk_hist, parts, parts + n_list};
     const int cus = device_cus();
     const int64_t gc = n_chunks < (int64_t)cus * 4 ? n_chunks : (int64_t)cus * 4;
     ATP_LAUNCH("bucket", 0, 0, s, k_bucket_count, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);
-    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scan, dim3((unsigned)(n_list < 1024 ? n_list : 1024)), dim3(256), 0, s, b);
+    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scan, dim3((unsigned)(n_list < 1024 ? n_list : 1024)), dim3(256), 0, s, b,
+               a.tune);
+    launch_scan_i64(b.part_cnt, b.part_base, n_list, b.part_base + n_list + 1, s, t);
     ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scatter, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);
     const int64_t n_tasks = n_list * ntiles;
     const int64_t ga = n_tasks < (int64_t)cus * 2 ? n_tasks : (int64_t)cus * 2;
