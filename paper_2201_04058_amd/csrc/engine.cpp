@@ -345,7 +345,9 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         s_block = L->side[1];
         s_bucket = L->side[2];
     }
-    for (int b = BIN_W64; b <= BIN_B8192; ++b)
+    // the largest hash bins first: their rows take longest, and they get CUs before the
+    // dense kernel's persistent workgroups fill the LDS
+    for (int b = BIN_B8192; b >= BIN_W64; --b)
         launch_numeric_hash(b, bin_lists.as<int32_t>() + (int64_t)b * n_cand, h1.bin_count[b], na,
                             b <= BIN_W512 ? s_wave : s_block, t);
     if (nb > 0) {

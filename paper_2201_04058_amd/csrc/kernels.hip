@@ -1790,8 +1790,10 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
 // ---------------------------------------------------------------------------
 // compaction
 
-__global__ void k_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
-                                const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val) {
+__global__ void k_copy_segments(const int64_t *__restrict__ seg_cnt, const int64_t *__restrict__ seg_src,
+                                const int64_t *__restrict__ seg_dst, int64_t n_segs,
+                                const int32_t *__restrict__ slot_col, const uint64_t *__restrict__ slot_val,
+                                int32_t *__restrict__ col, uint64_t *__restrict__ val) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1799,7 +1801,22 @@ __global__ void k_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, 
         const int64_t n = seg_cnt[sgm];
         if (n == 0) continue;
         const int64_t src = seg_src[sgm], dst = seg_dst[sgm];
-        for (int64_t t = lane; t < n; t += 64) {
+        int64_t t = lane;
+        for (; t + 192 < n; t += 256) {  // four loads of each array in flight per lane
+            int32_t c[4];
+            uint64_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = slot_col[src + t + 64 * u];
+                v[u] = slot_val[src + t + 64 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                col[dst + t + 64 * u] = c[u];
+                val[dst + t + 64 * u] = v[u];
+            }
+        }
+        for (; t < n; t += 64) {
             col[dst + t] = slot_col[src + t];
             val[dst + t] = slot_val[src + t];
         }
