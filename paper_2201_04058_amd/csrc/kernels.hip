@@ -393,6 +393,7 @@ __device__ __forceinline__ int64_t sum_right_rows(const Operand &X, const Operan
 // Eight lanes per candidate row (they stride over its entries); rows longer
 // than kLongRow are left to the chunked pass.
 constexpr int kSymLanes = 8;
+constexpr int kBinThreads = 1024;  // rows per binning workgroup
 __global__ __launch_bounds__(256) void k_symbolic(SymbolicArgs a) {
     const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kSymLanes;
     const int li = threadIdx.x & (kSymLanes - 1);
@@ -417,18 +418,26 @@ __global__ __launch_bounds__(256) void k_symbolic(SymbolicArgs a) {
         a.bucket_chunks[c] = 0;
         a.bucket_nop[c] = 0;
     }
+    // the step's product total: one atomic per workgroup
+    __shared__ int64_t s_sum[4];
     int64_t wsum = li == 0 ? nop : 0;
     for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
-    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)wsum);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = wsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t bsum = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        if (bsum) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)bsum);
+    }
 }
 
 // Long rows are cut into chunks of kSymChunk entries (long_len holds each
 // candidate's chunk count, long_off its exclusive scan); one workgroup per
-// chunk sums the products and adds them with one atomic.
+// chunk sums the products and adds them to the row with one atomic.
 __global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a, const int64_t *long_off) {
     __shared__ int64_t sw[4];
     __shared__ int64_t s_c;
     const int64_t n_chunks = long_off[a.n_cand];
+    int64_t block_total = 0;  // thread 0's sum over the workgroup's chunks
     for (int64_t id = blockIdx.x; id < n_chunks; id += gridDim.x) {
         if (threadIdx.x < 64) {
             const int64_t c = group_lower_bound(long_off, 0, a.n_cand, id + 1, 64, threadIdx.x, ~0ull) - 1;
@@ -445,15 +454,20 @@ __global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a, const int
         block_inclusive_scan(s, sw, &tot);
         if (threadIdx.x == 0 && tot) {
             atomicAdd((unsigned long long *)&a.nop[c], (unsigned long long)tot);
-            atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)tot);
+            block_total += tot;
         }
     }
+    // the step's product total: one atomic per workgroup
+    if (threadIdx.x == 0 && block_total) atomicAdd((unsigned long long *)&a.hdr->n_op_total, (unsigned long long)block_total);
 }
 
-__global__ void k_bin_rows(SymbolicArgs a) {
+__global__ __launch_bounds__(kBinThreads) void k_bin_rows(SymbolicArgs a) {
+    constexpr int NWV = kBinThreads / 64;
+    __shared__ int32_t s_cnt[BIN_COUNT][NWV];           // members per (bin, wavefront)
+    __shared__ unsigned long long s_base[BIN_COUNT][NWV];  // list position of each wavefront's first
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool live = c < a.n_cand;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t nop = live ? a.nop[c] : 0;
     int64_t ub = nop < a.ycols_eff ? nop : a.ycols_eff;
     int32_t bin = BIN_NONE;
@@ -480,15 +494,28 @@ __global__ void k_bin_rows(SymbolicArgs a) {
         a.nseg[c] = nseg;
         a.bin[c] = bin;
     }
-    // bin lists: one atomic per (wavefront, bin)
+    // bin lists: one atomic per (workgroup, bin); wavefronts take consecutive ranges
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int b = BIN_W64; b < BIN_COUNT; ++b) {
         const uint64_t m = __ballot(bin == b);
+        if (lane == 0) s_cnt[b][wave] = __popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x >= BIN_W64 && threadIdx.x < BIN_COUNT) {
+        const int b = threadIdx.x;
+        unsigned long long tot = 0;
+        for (int w = 0; w < NWV; ++w) tot += (unsigned long long)s_cnt[b][w];
+        unsigned long long base = tot ? atomicAdd((unsigned long long *)&a.hdr->bin_count[b], tot) : 0ull;
+        for (int w = 0; w < NWV; ++w) {
+            s_base[b][w] = base;
+            base += (unsigned long long)s_cnt[b][w];
+        }
+    }
+    __syncthreads();
+    for (int b = BIN_W64; b < BIN_COUNT; ++b) {
+        const uint64_t m = __ballot(bin == b);
         if (m == 0) continue;
-        const int leader = __builtin_ctzll(m);
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd((unsigned long long *)&a.hdr->bin_count[b], (unsigned long long)__popcll(m));
-        base = __shfl(base, leader, 64);
+        const unsigned long long base = s_base[b][wave];
         if (bin == b) {
             const int64_t pos = (int64_t)base + __popcll(m & lt);
             a.bin_lists[(int64_t)b * a.n_cand + pos] = (int32_t)c;
@@ -2123,7 +2150,8 @@ void launch_symbolic(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
 
 void launch_bin_rows(const SymbolicArgs &a, hipStream_t s, KernelTimer *t) {
     if (a.n_cand <= 0) return;
-    ATP_LAUNCH("binning", 0, 0, s, k_bin_rows, dim3((unsigned)((a.n_cand + 255) / 256)), dim3(256), 0, s, a);
+    ATP_LAUNCH("binning", 0, 0, s, k_bin_rows, dim3((unsigned)((a.n_cand + kBinThreads - 1) / kBinThreads)),
+               dim3(kBinThreads), 0, s, a);
 }
 
 void launch_numeric_hash(int32_t bin, const int32_t *list, int64_t n, const NumericArgs &a, hipStream_t s,
