@@ -406,6 +406,13 @@ int32_t atp_kernel_times(atp_ctx *ctx, const char **names, double *ms, int64_t *
                          int32_t cap);
 void atp_kernel_times_reset(atp_ctx *ctx);
 
+/* Restrict ATP_OPT_PROFILE to the launches of one kernel name (as reported by
+ * atp_kernel_times, e.g. "dense"); NULL or "" times every launch again.  A
+ * timed launch records two HIP events, so timing one kernel leaves the rest
+ * of a query's launch sequence as it runs unprofiled.  The name is copied.
+ * Returns ATP_EINVAL for a NULL context. */
+atp_status atp_set_profile_kernel(atp_ctx *ctx, const char *name);
+
 /* Bytes of device memory currently held by the context (pool included). */
 int64_t atp_device_bytes(const atp_ctx *ctx);
 

@@ -25,6 +25,7 @@ EXPORTS = [
     "atp_create", "atp_destroy", "atp_add_node_type", "atp_add_relation", "atp_add_property",
     "atp_eval", "atp_eval_plan", "atp_result_csr", "atp_result_to_host", "atp_result_stats",
     "atp_result_free", "atp_plan_chain", "atp_set_flags", "atp_kernel_times", "atp_kernel_times_reset",
+    "atp_set_profile_kernel",
     "atp_device_bytes", "atp_status_str", "atp_cache_configure", "atp_cache_get_stats", "atp_otree_create",
     "atp_otree_destroy", "atp_otree_insert", "atp_otree_frequency", "atp_otree_shape", "atp_cache_simulate",
     "atp_eval_batch", "atp_server_start", "atp_submit", "atp_poll", "atp_server_pending", "atp_server_stop",
@@ -134,6 +135,7 @@ def lib() -> ctypes.CDLL:
         "atp_set_flags": ([vp, u32], i32),
         "atp_kernel_times": ([vp, P(ctypes.c_char_p), P(ctypes.c_double), P(i64), P(ctypes.c_double), i32], i32),
         "atp_kernel_times_reset": ([vp], None),
+        "atp_set_profile_kernel": ([vp, ctypes.c_char_p], ctypes.c_int32),
         "atp_device_bytes": ([vp], i64),
         "atp_status_str": ([i32], ctypes.c_char_p),
         "atp_cache_configure": ([vp, i32, ctypes.c_uint64], i32),
@@ -543,6 +545,10 @@ class Context:
 
     def kernel_times_reset(self) -> None:
         lib().atp_kernel_times_reset(self._h)
+
+    def set_profile_kernel(self, name: str | None) -> None:
+        """Time only the launches of this kernel (None: every launch) under profile=True."""
+        _check(lib().atp_set_profile_kernel(self._h, name.encode() if name else None), "atp_set_profile_kernel")
 
     def device_bytes(self) -> int:
         return int(lib().atp_device_bytes(self._h))

@@ -18,6 +18,8 @@ namespace atp {
 
 void timer_begin(KernelTimer *t, const char *name, hipStream_t s) {
     if (!t) return;
+    t->skip = !t->only.empty() && t->only != name;
+    if (t->skip) return;
     KernelTimer::Rec r{std::string(name) + t->suffix, t->take(), t->take()};
     if (r.e0) (void)hipEventRecord(r.e0, s);
     t->pending.push_back(r);
@@ -25,6 +27,10 @@ void timer_begin(KernelTimer *t, const char *name, hipStream_t s) {
 
 void timer_end(KernelTimer *t, hipStream_t s) {
     if (!t || t->pending.empty()) return;
+    if (t->skip) {
+        t->skip = false;
+        return;
+    }
     auto &r = t->pending.back();
     if (r.e1) (void)hipEventRecord(r.e1, s);
 }
@@ -1634,6 +1640,13 @@ int32_t atp_kernel_times(atp_ctx *c, const char **names, double *ms, int64_t *la
         ++n;
     }
     return n;
+}
+
+atp_status atp_set_profile_kernel(atp_ctx *c, const char *name) {
+    if (!c) return ATP_EINVAL;
+    c->main.timer.only = name ? name : "";
+    for (auto &ln : c->lanes) ln->timer.only = c->main.timer.only;
+    return ATP_OK;
 }
 
 void atp_kernel_times_reset(atp_ctx *c) {

@@ -31,6 +31,8 @@ struct KernelTimer {
         hipEvent_t e0, e1;
     };
     std::string suffix;  // appended to kernel names (per-product breakdown)
+    std::string only;    // time only launches of this kernel name (empty: all)
+    bool skip = false;   // the current launch is not timed
     std::vector<hipEvent_t> free_events;
     std::vector<Rec> pending;
     std::map<std::string, std::pair<double, int64_t>> acc;
