@@ -372,3 +372,29 @@ def test_every_kernel_path_under_forced_tunings(atp, oracle_mod, tune, monkeypat
     ctx = make_ctx(atp, hin)
     assert_same(ctx.eval_query(qs[0]), oracle_mod.eval_full(hin, qs[0]), f"{tune} tiny")
     ctx.close()
+
+
+def test_profiling_one_kernel(atp, oracle_mod):
+    """Timing every launch, then only one kernel's, leaves results as they
+    are; the restricted table names only that kernel."""
+    hin, rng = configs.make_hin("scholarly", 0.02)
+    qs = configs.make_queries("scholarly", hin, rng)
+    ctx = make_ctx(atp, hin)
+    q = qs[3]
+    ref = oracle_mod.eval_full(hin, q, nthreads=8)
+    ctx.set_flags(profile=True)
+    ctx.kernel_times_reset()
+    assert_same(ctx.eval_query(q), ref, "profile all")
+    every = {k: v for k, v in ctx.kernel_times().items() if v[1] > 0}
+    assert "symbolic" in every and len(every) > 3
+    name = max(every, key=lambda k: every[k][0])
+    ctx.set_profile_kernel(name)
+    ctx.kernel_times_reset()
+    assert_same(ctx.eval_query(q), ref, f"profile {name}")
+    only = {k: v for k, v in ctx.kernel_times().items() if v[1] > 0}
+    assert set(only) == {name} and only[name][1] == every[name][1]
+    ctx.set_profile_kernel(None)
+    ctx.kernel_times_reset()
+    ctx.eval_query(q).free()
+    assert {k for k, v in ctx.kernel_times().items() if v[1] > 0} == set(every)
+    ctx.close()
