@@ -70,9 +70,38 @@ atp_status sync(Lane *L) {
     return ATP_OK;
 }
 
+// n int64 values from device memory into the lane's pinned header area: a
+// posting kernel writes them and a sequence number into host memory and the
+// host polls the number (no stream synchronisation on the way); while the
+// stream still runs, it is queried now and then so that a device error ends
+// the wait.  Without a device-writable mailbox: a copy and a synchronisation.
+atp_status read_values(Lane *L, const int64_t *src, int64_t n) {
+    if (!L->d_mailbox) {
+        HIPTRY(hipMemcpyAsync(L->h_hdr, src, 8 * (size_t)n, hipMemcpyDeviceToHost, L->stream));
+        return sync(L);
+    }
+    const uint64_t seq = ++L->seq;
+    launch_post(src, n, L->d_mailbox, L->d_flag, seq, L->stream);
+    HIPTRY(hipGetLastError());
+    for (uint64_t it = 1;; ++it) {
+        if (__atomic_load_n(L->h_flag, __ATOMIC_ACQUIRE) == seq) return ATP_OK;
+        if ((it & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(L->stream);
+            if (e == hipSuccess) {  // the post has run: its values are visible after a synchronisation
+                HIPTRY(hipStreamSynchronize(L->stream));
+                return __atomic_load_n(L->h_flag, __ATOMIC_ACQUIRE) == seq ? ATP_OK : ATP_EDEVICE;
+            }
+            if (e != hipErrorNotReady) {
+                (void)hipGetLastError();
+                return ATP_EDEVICE;
+            }
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 atp_status read_header(Lane *L, const StepHeader *d_hdr) {
-    HIPTRY(hipMemcpyAsync(L->h_hdr, d_hdr, sizeof(StepHeader), hipMemcpyDeviceToHost, L->stream));
-    return sync(L);
+    return read_values(L, (const int64_t *)d_hdr, (int64_t)(sizeof(StepHeader) / 8));
 }
 
 // A matrix produced by (or feeding) one plan node.
@@ -328,28 +357,39 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     struct Join {
         Lane *L = nullptr;
         hipStream_t s = nullptr;
-        bool pending = false;
+        int n = 0;  // side streams forked
         atp_status run() {
-            if (!pending) return ATP_OK;
-            pending = false;
             atp_status st = ATP_OK;
-            for (int i = 0; i < kSideStreams; ++i)
+            for (int i = 0; i < n; ++i)
                 if (hipEventRecord(L->join[i], L->side[i]) != hipSuccess || hipStreamWaitEvent(s, L->join[i], 0) != hipSuccess)
                     st = ATP_EDEVICE;
+            n = 0;
             return st;
         }
         ~Join() { (void)run(); }
     } join;
     if (groups >= 2 && c->concurrent_bins && !(c->flags & ATP_OPT_SERIAL_BINS) && c->busy_lanes.load() <= 1) {
+        // the dense rows (else the first other group) keep the lane's stream; each
+        // further non-empty group takes a side stream forked from it
         TRY(lane_sides(L));
+        bool main_taken = h1.bin_count[BIN_DENSE] > 0;
+        int used = 0;
+        auto take = [&](bool present) -> hipStream_t {
+            if (!present) return s;
+            if (!main_taken) {
+                main_taken = true;
+                return s;
+            }
+            return L->side[used++];
+        };
+        s_wave = take(any_wave);
+        s_block = take(any_block);
+        s_bucket = take(nb > 0);
         HIPTRY(hipEventRecord(L->fork, s));
-        for (int i = 0; i < kSideStreams; ++i) HIPTRY(hipStreamWaitEvent(L->side[i], L->fork, 0));
+        for (int i = 0; i < used; ++i) HIPTRY(hipStreamWaitEvent(L->side[i], L->fork, 0));
         join.L = L;
         join.s = s;
-        join.pending = true;
-        s_wave = L->side[0];
-        s_block = L->side[1];
-        s_bucket = L->side[2];
+        join.n = used;
     }
     // the largest hash bins first: their rows take longest, and they get CUs before the
     // dense kernel's persistent workgroups fill the LDS
@@ -1002,9 +1042,8 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         } else
             launch_cols_to_bits(X.op.col, X.nnz, X.nnz_dev, bits.as<uint32_t>(), s, t);
         launch_bits_count(bits.as<uint32_t>(), words, cnt.as<int64_t>(), scan.as<int64_t>(), tmpb.as<int64_t>(), s, t);
-        int64_t n = 0;
-        HIPTRY(hipMemcpyAsync(&n, scan.as<int64_t>() + words, 8, hipMemcpyDeviceToHost, s));
-        TRY(sync(L));
+        TRY(read_values(L, scan.as<int64_t>() + words, 1));
+        const int64_t n = *(const int64_t *)L->h_hdr;
         TRY(list.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(n, 1)));
         launch_bits_scatter(bits.as<uint32_t>(), words, scan.as<int64_t>(), list.as<int32_t>(), s, t);
         r.bits = bits.as<uint32_t>();
@@ -1289,11 +1328,45 @@ atp_status lane_init(atp_ctx *c, Lane *L, int id) {
         return ATP_EDEVICE;
     }
     L->own_stream = true;
-    if (hipHostMalloc((void **)&L->h_hdr, sizeof(StepHeader), hipHostMallocDefault) != hipSuccess) {
+    return lane_mailbox(L);
+}
+
+// The pinned block holds the step header (a mailbox of posted values) and,
+// 64-byte aligned after it, the post flag; both get device addresses when
+// the runtime maps them (else values are read by copies).
+atp_status lane_mailbox(Lane *L) {
+    constexpr size_t hdr_bytes = (sizeof(StepHeader) + 63) / 64 * 64;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, hdr_bytes + 64, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return ATP_ENOMEM;
     }
+    std::memset(p, 0, hdr_bytes + 64);
+    L->h_hdr = (StepHeader *)p;
+    L->h_flag = (uint64_t *)((char *)p + hdr_bytes);
+    L->seq = 0;
+    void *dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, p, 0) == hipSuccess && dp) {
+        L->d_mailbox = (int64_t *)dp;
+        L->d_flag = (uint64_t *)((char *)dp + hdr_bytes);
+    } else {
+        (void)hipGetLastError();
+        L->d_mailbox = nullptr;
+        L->d_flag = nullptr;
+    }
+    if (std::getenv("ATP_NO_MAILBOX")) {  // read posted values by copies instead
+        L->d_mailbox = nullptr;
+        L->d_flag = nullptr;
+    }
     return ATP_OK;
+}
+
+void lane_free_mailbox(Lane *L) {
+    if (L->h_hdr) (void)hipHostFree(L->h_hdr);
+    L->h_hdr = nullptr;
+    L->h_flag = nullptr;
+    L->d_mailbox = nullptr;
+    L->d_flag = nullptr;
 }
 
 atp_status lane_sides(Lane *L) {
@@ -1331,8 +1404,7 @@ void lane_destroy(Lane *L) {
     lane_release_sides(L);
     L->timer.flush();
     L->pool.destroy();
-    if (L->h_hdr) (void)hipHostFree(L->h_hdr);
-    L->h_hdr = nullptr;
+    lane_free_mailbox(L);
     if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
     L->stream = nullptr;
 }
@@ -1380,8 +1452,7 @@ atp_status atp_create(const atp_options *o, atp_ctx **out) {
     c->main.pool.user = d.alloc_user;
     c->main.pool.budget = d.mem_budget_bytes;
     c->main.pool.on_oom = [c]() { release_pool_caches(c); };
-    if (hipHostMalloc((void **)&c->main.h_hdr, sizeof(StepHeader), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
+    if (lane_mailbox(&c->main) != ATP_OK) {
         delete c;
         return ATP_ENOMEM;
     }
@@ -1414,7 +1485,7 @@ atp_status atp_destroy(atp_ctx *c) {
     lane_release_sides(&c->main);
     c->main.timer.flush();
     c->main.pool.destroy();
-    if (c->main.h_hdr) (void)hipHostFree(c->main.h_hdr);
+    lane_free_mailbox(&c->main);
     delete c;
     return ATP_OK;
 }

@@ -279,13 +279,20 @@ struct Lane {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     Pool pool;
-    StepHeader *h_hdr = nullptr;  // pinned
+    StepHeader *h_hdr = nullptr;  // pinned; device-writable (mailbox of posted values)
+    uint64_t *h_flag = nullptr;   // pinned: sequence number of the last post
+    int64_t *d_mailbox = nullptr; // device addresses of h_hdr and h_flag (nullptr: read by copies)
+    uint64_t *d_flag = nullptr;
+    uint64_t seq = 0;
     KernelTimer timer;
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork = nullptr, join[kSideStreams] = {};
 };
 // creates the lane's side streams and events on first use
 atp_status lane_sides(Lane *L);
+// pinned step header + post flag of a lane
+atp_status lane_mailbox(Lane *L);
+void lane_free_mailbox(Lane *L);
 void lane_release_sides(Lane *L);
 
 // Device-resident cached results and their bookkeeping (Sec. 3.3-3.4).

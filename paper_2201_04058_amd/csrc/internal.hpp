@@ -75,6 +75,12 @@ struct StepHeader {
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------------
+
+// Post n int64 values from device memory to mapped pinned host memory, then
+// set *flag = seq (system-scope release): the host polls the flag instead of
+// synchronising the stream.  One workgroup.
+void launch_post(const int64_t *src, int64_t n, int64_t *dst_host, uint64_t *flag_host, uint64_t seq,
+                 hipStream_t s);
 struct KernelTimer;  // host-side profiler hook (engine.cpp)
 
 void timer_begin(KernelTimer *t, const char *name, hipStream_t s);

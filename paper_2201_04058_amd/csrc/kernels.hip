@@ -2038,6 +2038,17 @@ int device_cus() {
         timer_end(t, stream);                                         \
     } while (0)
 
+__global__ void k_post(const int64_t *src, int64_t n, int64_t *dst, uint64_t *flag, uint64_t seq) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_post(const int64_t *src, int64_t n, int64_t *dst_host, uint64_t *flag_host, uint64_t seq,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, src, n, dst_host, flag_host, seq);
+}
+
 void launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s, KernelTimer *t) {
     if (n <= 0) return;
     ATP_LAUNCH("fill", 0, 0, s, k_fill_i64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
