@@ -131,6 +131,9 @@ struct PosMask {
     std::vector<int32_t> h_ids;
     std::vector<std::vector<int32_t>> staged;  // host sources of asynchronous copies
     std::vector<Buf> spent;                    // device id lists of the other id sets
+    const PosMask *alias = nullptr;            // the same constraints at an earlier position of the query
+    const uint32_t *bits_ptr() const { return alias ? alias->bits.as<uint32_t>() : bits.as<uint32_t>(); }
+    const int32_t *ids_ptr() const { return alias ? alias->ids.as<int32_t>() : ids.as<int32_t>(); }
 };
 
 struct StepStats {
@@ -820,7 +823,15 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     TRY(pops.alloc(&L->pool, 8 * n_types));
     std::vector<std::string> memo_key(n_types);
     bool readback = false;
+    std::vector<int> same(n_types, -1);  // an earlier position of the same type with the same constraints
+    for (int i = 0; i < n_types; ++i)
+        for (int j = 0; j < i && !mkeys[i].empty(); ++j)
+            if (types[j] == types[i] && mkeys[j] == mkeys[i]) {
+                same[i] = j;
+                break;
+            }
     for (int i = 0; i < n_types; ++i) {
+        if (same[i] >= 0) continue;  // shares that position's mask (below)
         TRY(build_mask(c, L, types[i], cons, n_cons, i, masks[i]));
         if (masks[i].pop < 0) continue;
         if (n_at[i] == 1 && ranges_at[i] == 0) {
@@ -853,6 +864,14 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
                 c->pop_memo[memo_key[i]] = h_pop[i];
             }
     }
+    for (int i = 0; i < n_types; ++i)
+        if (same[i] >= 0) {
+            const PosMask &m0 = masks[same[i]];
+            masks[i].alias = &m0;
+            masks[i].pop = m0.pop;
+            masks[i].n_ids = m0.n_ids;
+            masks[i].h_ids = m0.h_ids;
+        }
     auto sel_of = [&](int i) {
         const double n = (double)c->types[types[i]].count;
         return masks[i].pop >= 0 ? (n > 0 ? masks[i].pop / n : 0.0) : 1.0;
@@ -869,10 +888,10 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         L.cols = c->types[types[i + 1]].count;
         L.nnz = r.nnz;
         L.op = Operand{r.rp.as<int64_t>(), r.col.as<int32_t>(), nullptr,
-                       masks[i].pop >= 0 ? masks[i].bits.as<uint32_t>() : nullptr,
-                       masks[i + 1].pop >= 0 ? masks[i + 1].bits.as<uint32_t>() : nullptr, L.rows, L.cols, r.nnz};
+                       masks[i].pop >= 0 ? masks[i].bits_ptr() : nullptr,
+                       masks[i + 1].pop >= 0 ? masks[i + 1].bits_ptr() : nullptr, L.rows, L.cols, r.nnz};
         if (masks[i].n_ids >= 0) {
-            L.cand = masks[i].ids.as<int32_t>();
+            L.cand = masks[i].ids_ptr();
             L.n_cand = masks[i].n_ids;
         }
         ChainStats cs;

@@ -350,12 +350,13 @@ def test_memory_budget(atp, oracle_mod, tiny_cfg):
                                   {"ATP_SPLIT_OPS": "1024", "ATP_PART_TARGET": "64", "ATP_BUCKET_PCT": "100"},
                                   {"ATP_TILE_INDEX_CAP": "0"}, {"ATP_TILE_INDEX_CAP": "0", "ATP_PART_TARGET": "1"},
                                   {"ATP_BUCKET_PCT": "0", "ATP_BUCKET_CHUNK": "64"}, {"ATP_SERIAL_BINS": "1"},
-                                  {"ATP_BUCKET_PCT": "0", "ATP_CHUNK_HIST_CAP": "0"}])
+                                  {"ATP_BUCKET_PCT": "0", "ATP_CHUNK_HIST_CAP": "0"}, {"ATP_NO_MAILBOX": "1"}])
 def test_every_kernel_path_under_forced_tunings(atp, oracle_mod, tune, monkeypatch):
     """The binning thresholds only move rows between kernels (hash parts,
     dense tiles, split tiles, tile buckets) and segment bounds between the tile
-    index and searches, and the bins run on one stream or beside each other;
-    results must not change."""
+    index and searches, the bins run on one stream or beside each other, and
+    step totals come back through the mapped mailbox or by copies; results
+    must not change."""
     for k, v in tune.items():
         monkeypatch.setenv(k, v)
     for name, scale in [("scholarly", 0.02), ("news", 0.03)]:
