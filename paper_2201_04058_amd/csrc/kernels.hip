@@ -817,28 +817,56 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
 // ---------------------------------------------------------------------------
 // numeric: LDS hash, one workgroup per row
 
-// Block-wide bitonic sort of n (power of two) key/value pairs in LDS.
-__device__ void bitonic_sort_rt(int32_t *keys, unsigned long long *vals, int n) {
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
-                int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                int b = a + j;
-                bool up = (a & k) == 0;
-                int32_t ka = keys[a], kb = keys[b];
-                if ((ka > kb) == up) {
-                    keys[a] = kb;
-                    keys[b] = ka;
-                    unsigned long long va = vals[a];
-                    vals[a] = vals[b];
-                    vals[b] = va;
-                }
+// Sort keys/vals[0, n) ascending by key within a workgroup of NT threads
+// (keys unique; n <= S/2 and entries [n, S) free).  128-entry chunks are
+// bitonic-sorted by one wavefront each (no workgroup barriers); then runs
+// are merged pairwise, every entry placed at its index in its run plus the
+// number of entries of the other run that precede it (a binary search:
+// keys below it from a right run, keys up to it from a left run), moving
+// between the two halves of the arrays.  Returns the offset of the sorted
+// entries.
+template <int S, int NT>
+__device__ int merge_sort_block(int32_t *keys, unsigned long long *vals, int n) {
+    constexpr int C = 128;
+    constexpr int NWV = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int np = (n + C - 1) / C * C;  // whole chunks, padded with keys above every column
+    for (int t = n + threadIdx.x; t < np; t += NT) keys[t] = kEmptyKey;
+    __syncthreads();
+    for (int c = wave; c * C < np; c += NWV) bitonic_sort_wave_rt(keys + c * C, vals + c * C, C, lane);
+    __syncthreads();
+    int src = 0, dst = S / 2;
+    for (int L = C; L < np; L <<= 1) {
+        for (int t = threadIdx.x; t < np; t += NT) {
+            const int run = t / L;
+            const int base = (run & ~1) * L;  // start of the run pair
+            const bool left = (run & 1) == 0;
+            const int32_t k = keys[src + t];
+            const unsigned long long v = vals[src + t];
+            // the pair's other run [ob, oe) (empty for a left run without a partner)
+            const int ob = left ? base + L : base;
+            int oe = left ? base + 2 * L : base + L;
+            if (oe > np) oe = np;
+            int lo = ob, hi = oe > ob ? oe : ob;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int32_t km = keys[src + mid];
+                if (left ? (km < k) : (km <= k))
+                    lo = mid + 1;
+                else
+                    hi = mid;
             }
-            __syncthreads();
+            const int pos = base + (t - run * L) + (lo - ob);
+            keys[dst + pos] = k;
+            vals[dst + pos] = v;
         }
+        __syncthreads();
+        const int tmp = src;
+        src = dst;
+        dst = tmp;
     }
+    return src;
 }
-
 
 template <int S, int NT>
 __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t n, NumericArgs a) {
@@ -876,7 +904,7 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
             __syncthreads();
         }
         // compact the occupied slots to the front (each thread's slots pass
-        // through registers), then sort only the next power of two of them
+        // through registers), then sort them
         constexpr int PER = S / NT;
         int32_t kk[PER];
         unsigned long long vv[PER];
@@ -902,16 +930,13 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
             }
         }
         const int total = (int)tot64;
-        int p2 = 1;
-        while (p2 < total) p2 <<= 1;
-        for (int t = total + threadIdx.x; t < p2; t += NT) keys[t] = kEmptyKey;
         __syncthreads();
-        bitonic_sort_rt(keys, vals, p2);
+        const int so = merge_sort_block<S, NT>(keys, vals, total);
         const int64_t off = a.slot_off[c];
         bool sat = false;
         for (int t = threadIdx.x; t < total; t += NT) {
-            a.slot_col[off + t] = keys[t];
-            unsigned long long v = vals[t];
+            a.slot_col[off + t] = keys[so + t];
+            unsigned long long v = vals[so + t];
             a.slot_val[off + t] = v;
             sat |= (v & kSat) != 0;
         }
