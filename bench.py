@@ -32,7 +32,9 @@ def log(msg: str) -> None:
 
 # Source regions a kernel's counters depend on: the shared device helpers at
 # the top of kernels.hip, the kernel's own section, and internal.hpp.
-KERNEL_SECTIONS = {"dense": ("// numeric: dense LDS tiles over column ranges", "// numeric: tile buckets")}
+# sections of kernels.hip a kernel's code lives in (beside the shared helpers at the top)
+KERNEL_SECTIONS = {"dense": [("// Visit the flattened products", "// numeric: LDS hash, one wavefront per row"),
+                             ("// numeric: dense LDS tiles over column ranges", "// numeric: tile buckets")]}
 
 
 def kernel_source_digest(kernel: str = "dense") -> str:
@@ -41,9 +43,9 @@ def kernel_source_digest(kernel: str = "dense") -> str:
         text = fh.read()
     h = hashlib.sha256()
     if kernel in KERNEL_SECTIONS:
-        a, b = KERNEL_SECTIONS[kernel]
         h.update(text[:text.index("// fills, scans")].encode())
-        h.update(text[text.index(a):text.index(b)].encode())
+        for a, b in KERNEL_SECTIONS[kernel]:
+            h.update(text[text.index(a):text.index(b)].encode())
     else:
         h.update(text.encode())
     with open(os.path.join(csrc, "internal.hpp")) as fh:
