@@ -359,33 +359,34 @@ __global__ void k_popcount(const uint32_t *bits, int64_t words, int64_t *out) {
 // symbolic pass
 
 // Sum of |Y row k| over the X entries k at positions p0, p0 + stride, ...
-// below e that pass X's column mask; four entries' loads are in flight
+// below e that pass X's column mask; UN entries' loads are in flight
 // together (column ids, then mask words, then row-pointer pairs).
+template <int UN = 4>
 __device__ __forceinline__ int64_t sum_right_rows(const Operand &X, const Operand &Y, int64_t p0, int64_t e,
                                                   int stride) {
     int64_t s = 0;
-    for (int64_t p = p0; p < e; p += 4 * (int64_t)stride) {
-        int32_t k[4];
-        bool ok[4];
+    for (int64_t p = p0; p < e; p += UN * (int64_t)stride) {
+        int32_t k[UN];
+        bool ok[UN];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < UN; ++u) {
             const int64_t q = p + (int64_t)u * stride;
             ok[u] = q < e;
             k[u] = ok[u] ? X.col[q] : 0;
         }
         if (X.cmask) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < UN; ++u)
                 if (ok[u]) ok[u] = bit_test(X.cmask, k[u]);
         }
-        int64_t lo[4], hi[4];
+        int64_t lo[UN], hi[UN];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < UN; ++u) {
             lo[u] = ok[u] ? Y.rp[k[u]] : 0;
             hi[u] = ok[u] ? Y.rp[k[u] + 1] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s += hi[u] - lo[u];
+        for (int u = 0; u < UN; ++u) s += hi[u] - lo[u];
     }
     return s;
 }
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(256) void k_symbolic(SymbolicArgs a) {
             if (e - b > kLongRow) {
                 deferred = (e - b + kSymChunk - 1) / kSymChunk;
             } else {
-                nop = sum_right_rows(a.X, a.Y, b + li, e, kSymLanes);
+                nop = sum_right_rows<4>(a.X, a.Y, b + li, e, kSymLanes);
             }
         }
     }
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(256) void k_symbolic_long(SymbolicArgs a, const int
         const int64_t q = id - long_off[c];
         const int64_t b = a.X.rp[i] + q * kSymChunk;
         const int64_t e = (b + kSymChunk < a.X.rp[i + 1]) ? b + kSymChunk : a.X.rp[i + 1];
-        const int64_t s = sum_right_rows(a.X, a.Y, b + threadIdx.x, e, blockDim.x);
+        const int64_t s = sum_right_rows<8>(a.X, a.Y, b + threadIdx.x, e, blockDim.x);
         int64_t tot;
         block_inclusive_scan(s, sw, &tot);
         if (threadIdx.x == 0 && tot) {
@@ -1677,12 +1678,18 @@ __global__ __launch_bounds__(256) void k_bucket_scan(BucketArgs b, Tuning tune) 
         if (threadIdx.x == 0) off[b.ntiles] = carry;
         __syncthreads();
         if (b.chunk_hist) {
+            const int64_t q0 = b.chunk_base[p], q1 = b.chunk_base[p + 1];
             for (int64_t t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
                 int64_t run = off[t];
-                for (int64_t q = b.chunk_base[p]; q < b.chunk_base[p + 1]; ++q) {
-                    const int64_t v = b.chunk_hist[q * b.ntiles + t];
-                    b.chunk_hist[q * b.ntiles + t] = run;
-                    run += v;
+                for (int64_t q = q0; q < q1; q += 8) {  // eight chunks' counts loaded together
+                    int64_t v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = q + u < q1 ? b.chunk_hist[(q + u) * b.ntiles + t] : 0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        if (q + u < q1) b.chunk_hist[(q + u) * b.ntiles + t] = run;
+                        run += v[u];
+                    }
                 }
             }
         }
