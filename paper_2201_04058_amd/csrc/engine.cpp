@@ -179,9 +179,11 @@ atp_status count_bytes(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, const in
 // need_active: Z will be the left operand of a later product.
 // defer: Z is an intermediate (not the result, no cache): its sizes are not
 // read back (no host synchronisation after the numeric phase); its true
-// nonzero count is added to *nnz_acc on the device.
+// nonzero count is added to *nnz_acc on the device.  defer_below > 0: defer
+// too when the symbolic bound on Z's nonzeros is below it (a caller that
+// compares Z's size with that limit gets the same answer from the bound).
 atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols_eff, bool need_active, Mat &Z,
-                  StepStats &st, bool &saturated, bool defer, int64_t *nnz_acc) {
+                  StepStats &st, bool &saturated, bool defer, int64_t *nnz_acc, int64_t defer_below = 0) {
     Pool *pool = &L->pool;
     hipStream_t s = L->stream;
     KernelTimer *t = c->kt(L);
@@ -432,6 +434,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     Buf tmp2;
     TRY(tmp2.alloc(pool, 8 * (size_t)scan_multi_tmp_elems(jobs2, n_jobs2)));
     launch_scan_multi(jobs2, n_jobs2, tmp2.as<int64_t>(), s, t);
+    if (defer_below > 0 && h1.slots_total < defer_below && nnz_acc) defer = true;
     if (defer) {
         // capacities from the symbolic bounds; the counts stay on the device
         Z.nnz = h1.slots_total;
@@ -1166,7 +1169,12 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
             HIPTRY(hipEventRecord(rec.e0, s));
         }
         const bool defer = may_defer && v != forced_root && !feeds_restriction[v];
-        TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat, defer, nnz_acc.as<int64_t>()));
+        // a left operand whose size decides its parent's restriction (size below half the rows
+        // of the parent's right operand) can keep its size on the device when its bound decides
+        const int64_t defer_below = may_defer && v != forced_root && feeds_restriction[v]
+                                        ? c->types[types[r1 + 1]].count / 2
+                                        : 0;
+        TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat, defer, nnz_acc.as<int64_t>(), defer_below));
         if (c->cost_sink) {
             HIPTRY(hipEventRecord(rec.e1, s));
             rec.n_op = (double)st.n_op - rec.n_op;
