@@ -1592,6 +1592,8 @@ __device__ __forceinline__ int64_t bucket_part_tiles(int64_t nop, int64_t ntiles
     return m;
 }
 
+constexpr int kBucketUnroll = 2;  // products per lane per step of the bucket passes' walk
+
 // Products of X entries [e0, e1) of one row in batches of kBucketThreads
 // entries, walked flattened: f(column, value) for each.
 template <typename F>
@@ -1601,7 +1603,8 @@ __device__ __forceinline__ void walk_entry_range(const NumericArgs &a, int64_t e
         const int64_t nb = (e1 - eb < kBucketThreads) ? e1 - eb : kBucketThreads;
         const int64_t tot = row_segments<kBucketThreads>(a.X, a.Y, eb, nb, seg_s, seg_o, sw);
         if (tot < kWalkMax) {
-            walk_products_any<kBucketThreads>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr, f);
+            walk_products_any<kBucketThreads, kBucketUnroll>(a.Y, seg_o, seg_s, (int32_t)tot,
+                                                              a.X.val ? a.X.val + eb : nullptr, f);
         } else {
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
             for (int64_t e = eb + wave; e < eb + nb; e += kBucketThreads / 64) {
