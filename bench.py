@@ -275,6 +275,7 @@ def _serve(atp, ctx, arrivals, qs, lanes, max_batch, admit_bytes, cap_s):
             "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "mean_ms": round(float(np.mean(lat)), 3),
             "errors": sum(1 for d in done.values() if d[0] != 0),
             "error_status": sorted({int(d[0]) for d in done.values() if d[0] != 0}),
+            "error_queries": [qs[z].name for z in sorted(done) if done[z][0] != 0][:8],
             "mean_batch": round(float(np.mean([d[3] for d in done.values()])), 3)}, done
 
 

@@ -928,7 +928,9 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     auto sub_types = [&](int a, int b) { return std::vector<int32_t>(types + a, types + b + 2); };
     auto sub_rels = [&](int a, int b) { return std::vector<int32_t>(rel.begin() + a, rel.begin() + b + 1); };
     auto sub_pos = [&](int a, int b) { return std::vector<std::string>(pkeys.begin() + a, pkeys.begin() + b + 2); };
+    uint64_t cache_budget = 0;
     if (caching) {
+        cache_budget = cs.budget;
         pkeys = position_keys(n_types, cons, n_cons);
         for (int w = 0; w < weight; ++w) cs.tree->insert(std::vector<int32_t>(types, types + n_types));
         cs.stats.queries += weight;
@@ -960,11 +962,9 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     cache_lock.unlock();
 
     std::string plan_str;
-    if (plan) {
-        plan_str = plan;
-        for (const PlanTree &nd : forced)
-            if (nd.block_lo >= 0 && (!caching || cached_item[nd.block_lo][nd.block_hi] < 0)) return ATP_EINVAL;
-    } else {
+    std::vector<std::vector<double>> span_nnz;  // planner estimate of every sub-chain (none for a given plan)
+    // Eq. 1 over the leaves, with cached sub-chains at no cost when with_cache
+    auto choose_plan = [&](bool with_cache) -> atp_status {
         std::vector<JunctionSketch> js;
         std::vector<double> jsel, csel;
         std::vector<ColumnHist> ch;
@@ -978,16 +978,25 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
             auto it = c->col_hists.find(rel[k]);
             if (it == c->col_hists.end()) {
                 const Rel &r = *c->rels[rel[k]];
-                it = c->col_hists.emplace(rel[k], make_column_hist(r.h_indeg.data(), (int64_t)r.h_indeg.size())).first;
+                it = c->col_hists.emplace(rel[k], make_column_hist(r.h_indeg.data(), (int64_t)r.h_indeg.size()))
+                         .first;
             }
             ch.push_back(it->second);
             csel.push_back(sel_of(k + 1));
         }
         const CostCoeffs cc = c->cost;
         PlanResult pr = plan_chain(lst, js, jsel, ch, csel, uniform ? Estimator::Uniform : Estimator::Sketch, cc,
-                                   caching ? &cached_stats : nullptr);
+                                   with_cache ? &cached_stats : nullptr);
         plan_str = pr.plan;
-        if (!parse_plan(plan_str.c_str(), p, forced, forced_root)) return ATP_ESTATE;
+        span_nnz = std::move(pr.span_nnz);
+        return parse_plan(plan_str.c_str(), p, forced, forced_root) ? ATP_OK : ATP_ESTATE;
+    };
+    if (plan) {
+        plan_str = plan;
+        for (const PlanTree &nd : forced)
+            if (nd.block_lo >= 0 && (!caching || cached_item[nd.block_lo][nd.block_hi] < 0)) return ATP_EINVAL;
+    } else {
+        TRY(choose_plan(caching));
     }
 
     // a single relation: multiply by the identity so the masked relation is
@@ -1028,9 +1037,13 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     // restricted to the left operand's columns (a base relation's rows are
     // only read where the left operand points, so it gains nothing)
     auto internal = [&](int v) { return tree[v].leaf < 0 && tree[v].block_lo < 0; };
-    std::vector<char> feeds_restriction(tree.size(), 0);
-    for (size_t v = 0; v < tree.size(); ++v)
-        if (restrict_rows && internal((int)v) && internal(tree[v].right)) feeds_restriction[tree[v].left] = 1;
+    std::vector<char> feeds_restriction;
+    auto mark_restrictions = [&]() {
+        feeds_restriction.assign(tree.size(), 0);
+        for (size_t v = 0; v < tree.size(); ++v)
+            if (restrict_rows && internal((int)v) && internal(tree[v].right)) feeds_restriction[tree[v].left] = 1;
+    };
+    mark_restrictions();
     // intermediates whose sizes stay on the device (no read-back per product):
     // not the result, not kept by the cache, not timed or byte-counted, and not
     // a left operand whose size decides a restriction
@@ -1090,13 +1103,14 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         }
     } cost_recs;
     std::vector<int64_t> used_items;
+    bool whole_allowed = true;
     // post-order evaluation of node v into outm; rs restricts v's rows; cost =
     // seconds to compute it from the base relations in this query
     std::function<atp_status(int, bool, const Restriction *, Mat &, int &, int &, double &)> run =
         [&](int v, bool as_left, const Restriction *rs, Mat &outm, int &lo, int &hi, double &cost) -> atp_status {
         const PlanTree &nd = tree[v];
         cost = 0;
-        if (nd.block_lo >= 0) {  // a cached result (caching implies no row restriction)
+        if (nd.block_lo >= 0) {  // a cached result, computed on all its rows
             lo = nd.block_lo;
             hi = nd.block_hi;
             const int64_t id = cached_item[lo][hi];
@@ -1109,6 +1123,12 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
             outm.nnz = P.nnz;
             outm.n_active = P.n_active;
             outm.active_ptr = P.n_active >= 0 ? P.active.as<int32_t>() : nullptr;
+            if (rs && (P.n_active < 0 || rs->n < P.n_active)) {
+                // as a left operand under a restriction only the listed rows are multiplied
+                // (a listed row that is empty in the result adds nothing)
+                outm.n_active = rs->n;
+                outm.active_ptr = rs->list;
+            }
             outm.op = Operand{P.rp.as<int64_t>(), P.col.as<int32_t>(), P.val.as<uint64_t>(), nullptr, nullptr,
                               P.rows, P.cols, P.nnz};
             used_items.push_back(id);
@@ -1146,8 +1166,13 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         const bool x_small = X.leaf ? (X.cand != nullptr && X.n_cand < y_rows) : (X.nnz < y_rows / 2);
         // with a cache, a right sub-chain that is an overlap (seen in an earlier
         // query) is computed on all its rows so that its result can be kept
+        // (only when its estimated columns and values fit an item the cache admits, at most
+        // 80% of its budget, and not on the retry of a query that ran out of memory with it)
         const std::pair<int, int> ysp = span(nd.right);
-        const bool keep_whole = caching && ysp.second > ysp.first && freq[ysp.first][ysp.second] >= 2;
+        const bool fits =
+            span_nnz.empty() || 12.0 * span_nnz[ysp.first][ysp.second] <= 0.8 * (double)cache_budget;
+        const bool keep_whole =
+            caching && whole_allowed && fits && ysp.second > ysp.first && freq[ysp.first][ysp.second] >= 2;
         if (restrict_rows && x_small && !keep_whole && internal(nd.right)) {
             TRY(make_restriction(X, y_rows, r2));
             rp = &r2;
@@ -1236,6 +1261,27 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     } else {
         double root_cost = 0;
         stt = run(forced_root, false, nullptr, R, lo, hi, root_cost);
+        if ((stt == ATP_ENOMEM || stt == ATP_EBUDGET) && caching) {
+            // out of memory with the cache's choices (cached blocks in the plan, a sub-chain
+            // computed on all its rows to be kept): once more as without the cache
+            (void)hipStreamSynchronize(s);
+            for (auto &r : cost_recs) {
+                if (r.e0) (void)hipEventDestroy(r.e0);
+                if (r.e1) (void)hipEventDestroy(r.e1);
+            }
+            cost_recs.clear();
+            kept.clear();
+            keep.clear();
+            used_items.clear();
+            R = Mat();
+            st = StepStats();
+            n_products = 0;
+            overflow = false;
+            whole_allowed = false;
+            stt = plan ? ATP_OK : choose_plan(false);
+            mark_restrictions();
+            if (stt == ATP_OK) stt = run(forced_root, false, nullptr, R, lo, hi, root_cost);
+        }
         if (stt == ATP_OK && caching && !overflow) {
             std::lock_guard<std::mutex> g(cs.mu);
             if (cs.pol)  // the cache may have been switched off meanwhile

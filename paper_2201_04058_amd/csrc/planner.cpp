@@ -164,6 +164,9 @@ PlanResult plan_chain(const std::vector<ChainStats> &leaves, const std::vector<J
     };
     out.plan = str(0, p - 1);
     out.cost = C[0][p - 1];
+    out.span_nnz.assign(p, std::vector<double>(p, 0.0));
+    for (int i = 0; i < p; ++i)
+        for (int j = i; j < p; ++j) out.span_nnz[i][j] = D[i][j].nnz;
     return out;
 }
 

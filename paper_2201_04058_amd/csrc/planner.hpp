@@ -49,6 +49,7 @@ struct PlanResult {
     std::string plan;
     double cost = 0;
     std::vector<ChainStats> node_stats;  // estimate of the root and every product, post-order
+    std::vector<std::vector<double>> span_nnz;  // [i][j]: estimated nnz of the product of leaves i..j
 };
 
 // Dynamic program of Eq. 1 over p = leaves.size() matrices.  junctions[k]

@@ -91,6 +91,33 @@ def test_repeated_query_is_a_whole_hit_and_sub_results_are_reused(atp, oracle_mo
     ctx.close()
 
 
+def test_cached_block_as_restricted_left_operand(atp, oracle_mod, scholarly_small):
+    """A cached sub-chain that is the left operand of a product whose rows are
+    restricted (its left neighbour picks few columns) multiplies only the
+    listed rows: same result, fewer products than over all its rows."""
+    hin, _ = scholarly_small
+    ctx = atp.Context(device=0)
+    ctx.load_hin(hin)
+    ctx.cache_configure(atp.ATP_CACHE_OTREE, 1 << 30)
+    # one publication year keeps the co-authorship block small (about 0.6M entries)
+    yr = lambda pos: Constraint(pos, "range", prop="year", lo=2015, hi=2015)
+    sub = Query("P-A-P", ["P", "A", "P"], [yr(0), yr(2)])
+    for _ in range(2):
+        ctx.eval_query(sub).free()
+    assert ctx.cache_stats()["whole_hits"] == 1
+    q = Query("A-P-A-P-V", ["A", "P", "A", "P", "V"],
+              [Constraint(0, "idset", ids=np.array([20], np.int32)), yr(1), yr(3)])
+    ref = oracle_mod.eval_full(hin, q)
+    r = ctx.eval_query(q, plan="(0,([1-2],3))")
+    assert same(r, ref)
+    n_op_restricted = r.stats()["n_op"]
+    ctx.set_flags(no_restrict=True)
+    r2 = ctx.eval_query(q, plan="(0,([1-2],3))")
+    assert same(r2, ref)
+    assert n_op_restricted < r2.stats()["n_op"]
+    ctx.close()
+
+
 def test_cache_off_again_matches(atp, oracle_mod, scholarly_small):
     hin, qs = scholarly_small
     ctx = atp.Context(device=0)
