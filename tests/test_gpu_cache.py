@@ -118,6 +118,27 @@ def test_cached_block_as_restricted_left_operand(atp, oracle_mod, scholarly_smal
     ctx.close()
 
 
+def test_out_of_memory_with_the_cache_retries_restricted(atp, oracle_mod, scholarly_small):
+    """P-T-P-A seen before makes the cache compute that right sub-chain on all
+    its rows (about 8e7 entries) so it can be kept; under a 256 MiB budget that
+    fails, and the query is evaluated again restricted to one author's papers."""
+    hin, _ = scholarly_small
+    ctx = atp.Context(device=0, budget_bytes=256 << 20)
+    ctx.load_hin(hin)
+    ctx.cache_configure(atp.ATP_CACHE_OTREE, 1 << 30)
+    yr = lambda pos: Constraint(pos, "range", prop="year", lo=2012, hi=32767)
+    seen = Query("P-T-P-A", ["P", "T", "P", "A"],
+                 [Constraint(0, "idset", ids=np.array([24806], np.int32)), yr(0), yr(2)])
+    ctx.eval_query(seen).free()
+    q = Query("A-P-T-P-A", ["A", "P", "T", "P", "A"],
+              [Constraint(0, "idset", ids=np.array([1], np.int32)), yr(1), yr(3)])
+    r = ctx.eval_query(q, plan="(0,((1,2),3))")
+    assert same(r, oracle_mod.eval_full(hin, q))
+    r.free()
+    assert ctx.cache_stats()["queries"] == 2
+    ctx.close()
+
+
 def test_cache_off_again_matches(atp, oracle_mod, scholarly_small):
     hin, qs = scholarly_small
     ctx = atp.Context(device=0)
