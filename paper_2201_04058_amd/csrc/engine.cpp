@@ -116,7 +116,8 @@ struct Mat {
     bool view = false;                    // a cached result, not owned
     const int32_t *cand = nullptr;  // leaf: candidate rows from an id-set constraint
     int64_t n_cand = 0;
-    // a product whose size was not read back: nnz is an upper bound (the
+    // the product's step header (kept for the value bound at hdr->vmax).  A
+    // product whose size was not read back: nnz is an upper bound (the
     // arrays' capacity), the true count is at nnz_dev in the kept header, and
     // the active list holds every candidate row, non-empty ones first
     Buf hdr;
@@ -442,7 +443,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
         launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
                              slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
-                             Z.val.as<uint64_t>(), s, t);
+                             Z.val.as<uint64_t>(), &d_hdr->vmax, s, t);
         if (need_active) {
             Z.n_active = n_cand;
             TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(n_cand, 1)));
@@ -462,16 +463,18 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
         launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
                              slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
-                             Z.val.as<uint64_t>(), s, t);
+                             Z.val.as<uint64_t>(), &d_hdr->vmax, s, t);
         if (need_active) {
             Z.n_active = h2.n_active;
             TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.n_active, 1)));
             Z.active_ptr = Z.active.as<int32_t>();
             launch_active_scatter(cand, n_cand, flags_scan.as<int64_t>(), Z.active.as<int32_t>(), false, s, t);
         }
+        Z.hdr = std::move(hdr);  // holds the value bound
     }
     Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
                    Z.rows, Z.cols, Z.nnz};
+    Z.op.vmax = &d_hdr->vmax;
     if (c->flags & ATP_OPT_COUNT_BYTES) L->timer.bytes["copy"] += 24.0 * (double)Z.nnz + 24.0 * (double)h1.segs_total;
     // temporaries go back to the pool here; later work on the stream is ordered after this step
     return ATP_OK;

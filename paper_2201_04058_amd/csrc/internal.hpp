@@ -45,6 +45,7 @@ struct Operand {
     const uint32_t *rmask = nullptr; // row mask bits (leaf X only)
     const uint32_t *cmask = nullptr; // column mask bits (leaf only)
     int64_t rows = 0, cols = 0, nnz = 0;
+    const uint64_t *vmax = nullptr;  // device: no stored value exceeds *vmax (nullptr: no bound known)
 };
 
 // Runtime tunables of the binning and numeric kernels (defaults above).
@@ -70,6 +71,7 @@ struct StepHeader {
     int64_t bucket_products;  // products buffered by the bucket bin
     int64_t nnz_total;        // result nonzeros (after numeric)
     int64_t n_active;         // non-empty result rows
+    uint64_t vmax;            // largest result value (the compaction copy's maximum)
     int32_t saturated;        // some emitted value is saturated
     int32_t pad;
 };
@@ -190,7 +192,7 @@ constexpr int64_t kChunkHistCap = (int64_t)64 << 20;  // per-chunk tile counts k
 // compaction
 void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
                           const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val,
-                          hipStream_t s, KernelTimer *t);
+                          uint64_t *vmax, hipStream_t s, KernelTimer *t);
 void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row_nnz, int64_t *flags,
                          hipStream_t s, KernelTimer *t);
 // the non-empty candidate rows in order; with partition the empty ones

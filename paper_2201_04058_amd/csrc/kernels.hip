@@ -1256,6 +1256,13 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
     __syncthreads();
     const int64_t ycols = a.ycols;
     const int64_t ntiles = (ycols + W - 1) / W;
+    // bound of every product value (an operand without values holds ones; one
+    // without a known bound gives 2^63).  A row of nop products, each at most
+    // vm, cannot bring any column to 2^63 when nop * vm < 2^63: its tiles add
+    // without the returning atomic of the saturation check.
+    const uint64_t xm = a.X.val ? (a.X.vmax ? *a.X.vmax : kSat) : 1;
+    const uint64_t ym = a.Y.val ? (a.Y.vmax ? *a.Y.vmax : kSat) : 1;
+    const uint64_t vm = sat_mul(xm, ym);
 
     // segments of the batch starting at eb over columns [c0, c1); start from
     // cur[] when from_cursor.  The bound searches are shared out to groups of
@@ -1415,6 +1422,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
 
         // dense part: tile by tile (cursors only without the tile index)
         const bool cursors = single && !a.ytile;
+        const bool no_sat = sat_mul(vm, (uint64_t)a.nop[c]) < kSat;
         if (cursors) {  // cursors at the part start
             for (int64_t e = tid; e < xlen; e += NT) {
                 int32_t k = a.X.col[xb + e];
@@ -1442,7 +1450,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
                 const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
                 products(tot, xval, [&](int32_t j, uint64_t v) {
                     const uint32_t slot = (uint32_t)(j - c0);
-                    acc_add(&acc[slot], satw, slot, v);
+                    if (no_sat)
+                        (void)__hip_atomic_fetch_add(&acc[slot], (unsigned long long)v, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+                    else
+                        acc_add(&acc[slot], satw, slot, v);
                 });
                 __syncthreads();
             }
@@ -1852,10 +1864,17 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
 // ---------------------------------------------------------------------------
 // compaction
 
-__global__ void k_copy_segments(const int64_t *__restrict__ seg_cnt, const int64_t *__restrict__ seg_src,
-                                const int64_t *__restrict__ seg_dst, int64_t n_segs,
-                                const int32_t *__restrict__ slot_col, const uint64_t *__restrict__ slot_val,
-                                int32_t *__restrict__ col, uint64_t *__restrict__ val) {
+// Segments of slots -> exact-size arrays; also raises *vmax to the largest
+// value copied (one atomic per workgroup at most).  256 threads.
+__global__ __launch_bounds__(256) void k_copy_segments(const int64_t *__restrict__ seg_cnt,
+                                                       const int64_t *__restrict__ seg_src,
+                                                       const int64_t *__restrict__ seg_dst, int64_t n_segs,
+                                                       const int32_t *__restrict__ slot_col,
+                                                       const uint64_t *__restrict__ slot_val,
+                                                       int32_t *__restrict__ col, uint64_t *__restrict__ val,
+                                                       unsigned long long *vmax) {
+    __shared__ unsigned long long s_max[4];
+    unsigned long long m = 0;
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1876,12 +1895,25 @@ __global__ void k_copy_segments(const int64_t *__restrict__ seg_cnt, const int64
             for (int u = 0; u < 4; ++u) {
                 col[dst + t + 64 * u] = c[u];
                 val[dst + t + 64 * u] = v[u];
+                m = v[u] > m ? v[u] : m;
             }
         }
         for (; t < n; t += 64) {
             col[dst + t] = slot_col[src + t];
-            val[dst + t] = slot_val[src + t];
+            const uint64_t v = slot_val[src + t];
+            val[dst + t] = v;
+            m = v > m ? v : m;
         }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(m, o, 64);
+        m = y > m ? y : m;
+    }
+    if (lane == 0) s_max[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) m = s_max[w] > m ? s_max[w] : m;
+        if (m > __hip_atomic_load(vmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(vmax, m);
     }
 }
 
@@ -2264,11 +2296,11 @@ void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *c
 
 void launch_copy_segments(const int64_t *seg_cnt, const int64_t *seg_src, const int64_t *seg_dst, int64_t n_segs,
                           const int32_t *slot_col, const uint64_t *slot_val, int32_t *col, uint64_t *val,
-                          hipStream_t s, KernelTimer *t) {
+                          uint64_t *vmax, hipStream_t s, KernelTimer *t) {
     if (n_segs <= 0) return;
     const int cus = device_cus();
     ATP_LAUNCH("copy", 0, 0, s, k_copy_segments, dim3(grid_for(n_segs * 64, 256, (int64_t)cus * 8)), dim3(256), 0, s,
-               seg_cnt, seg_src, seg_dst, n_segs, slot_col, slot_val, col, val);
+               seg_cnt, seg_src, seg_dst, n_segs, slot_col, slot_val, col, val, (unsigned long long *)vmax);
 }
 
 void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row_nnz, int64_t *flags,
