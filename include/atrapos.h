@@ -190,8 +190,13 @@ atp_status atp_result_free(atp_result *res);
  * full sub-metapath results are kept: a right sub-chain is restricted to the
  * rows its left neighbour reaches (and then not cached) unless its type string
  * already occurred in an earlier query (Overlap-Tree frequency >= 2), in which
- * case it is computed on all rows and becomes a cache candidate.  Results are
- * identical with and without a cache. */
+ * case it is computed on all rows and becomes a cache candidate, provided the
+ * planner's size estimate of it fits an item the cache admits.  A cached
+ * sub-metapath that is the left operand of a restricted product multiplies
+ * only the restricted rows.  A query that runs out of device memory (or over
+ * the context's budget) with the cache's choices is evaluated once more with
+ * a plan chosen without cached results and every right sub-chain restricted.
+ * Results are identical with and without a cache. */
 enum { ATP_CACHE_OFF = 0, ATP_CACHE_OTREE = 1, ATP_CACHE_PGDS = 2, ATP_CACHE_LRU = 3, ATP_CACHE_CBS1 = 4,
        ATP_CACHE_CBS2 = 5 };
 
