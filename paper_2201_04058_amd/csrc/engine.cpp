@@ -184,7 +184,8 @@ atp_status count_bytes(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, const in
 // too when the symbolic bound on Z's nonzeros is below it (a caller that
 // compares Z's size with that limit gets the same answer from the bound).
 atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols_eff, bool need_active, Mat &Z,
-                  StepStats &st, bool &saturated, bool defer, int64_t *nnz_acc, int64_t defer_below = 0) {
+                  StepStats &st, bool &saturated, bool defer, int64_t *nnz_acc, int64_t defer_below = 0,
+                  bool operand = true) {
     Pool *pool = &L->pool;
     hipStream_t s = L->stream;
     KernelTimer *t = c->kt(L);
@@ -243,6 +244,8 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
 
     StepHeader *d_hdr = hdr.as<StepHeader>();
     launch_fill_i64((int64_t *)d_hdr, sizeof(StepHeader) / 8, 0, s, t);
+    // a product that feeds another one records its largest value (the dense tiles' bound)
+    uint64_t *vmax = operand ? &d_hdr->vmax : nullptr;
 
     SymbolicArgs sa;
     sa.X = X.op;
@@ -443,7 +446,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
         launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
                              slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
-                             Z.val.as<uint64_t>(), &d_hdr->vmax, s, t);
+                             Z.val.as<uint64_t>(), vmax, s, t);
         if (need_active) {
             Z.n_active = n_cand;
             TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(n_cand, 1)));
@@ -463,7 +466,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
         TRY(Z.val.alloc(pool, 8 * (size_t)std::max<int64_t>(Z.nnz, 1)));
         launch_copy_segments(seg_cnt.as<int64_t>(), seg_src.as<int64_t>(), seg_dst.as<int64_t>(), h1.segs_total,
                              slot_col.as<int32_t>(), slot_val.as<uint64_t>(), Z.col.as<int32_t>(),
-                             Z.val.as<uint64_t>(), &d_hdr->vmax, s, t);
+                             Z.val.as<uint64_t>(), vmax, s, t);
         if (need_active) {
             Z.n_active = h2.n_active;
             TRY(Z.active.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.n_active, 1)));
@@ -474,7 +477,7 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
     }
     Z.op = Operand{Z.rp.as<int64_t>(), Z.col.as<int32_t>(), Z.val.as<uint64_t>(), nullptr, nullptr,
                    Z.rows, Z.cols, Z.nnz};
-    Z.op.vmax = &d_hdr->vmax;
+    Z.op.vmax = vmax;
     if (c->flags & ATP_OPT_COUNT_BYTES) L->timer.bytes["copy"] += 24.0 * (double)Z.nnz + 24.0 * (double)h1.segs_total;
     // temporaries go back to the pool here; later work on the stream is ordered after this step
     return ATP_OK;
@@ -1202,7 +1205,8 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         const int64_t defer_below = may_defer && v != forced_root && feeds_restriction[v]
                                         ? c->types[types[r1 + 1]].count / 2
                                         : 0;
-        TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat, defer, nnz_acc.as<int64_t>(), defer_below));
+        TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat, defer, nnz_acc.as<int64_t>(), defer_below,
+                   v != forced_root));
         if (c->cost_sink) {
             HIPTRY(hipEventRecord(rec.e1, s));
             rec.n_op = (double)st.n_op - rec.n_op;
@@ -1236,7 +1240,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         X.n_cand = leaves[0].n_cand;
         ident.op.cmask = leaves[0].op.cmask;
         bool sat = false;
-        stt = spgemm(c, L, X, ident, ycols_eff, false, R, st, sat, false, nullptr);
+        stt = spgemm(c, L, X, ident, ycols_eff, false, R, st, sat, false, nullptr, 0, false);
         n_products = 1;
         overflow = sat;
     } else if (caching && tree[forced_root].block_lo == 0 && tree[forced_root].block_hi == p - 1) {

@@ -1864,8 +1864,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
 // ---------------------------------------------------------------------------
 // compaction
 
-// Segments of slots -> exact-size arrays; also raises *vmax to the largest
-// value copied (one atomic per workgroup at most).  256 threads.
+// Segments of slots -> exact-size arrays; with vmax, also raises *vmax to the
+// largest value copied (one atomic per workgroup at most).  256 threads.
 __global__ __launch_bounds__(256) void k_copy_segments(const int64_t *__restrict__ seg_cnt,
                                                        const int64_t *__restrict__ seg_src,
                                                        const int64_t *__restrict__ seg_dst, int64_t n_segs,
@@ -1905,6 +1905,7 @@ __global__ __launch_bounds__(256) void k_copy_segments(const int64_t *__restrict
             m = v > m ? v : m;
         }
     }
+    if (!vmax) return;  // kernel-uniform
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long y = __shfl_xor(m, o, 64);
         m = y > m ? y : m;
