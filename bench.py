@@ -407,6 +407,8 @@ def main() -> int:
     ap.add_argument("--workload", default="scholarly", choices=["scholarly", "news", "tiny"])
     ap.add_argument("--cpu-rows", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side-by-side", action="store_true",
+                    help="skip the second timed region (the step's queries side by side on four lanes)")
     ap.add_argument("--plan-eac", action="store_true", help="paper's uniform E_ac planner")
     ap.add_argument("--mode", default="plain", choices=["plain", "workload", "batch", "serve", "costfit"],
                     help="plain: the workload's queries, one at a time; workload: a session query stream "
@@ -543,16 +545,18 @@ def main() -> int:
             if r.shape()[2] != plans[q.name]["nnz"]:
                 raise RuntimeError(f"{q.name}: {r.shape()[2]} nonzeros side by side, {plans[q.name]['nnz']} alone")
             r.free()
-    for _ in range(max(1, args.warmup)):
-        conc_step()
-    if stream is not None:
-        torch.cuda.synchronize()
-    t_c = time.perf_counter()
-    for _ in range(args.steps):
-        conc_step()
-    if stream is not None:
-        torch.cuda.synchronize()
-    conc_elapsed = time.perf_counter() - t_c
+    conc_elapsed = None
+    if not args.no_side_by_side:
+        for _ in range(max(1, args.warmup)):
+            conc_step()
+        if stream is not None:
+            torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for _ in range(args.steps):
+            conc_step()
+        if stream is not None:
+            torch.cuda.synchronize()
+        conc_elapsed = time.perf_counter() - t_c
 
     ms_total, launches, _ = kt[dom]
     alg_bytes = bytes_per_step.get(dom, 0.0) * args.steps
@@ -607,7 +611,7 @@ def main() -> int:
         "nnz_result_per_step": int(sum(v["nnz"] for v in plans.values())),
         # not the headline: the queries of a step evaluated concurrently instead of one at a time
         "side_by_side": {"lanes": conc_lanes, "queries_per_s": round(n_q / conc_elapsed, 3),
-                         "ms_per_step": round(conc_elapsed / args.steps * 1e3, 3)},
+                         "ms_per_step": round(conc_elapsed / args.steps * 1e3, 3)} if conc_elapsed else None,
     }
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
