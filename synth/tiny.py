@@ -3,7 +3,8 @@
 Random schemas (2-4 node types, self-relations allowed, relations directed
 and independent), one small integer property per type, and random schema
 walks with random per-position constraints, including the degenerate ones:
-empty id sets, ranges that keep nothing or everything, empty relations.
+empty id sets, ranges that keep nothing or everything, empty relations, and
+positions that carry two constraints at once.
 """
 from __future__ import annotations
 
@@ -34,7 +35,8 @@ def random_hin(seed: int, max_nodes: int = 12, max_types: int = 4,
     return hin
 
 
-def random_query(hin: HIN, rng: np.random.Generator, max_len: int = 6) -> Query | None:
+def random_query(hin: HIN, rng: np.random.Generator, max_len: int = 6,
+                 p_double: float = 0.25) -> Query | None:
     outs = {}
     for (s, d) in hin.relations:
         outs.setdefault(s, []).append(d)
@@ -52,8 +54,8 @@ def random_query(hin: HIN, rng: np.random.Generator, max_len: int = 6) -> Query 
     if len(types) < 2:
         return None
     cons = []
-    for i, ty in enumerate(types):
-        u = rng.random()
+
+    def draw(i, ty, u):
         if u < 0.3:
             lo = int(rng.integers(-1, 10))
             hi = int(rng.integers(lo - 1, 11))
@@ -62,4 +64,11 @@ def random_query(hin: HIN, rng: np.random.Generator, max_len: int = 6) -> Query 
             k = int(rng.integers(0, hin.counts[ty] + 1))
             ids = np.sort(rng.choice(hin.counts[ty], size=k, replace=False)).astype(np.int32)
             cons.append(Constraint(i, "idset", ids=ids))
+
+    for i, ty in enumerate(types):
+        draw(i, ty, rng.random())
+        if rng.random() < p_double:
+            # a second constraint at the same position (range and id set, two
+            # id sets or two ranges): the position keeps what passes both
+            draw(i, ty, 0.45 * rng.random())
     return Query("-".join(types), types, cons)

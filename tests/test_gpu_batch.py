@@ -1,7 +1,7 @@
 """Batches and the serving loop (workloads of queries, Problem 2): every
-result is bit-identical to the same query evaluated alone, whatever the lanes,
-fusion, memory admission, cache and arrival order; fused chains that overflow
-fall back to one query at a time."""
+result is bit-identical to the CPU oracle's (and so to the same query
+evaluated alone), whatever the lanes, fusion, memory admission, cache and
+arrival order; fused chains that overflow fall back to one query at a time."""
 import numpy as np
 import pytest
 
@@ -57,14 +57,24 @@ def alone_results(atp, hin, qs):
 
 
 @pytest.fixture(scope="module")
-def mixed(atp, net):
+def mixed(atp, oracle_mod, net):
+    """The mixed queries and their oracle results; each query evaluated alone
+    on the GPU equals its oracle result, so every comparison with ``ref``
+    below is a comparison with the oracle."""
     qs = mixed_queries(net)
-    return qs, alone_results(atp, net, qs)
+    ref = []
+    for q in qs:
+        rp, col, val, st = oracle_mod.eval_full(net, q, nthreads=8)
+        assert st == oracle_mod.ORC_OK, q.name
+        ref.append((rp, col, val.astype(np.int64)))
+    for z, got in enumerate(alone_results(atp, net, qs)):
+        assert same(got, ref[z]), (z, qs[z].name)
+    return qs, ref
 
 
 @pytest.mark.parametrize("lanes,max_batch,budget", [(1, 1, 0), (1, 16, 0), (4, 16, 0), (4, 64, 1 << 20),
                                                     (3, 4, 0)])
-def test_batch_equals_alone(atp, net, mixed, lanes, max_batch, budget):
+def test_batch_equals_oracle(atp, net, mixed, lanes, max_batch, budget):
     qs, ref = mixed
     ctx = atp.Context(device=0)
     ctx.load_hin(net)
@@ -103,7 +113,7 @@ def test_batch_fuses_and_matches_oracle(atp, oracle_mod, net):
     ctx.close()
 
 
-def test_empty_and_invalid_members(atp, net):
+def test_empty_and_invalid_members(atp, oracle_mod, net):
     """An empty start set and a malformed query inside a batch."""
     ctx = atp.Context(device=0)
     ctx.load_hin(net)
@@ -117,6 +127,8 @@ def test_empty_and_invalid_members(atp, net):
     assert same(host(res[0]), host(res[3]))
     alone = ctx.eval_query(good)
     assert same(host(res[0]), host(alone))
+    orp, ocol, oval, st = oracle_mod.eval_full(net, good)
+    assert st == oracle_mod.ORC_OK and same(host(res[0]), (orp, ocol, oval.astype(np.int64)))
     ctx.close()
 
 
@@ -132,7 +144,7 @@ def _overflow_net():
     return hin
 
 
-def test_fused_overflow_falls_back_to_each_query(atp):
+def test_fused_overflow_falls_back_to_each_query(atp, oracle_mod):
     hin = _overflow_net()
     types = ["A", "B"] * 4 + ["A"]
     q0 = Query("hub", types, [Constraint(0, "idset", ids=np.array([0], np.int32))])
@@ -146,13 +158,17 @@ def test_fused_overflow_falls_back_to_each_query(atp):
     res = ctx.eval_batch([q0, q1], lanes=1, max_batch=2)
     assert isinstance(res[0], atp.AtpError) and res[0].status == atp.ATP_EOVERFLOW
     assert same(host(res[1]), alone)
+    assert oracle_mod.eval_full(hin, q0)[3] == oracle_mod.ORC_OVERFLOW
+    orp, ocol, oval, st = oracle_mod.eval_full(hin, q1)
+    assert st == oracle_mod.ORC_OK and same(alone, (orp, ocol, oval.astype(np.int64)))
     ctx.close()
 
 
 @pytest.mark.parametrize("cache", [False, True])
-def test_server_results_equal_alone(atp, net, mixed, cache):
+def test_server_results_equal_oracle(atp, net, mixed, cache):
     """Continuous batching: requests submitted while others run are fused and
-    overlapped; each completion equals the query alone."""
+    overlapped; each completion equals the oracle's result (and the query
+    alone)."""
     qs, ref = mixed
     ctx = atp.Context(device=0)
     ctx.load_hin(net)

@@ -43,6 +43,56 @@ def test_oracle_equals_bruteforce_random(oracle_mod, seed):
     assert csr_to_dict(rp, col, val) == count_instances(hin, q)
 
 
+def _random_case(seed):
+    hin = tinygen.random_hin(seed, max_nodes=8)
+    rng = np.random.default_rng(10_000 + seed)
+    return hin, tinygen.random_query(hin, rng, max_len=5)
+
+
+def _doubled_positions(q):
+    pos = [c.position for c in q.constraints]
+    return {p for p in pos if pos.count(p) > 1}
+
+
+def test_random_cases_reach_anded_constraints():
+    """The brute-force cases above include positions with two constraints
+    (Def. 3 allows one per position; several are read as their conjunction),
+    with both kinds mixed and with two id sets."""
+    kinds = set()
+    n_doubled = 0
+    for seed in range(300):
+        hin, q = _random_case(seed)
+        if q is None:
+            continue
+        for p in _doubled_positions(q):
+            n_doubled += 1
+            kinds.add(tuple(sorted(c.kind for c in q.constraints if c.position == p)))
+    assert n_doubled >= 40
+    assert {("idset", "range"), ("idset", "idset"), ("range", "range")} <= kinds
+
+
+def test_last_constraint_wins_mistake_is_caught(oracle_mod, monkeypatch):
+    """Plant a plausible mistake in the oracle (the last constraint at a
+    position replaces the earlier ones instead of being ANDed with them): the
+    brute-force pin must reject it on some random case."""
+    def last_wins(hin, query):
+        masks = [None] * len(query.types)
+        for c in query.constraints:
+            masks[c.position] = oracle_mod.constraint_mask(hin, query.types[c.position], c)
+        return masks
+
+    monkeypatch.setattr(oracle_mod, "query_masks", last_wins)
+    caught = 0
+    for seed in range(300):
+        hin, q = _random_case(seed)
+        if q is None or not _doubled_positions(q):
+            continue
+        rp, col, val, st = oracle_mod.eval_full(hin, q)
+        if csr_to_dict(rp, col, val) != count_instances(hin, q):
+            caught += 1
+    assert caught >= 5
+
+
 def test_oracle_equals_bruteforce_tiny_config(oracle_mod, tiny_cfg):
     """The whole tiny scholarly query (A-P-T-P-A, 10% of topics), every pair."""
     hin, qs = tiny_cfg
@@ -322,6 +372,89 @@ def test_spgemm_valued_matches_scipy(oracle_mod):
         z.eliminate_zeros(); z.sort_indices()
         assert np.array_equal(rp, z.indptr) and np.array_equal(col, z.indices)
         assert np.array_equal(val.astype(np.int64), z.data)
+
+
+def _python_product(m, n, x, y):
+    """Exact Z = X * Y with Python integers (no fixed width), as a dict."""
+    out = {}
+    for i in range(m):
+        for e in range(x.indptr[i], x.indptr[i + 1]):
+            k, a = int(x.indices[e]), int(x.data[e])
+            for f in range(y.indptr[k], y.indptr[k + 1]):
+                j = int(y.indices[f])
+                out[(i, j)] = out.get((i, j), 0) + a * int(y.data[f])
+    return out
+
+
+def _large_value_case(oracle_mod, seed):
+    """Valued operands between 2^31 and 2^62: each entry of the oracle's
+    product is the exact sum (Python integers) when below 2^63 and 2^63
+    otherwise, and the status says overflow exactly when some entry reached
+    2^63 (the int64 reading of the counts)."""
+    rng = np.random.default_rng(100 + seed)
+    m, k, n = (int(v) for v in rng.integers(2, 12, size=3))
+    # X entries of b bits, b in [31, 62]; Y entries of about 61 - b bits, so
+    # that products and their sums straddle 2^63
+    bx = int(rng.integers(31, 63))
+    by = max(1, 61 - bx)
+
+    def vals_of(bits):
+        def draw(size):
+            b = np.clip(bits + rng.integers(-2, 2, size=size), 1, 62)
+            return np.array([int(rng.integers(1 << (int(v) - 1), 1 << int(v))) for v in b], dtype=np.int64)
+        return draw
+
+    x = sp.random(m, k, density=0.5, random_state=rng, format="csr", data_rvs=vals_of(bx), dtype=np.int64)
+    y = sp.random(k, n, density=0.5, random_state=rng, format="csr", data_rvs=vals_of(by), dtype=np.int64)
+    assert x.data.dtype == np.int64 and y.data.dtype == np.int64
+    x.sort_indices(); y.sort_indices()
+    exact = _python_product(m, n, x, y)
+    rp, col, val, st = oracle_mod.spgemm(m, n, x.indptr, x.indices, x.data.astype(np.int64),
+                                         y.indptr, y.indices, y.data.astype(np.int64))
+    got = csr_to_dict(rp, col, val)
+    assert set(got) == {ij for ij, v in exact.items() if v != 0}
+    for ij, v in exact.items():
+        assert got[ij] == min(v, 1 << 63), ij
+    over = any(v >= (1 << 63) for v in exact.values())
+    assert st == (oracle_mod.ORC_OVERFLOW if over else oracle_mod.ORC_OK)
+    return sum(1 for v in exact.values() if v >= (1 << 63)), sum(1 for v in exact.values() if 0 < v < (1 << 63))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_spgemm_large_values_saturate_exactly(oracle_mod, seed):
+    _large_value_case(oracle_mod, seed)
+
+
+def test_large_value_cases_straddle_the_bound(oracle_mod):
+    """The random large-value cases hold entries on both sides of 2^63 and
+    cases with and without overflow."""
+    stats = [_large_value_case(oracle_mod, s) for s in range(12)]
+    assert sum(a for a, _ in stats) > 20 and sum(b for _, b in stats) > 20
+    assert any(a == 0 for a, _ in stats) and any(a > 0 for a, _ in stats)
+
+
+@pytest.mark.parametrize("terms,total", [
+    ([(7, 1317624576693539401)], (1 << 63) - 1),                   # 7 * (2^63 - 1) / 7
+    ([(1 << 32, 1 << 31)], 1 << 63),                               # exactly 2^63
+    ([(1 << 31, 1 << 31), (1 << 62, 1)], (1 << 62) + (1 << 62)),   # two terms reaching 2^63
+    ([(3, 1 << 61), (1, (1 << 61) - 1)], (1 << 63) - 1),            # two terms just below
+    ([((1 << 62) + 1, 3)], 3 * ((1 << 62) + 1)),                     # one product far above
+])
+def test_spgemm_saturation_boundary(oracle_mod, terms, total):
+    """One output entry made of the given products x*y (1 x t times t x 1):
+    below 2^63 it is exact, at or above it reads 2^63 with ORC_OVERFLOW."""
+    t = len(terms)
+    xrp = np.array([0, t], np.int64)
+    xcol = np.arange(t, dtype=np.int32)
+    xval = np.array([a for a, _ in terms], np.int64)
+    yrp = np.arange(t + 1, dtype=np.int64)
+    ycol = np.zeros(t, np.int32)
+    yval = np.array([b for _, b in terms], np.int64)
+    assert sum(a * b for a, b in terms) == total
+    rp, col, val, st = oracle_mod.spgemm(1, 1, xrp, xcol, xval, yrp, ycol, yval)
+    assert list(rp) == [0, 1] and list(col) == [0]
+    assert int(val[0]) == min(total, 1 << 63)
+    assert st == (oracle_mod.ORC_OVERFLOW if total >= (1 << 63) else oracle_mod.ORC_OK)
 
 
 # ---------------------------------------------------------------------------
