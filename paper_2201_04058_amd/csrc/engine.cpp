@@ -83,8 +83,12 @@ atp_status read_values(Lane *L, const int64_t *src, int64_t n) {
     const uint64_t seq = ++L->seq;
     launch_post(src, n, L->d_mailbox, L->d_flag, seq, L->stream);
     HIPTRY(hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
     for (uint64_t it = 1;; ++it) {
         if (__atomic_load_n(L->h_flag, __ATOMIC_ACQUIRE) == seq) return ATP_OK;
+        if ((it & 63) == 0 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > L->wait_limit_s)
+            return ATP_EDEVICE;  // the caller synchronises the stream on its error path
         if ((it & 1023) == 0) {
             const hipError_t e = hipStreamQuery(L->stream);
             if (e == hipSuccess) {  // the post has run: its values are visible after a synchronisation
@@ -122,6 +126,9 @@ struct Mat {
     // the active list holds every candidate row, non-empty ones first
     Buf hdr;
     const int64_t *nnz_dev = nullptr;
+    // some count reached 2^63 (known when the size was read back; a deferred
+    // product is never cached, so it never needs the flag)
+    bool saturated = false;
 };
 
 struct PosMask {
@@ -453,13 +460,18 @@ atp_status spgemm(atp_ctx *c, Lane *L, const Mat &X, const Mat &Y, int64_t ycols
             Z.active_ptr = Z.active.as<int32_t>();
             launch_active_scatter(cand, n_cand, flags_scan.as<int64_t>(), Z.active.as<int32_t>(), true, s, t);
         }
-        if (nnz_acc) launch_accum_i64(&d_hdr->nnz_total, nnz_acc, s);
+        if (nnz_acc) launch_accum_step(d_hdr, nnz_acc, s);
         Z.nnz_dev = &d_hdr->nnz_total;
         Z.hdr = std::move(hdr);
     } else {
         TRY(read_header(L, d_hdr));
         const StepHeader h2 = *L->h_hdr;
+        if (h2.fault) {  // an LDS hash table ran out of probes: the product is invalid
+            c->broken = true;
+            return ATP_EDEVICE;
+        }
         saturated = h2.saturated != 0;
+        Z.saturated = saturated;
         Z.nnz = h2.nnz_total;
         st.nnz += Z.nnz;
         TRY(Z.col.alloc(pool, 4 * (size_t)std::max<int64_t>(Z.nnz, 1)));
@@ -569,8 +581,9 @@ uint64_t fnv1a64(const void *data, size_t n, uint64_t h = 1469598103934665603ull
     return h;
 }
 
-// canonical constraint string of every metapath position
-std::vector<std::string> position_keys(int32_t n_types, const atp_constraint *cons, int32_t n_cons) {
+// canonical constraint string of every metapath position; an id set is
+// named by its size and its context-wide serial number (exact identity)
+std::vector<std::string> position_keys(atp_ctx *c, int32_t n_types, const atp_constraint *cons, int32_t n_cons) {
     std::vector<std::vector<std::string>> per(n_types);
     for (int q = 0; q < n_cons; ++q) {
         const atp_constraint &k = cons[q];
@@ -581,8 +594,9 @@ std::vector<std::string> position_keys(int32_t n_types, const atp_constraint *co
             std::vector<int32_t> ids(k.ids, k.ids + k.n_ids);
             std::sort(ids.begin(), ids.end());
             ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
-            std::snprintf(buf, sizeof(buf), "I%zu:%016llx", ids.size(),
-                          (unsigned long long)fnv1a64(ids.data(), ids.size() * sizeof(int32_t)));
+            const size_t n = ids.size();
+            const uint64_t h = fnv1a64(ids.data(), n * sizeof(int32_t));
+            std::snprintf(buf, sizeof(buf), "I%zu:#%lld", n, (long long)c->idsets.serial(std::move(ids), h));
         }
         per[k.position].push_back(buf);
     }
@@ -742,13 +756,15 @@ atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std
     };
     std::vector<Cand> cands;
     cands.push_back(Cand{0, p - 1, root_cost, const_cast<Mat *>(&R), true});
+    // a product holding a count of 2^63 or more is never kept: as a whole
+    // query it must answer ATP_EOVERFLOW, which only a recomputation reports
     if (cs.policy == ATP_CACHE_CBS2) {
         for (auto &k : kept)
-            if (!k.partial) cands.push_back(Cand{k.lo, k.hi, k.cost, &k.m, false});
+            if (!k.partial && !k.m.saturated) cands.push_back(Cand{k.lo, k.hi, k.cost, &k.m, false});
     } else if (cs.policy != ATP_CACHE_CBS1) {
         KeptMat *best = nullptr;
         for (auto &k : kept) {
-            if (k.partial) continue;
+            if (k.partial || k.m.saturated) continue;
             const int node = cs.tree->find(std::vector<int32_t>(types + k.lo, types + k.hi + 2));
             if (node < 0 || cs.tree->node(node).leaf()) continue;
             if (!best || (k.hi - k.lo) > (best->hi - best->lo)) best = &k;
@@ -821,7 +837,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     // masks M_1..M_n (Def. 3).  Their popcounts (planner selectivities) come
     // from the id count of a lone id-set constraint, from a memo of range
     // constraints seen before, or from the device (one readback)
-    const std::vector<std::string> mkeys = position_keys(n_types, cons, n_cons);
+    const std::vector<std::string> mkeys = position_keys(c, n_types, cons, n_cons);
     std::vector<int> n_at(n_types, 0), ranges_at(n_types, 0);
     for (int q = 0; q < n_cons; ++q) {
         n_at[cons[q].position] += 1;
@@ -937,7 +953,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     uint64_t cache_budget = 0;
     if (caching) {
         cache_budget = cs.budget;
-        pkeys = position_keys(n_types, cons, n_cons);
+        pkeys = position_keys(c, n_types, cons, n_cons);
         for (int w = 0; w < weight; ++w) cs.tree->insert(std::vector<int32_t>(types, types + n_types));
         cs.stats.queries += weight;
         for (int a = 0; a < p; ++a)
@@ -1055,9 +1071,9 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     // a left operand whose size decides a restriction
     const bool may_defer = !caching && !(c->flags & ATP_OPT_COUNT_BYTES) && !c->cost_sink;
     Buf nnz_acc;
-    if (may_defer && p >= 3) {
-        TRY(nnz_acc.alloc(&L->pool, 8));
-        launch_fill_i64(nnz_acc.as<int64_t>(), 1, 0, s, t);
+    if (may_defer && p >= 3) {  // nonzeros and fault flag of the deferred products
+        TRY(nnz_acc.alloc(&L->pool, 16));
+        launch_fill_i64(nnz_acc.as<int64_t>(), 2, 0, s, t);
     }
     // Rows of a right sub-chain that can matter: the columns its left neighbour uses.
     struct Restriction {
@@ -1302,9 +1318,15 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     }
     // the deferred count comes back through the lane's pinned header, which
     // the last product has finished reading
-    if (nnz_acc.p) HIPTRY(hipMemcpyAsync(L->h_hdr, nnz_acc.p, 8, hipMemcpyDeviceToHost, s));
+    if (nnz_acc.p) HIPTRY(hipMemcpyAsync(L->h_hdr, nnz_acc.p, 16, hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
-    if (nnz_acc.p) st.nnz += *(const int64_t *)L->h_hdr;
+    if (nnz_acc.p) {
+        st.nnz += ((const int64_t *)L->h_hdr)[0];
+        if (((const int64_t *)L->h_hdr)[1]) {  // a deferred product's hash table overflowed
+            c->broken = true;
+            return ATP_EDEVICE;
+        }
+    }
     if (t) t->flush();
     if (c->cost_sink && !cost_recs.empty()) {
         std::lock_guard<std::mutex> g(c->stat_mu);
@@ -1361,7 +1383,7 @@ static std::string whole_key(atp_ctx *c, const QueryRef &q, std::vector<int32_t>
     if (resolve_rels(c, q.types, q.n_types, q.rel_ids, rel) != ATP_OK) return "";
     ty.assign(q.types, q.types + q.n_types);
     rl.assign(rel.begin(), rel.end());
-    ps = position_keys(q.n_types, q.cons, q.n_cons);
+    ps = position_keys(c, q.n_types, q.cons, q.n_cons);
     return item_key(ty, rl, ps);
 }
 
@@ -1398,6 +1420,7 @@ atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, const atp_r
 
 atp_status lane_init(atp_ctx *c, Lane *L, int id) {
     L->id = id;
+    L->wait_limit_s = c->wait_limit_s;
     L->pool.on_oom = [c]() { release_pool_caches(c); };
     L->pool.budget = c->main.pool.budget;
     L->pool.user_alloc = c->main.pool.user_alloc;
@@ -1532,6 +1555,7 @@ atp_status atp_create(const atp_options *o, atp_ctx **out) {
     c->main.pool.user = d.alloc_user;
     c->main.pool.budget = d.mem_budget_bytes;
     c->main.pool.on_oom = [c]() { release_pool_caches(c); };
+    c->main.wait_limit_s = c->wait_limit_s;
     if (lane_mailbox(&c->main) != ATP_OK) {
         delete c;
         return ATP_ENOMEM;

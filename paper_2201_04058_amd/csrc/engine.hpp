@@ -284,6 +284,7 @@ struct Lane {
     int64_t *d_mailbox = nullptr; // device addresses of h_hdr and h_flag (nullptr: read by copies)
     uint64_t *d_flag = nullptr;
     uint64_t seq = 0;
+    double wait_limit_s = 600.0;  // longest wait for posted values before the lane gives up (ATP_EDEVICE)
     KernelTimer timer;
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork = nullptr, join[kSideStreams] = {};
@@ -401,6 +402,25 @@ struct ProductHold {
 
 struct Server;  // serve.cpp
 
+// Identity of constraint id sets (cache keys, mask sharing, popcount memo):
+// each distinct canonical id list (sorted, unique) gets a serial number; a
+// lookup compares the whole list against the candidates of its hash, so two
+// different sets never share a number.  Lists are kept for the context's
+// lifetime (the keys that name them live as long).
+struct IdSets {
+    std::mutex mu;
+    std::map<uint64_t, std::vector<std::pair<std::vector<int32_t>, int64_t>>> by_hash;
+    int64_t next = 0;
+    int64_t serial(std::vector<int32_t> &&ids, uint64_t hash) {
+        std::lock_guard<std::mutex> g(mu);
+        auto &cands = by_hash[hash];
+        for (const auto &c : cands)
+            if (c.first == ids) return c.second;
+        cands.emplace_back(std::move(ids), next);
+        return next++;
+    }
+};
+
 }  // namespace atp
 
 struct atp_ctx {
@@ -415,6 +435,7 @@ struct atp_ctx {
     std::map<std::pair<int, int>, atp::JunctionSketch> sketches;
     std::map<int, atp::ColumnHist> col_hists;
     std::map<std::string, int64_t> pop_memo;  // mask popcount by (type, position constraint key)
+    atp::IdSets idsets;                       // id-set identities used in those keys
     atp::CostCoeffs cost;                     // Eq. 2 coefficients of the planner
     std::vector<std::array<double, 4>> *cost_sink = nullptr;  // (nnz(X), N_op, nnz(Z), ms) per multiplication
     atp::CacheState cache;
@@ -437,6 +458,9 @@ struct atp_ctx {
     int64_t chunk_hist_cap = std::getenv("ATP_CHUNK_HIST_CAP") ? std::atoll(std::getenv("ATP_CHUNK_HIST_CAP"))
                                                                : atp::kChunkHistCap;
     atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
+    // longest host wait for values a lane's kernels post (ATP_WAIT_LIMIT_S, seconds): a stream that
+    // neither finishes nor fails within it is treated as a device error
+    double wait_limit_s = std::getenv("ATP_WAIT_LIMIT_S") ? std::atof(std::getenv("ATP_WAIT_LIMIT_S")) : 600.0;
     atp::KernelTimer *kt(atp::Lane *L) { return (flags & ATP_OPT_PROFILE) ? &L->timer : nullptr; }
 };
 

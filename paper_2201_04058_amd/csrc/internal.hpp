@@ -73,7 +73,7 @@ struct StepHeader {
     int64_t n_active;         // non-empty result rows
     uint64_t vmax;            // largest result value (the compaction copy's maximum)
     int32_t saturated;        // some emitted value is saturated
-    int32_t pad;
+    int32_t fault;            // an LDS hash table overflowed its probe bound (a sizing error): result invalid
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------------
@@ -199,8 +199,8 @@ void launch_active_flags(const int32_t *cand, int64_t n_cand, const int64_t *row
 // follow, so that `active` holds n_cand rows
 void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *flags_scan, int32_t *active,
                            bool partition, hipStream_t s, KernelTimer *t);
-// *dst += *src on the stream
-void launch_accum_i64(const int64_t *src, int64_t *dst, hipStream_t s);
+// dst[0] += h->nnz_total, dst[1] |= h->fault on the stream (a deferred product's totals)
+void launch_accum_step(const StepHeader *h, int64_t *dst, hipStream_t s);
 
 // row restriction: columns used by a left operand -> bitmap -> ascending list
 // nnz_dev (optional) holds the true entry count on the device, nnz its upper bound

@@ -142,11 +142,16 @@ __device__ __forceinline__ uint32_t hash_of(int32_t j, int log2s) {
     return ((uint32_t)j * 0x9E3779B1u) >> (32 - log2s);
 }
 
+// Slot of column j in an open-addressing LDS table of S slots, inserted if
+// absent.  Tables hold at least twice the distinct columns they receive, so a
+// probe sequence ends within S steps; should it not (a sizing error), *fault
+// is set and slot 0 is returned: the product's result is then wrong, and the
+// host, which reads the fault flag, discards it (ATP_EDEVICE).
 template <int S>
-__device__ __forceinline__ uint32_t hash_find(int32_t *keys, int32_t j) {
+__device__ __forceinline__ uint32_t hash_find(int32_t *keys, int32_t j, int32_t *fault) {
     constexpr int L = __builtin_ctz(S);
     uint32_t h = hash_of(j, L);
-    while (true) {
+    for (int n = 0; n < S; ++n) {
         int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k == j) return h;
         if (k == kEmptyKey) {
@@ -155,6 +160,8 @@ __device__ __forceinline__ uint32_t hash_find(int32_t *keys, int32_t j) {
         }
         h = (h + 1) & (S - 1);
     }
+    atomicOr(fault, 1);
+    return 0;
 }
 
 // Accumulate row i of X*Y into an LDS hash table.  Groups of g lanes walk one
@@ -162,7 +169,7 @@ __device__ __forceinline__ uint32_t hash_find(int32_t *keys, int32_t j) {
 template <int S>
 __device__ __forceinline__ void accumulate_hash(const Operand &X, const Operand &Y, int64_t xb, int64_t xe,
                                                 int gid, int ng, int li, int g, int32_t *keys,
-                                                unsigned long long *vals, uint32_t *satw) {
+                                                unsigned long long *vals, uint32_t *satw, int32_t *fault) {
     for (int64_t e = xb + gid; e < xe; e += ng) {
         int32_t k = X.col[e];
         if (X.cmask && !bit_test(X.cmask, k)) continue;
@@ -172,7 +179,7 @@ __device__ __forceinline__ void accumulate_hash(const Operand &X, const Operand 
             int32_t j = Y.col[f];
             if (Y.cmask && !bit_test(Y.cmask, j)) continue;
             uint64_t c = Y.val ? sat_mul(xv, Y.val[f]) : xv;
-            uint32_t h = hash_find<S>(keys, j);
+            uint32_t h = hash_find<S>(keys, j, fault);
             acc_add(&vals[h], satw, h, c);
         }
     }
@@ -317,21 +324,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_small(ScanJobs sj) {
 // ---------------------------------------------------------------------------
 // masks (diagonal M_c as a bitset)
 
+// One bit per node: lo <= prop <= hi.  Each wavefront covers 64 consecutive
+// nodes per step (one ballot, two words), striding over the grid until every
+// node is covered, so any node count fits the launch.
 template <typename T>
 __global__ void k_mask_range(const T *prop, int64_t n, int64_t lo, int64_t hi, uint32_t *bits, int64_t words,
                              int and_mode) {
-    int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    bool keep = false;
-    if (gid < n) {
-        int64_t v = (int64_t)prop[gid];
-        keep = v >= lo && v <= hi;
-    }
-    uint64_t b = __ballot(keep);
-    if ((threadIdx.x & 63) == 0) {
-        int64_t w = gid >> 5;
-        uint32_t w0 = (uint32_t)b, w1 = (uint32_t)(b >> 32);
-        if (w < words) bits[w] = and_mode ? (bits[w] & w0) : w0;
-        if (w + 1 < words) bits[w + 1] = and_mode ? (bits[w + 1] & w1) : w1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int64_t gid = base + (threadIdx.x & 63);
+        bool keep = false;
+        if (gid < n) {
+            int64_t v = (int64_t)prop[gid];
+            keep = v >= lo && v <= hi;
+        }
+        uint64_t b = __ballot(keep);
+        if ((threadIdx.x & 63) == 0) {
+            int64_t w = base >> 5;
+            uint32_t w0 = (uint32_t)b, w1 = (uint32_t)(b >> 32);
+            if (w < words) bits[w] = and_mode ? (bits[w] & w0) : w0;
+            if (w + 1 < words) bits[w + 1] = and_mode ? (bits[w + 1] & w1) : w1;
+        }
     }
 }
 
@@ -758,11 +771,11 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
             if (tot < kWalkMax)
                 walk_products_any<64, kHashUnroll>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
                                       [&](int32_t j, uint64_t v) {
-                                          const uint32_t h = hash_find<S>(keys, j);
+                                          const uint32_t h = hash_find<S>(keys, j, &a.hdr->fault);
                                           acc_add(&vals[h], satw, h, v);
                                       });
             else
-                accumulate_hash<S>(a.X, a.Y, eb, eb + nb, 0, 1, lane, 64, keys, vals, satw);
+                accumulate_hash<S>(a.X, a.Y, eb, eb + nb, 0, 1, lane, 64, keys, vals, satw, &a.hdr->fault);
             wave_sync();
         }
         // compact the occupied slots to the front in one pass (a slot is read
@@ -896,12 +909,12 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
             if (tot < kWalkMax)
                 walk_products_any<NT, kHashUnroll>(a.Y, seg_o, seg_s, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr,
                                       [&](int32_t j, uint64_t v) {
-                                          const uint32_t h = hash_find<S>(keys, j);
+                                          const uint32_t h = hash_find<S>(keys, j, &a.hdr->fault);
                                           acc_add(&vals[h], satw, h, v);
                                       });
             else
                 accumulate_hash<S>(a.X, a.Y, eb, eb + nb, threadIdx.x >> 6, NT / 64, threadIdx.x & 63, 64, keys,
-                                   vals, satw);
+                                   vals, satw, &a.hdr->fault);
             __syncthreads();
         }
         // compact the occupied slots to the front (each thread's slots pass
@@ -1149,10 +1162,11 @@ __device__ void flush_split_tile(const NumericArgs &a, int64_t gt, int64_t ks, i
     }
 }
 
-__device__ __forceinline__ uint32_t hash_find_rt(int32_t *keys, int32_t j, int log2s) {
+// hash_find with the table size 2^log2s known at run time (same probe bound)
+__device__ __forceinline__ uint32_t hash_find_rt(int32_t *keys, int32_t j, int log2s, int32_t *fault) {
     const uint32_t mask = (1u << log2s) - 1u;
     uint32_t h = hash_of(j, log2s);
-    while (true) {
+    for (uint32_t n = 0; n <= mask; ++n) {
         int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k == j) return h;
         if (k == kEmptyKey) {
@@ -1161,6 +1175,8 @@ __device__ __forceinline__ uint32_t hash_find_rt(int32_t *keys, int32_t j, int l
         }
         h = (h + 1) & mask;
     }
+    atomicOr(fault, 1);
+    return 0;
 }
 
 // Emit a sparse part of row i (candidate c), columns [c0p, c1p): values in
@@ -1198,7 +1214,13 @@ __device__ void emit_hash_part(const NumericArgs &a, int32_t c, int64_t i, int64
             bits &= bits - 1;
             const int32_t col = (int32_t)(c0p + (int64_t)w * 32 + b);
             uint32_t h = hash_of(col, log2s);
-            while (keys[h] != col) h = (h + 1) & hmask;
+            for (uint32_t n = 0; keys[h] != col; ++n) {  // present: inserted by hash_find_rt
+                if (n > hmask) {  // not found (only after a fault of the insertion): emit garbage, flagged
+                    atomicOr(&a.hdr->fault, 1);
+                    break;
+                }
+                h = (h + 1) & hmask;
+            }
             const bool sb = (satw[h >> 5] >> (h & 31)) & 1u;
             sat |= sb;
             a.slot_col[pos] = col;
@@ -1409,7 +1431,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
                 const int64_t tot = single ? ltot : segments(xb, xlen, eb, c0p, c1p, false, false);
                 const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
                 products(tot, xval, [&](int32_t j, uint64_t v) {
-                    const uint32_t h = hash_find_rt(keys, j, log2s);
+                    const uint32_t h = hash_find_rt(keys, j, log2s, &a.hdr->fault);
                     acc_add(&vals[h], satw, h, v);
                     const int64_t r = j - c0p;
                     atomicOr(&bm[r >> 5], 1u << (r & 31));
@@ -1829,7 +1851,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
             for (int64_t e = off[t] + tid; e < off[t1]; e += kDenseThreads) {
                 const int32_t j = b.prod_col[e];
                 const uint64_t v = valued ? b.prod_val[e] : 1ull;
-                const uint32_t h = hash_find_rt(keys, j, log2s);
+                const uint32_t h = hash_find_rt(keys, j, log2s, &a.hdr->fault);
                 acc_add(&vals[h], satw, h, v);
                 const int64_t r = j - c0p;
                 atomicOr(&bm[r >> 5], 1u << (r & 31));
@@ -1939,7 +1961,12 @@ __global__ void k_active_scatter(const int32_t *cand, int64_t n_cand, const int6
 }
 
 // *dst += *src (one value; per-query statistics kept on the device)
-__global__ void k_accum_i64(const int64_t *src, int64_t *dst) { *dst += *src; }
+// a deferred product's step header into the query's totals: nonzeros added,
+// fault flag or-ed
+__global__ void k_accum_step(const StepHeader *h, int64_t *dst) {
+    dst[0] += h->nnz_total;
+    dst[1] |= h->fault;
+}
 
 // ---------------------------------------------------------------------------
 // rows of a fused batch result handed to one member query
@@ -2188,9 +2215,8 @@ void launch_fill_multi(const FillJob *jobs, int n_jobs, hipStream_t s, KernelTim
 void launch_mask_range(const void *prop, int32_t dtype, int64_t n, int64_t lo, int64_t hi, uint32_t *bits,
                        int and_mode, hipStream_t s, KernelTimer *t) {
     int64_t words = (n + 31) / 32;
-    int64_t threads = ((n + 63) / 64) * 64;
-    dim3 g(grid_for(threads, 256)), b(256);
-    if (threads > (int64_t)g.x * 256) return;  // cannot happen below 2^28 nodes
+    // the kernel strides over the nodes: a capped grid covers any count
+    dim3 g(grid_for(((n + 63) / 64) * 64, 256, 4096)), b(256);
     if (dtype == 1)
         ATP_LAUNCH("mask", 0, 0, s, k_mask_range<int16_t>, g, b, 0, s, (const int16_t *)prop, n, lo, hi, bits, words,
                    and_mode);
@@ -2318,8 +2344,8 @@ void launch_active_scatter(const int32_t *cand, int64_t n_cand, const int64_t *f
                n_cand, flags_scan, active, partition ? 1 : 0);
 }
 
-void launch_accum_i64(const int64_t *src, int64_t *dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_accum_i64, dim3(1), dim3(1), 0, s, src, dst);
+void launch_accum_step(const StepHeader *h, int64_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_accum_step, dim3(1), dim3(1), 0, s, h, dst);
 }
 
 void launch_bin_stats(const int32_t *list, int64_t n, const Operand &X, const int32_t *cand, const int64_t *row_nnz,

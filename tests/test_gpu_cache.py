@@ -6,6 +6,7 @@ import pytest
 
 from synth import configs, workload
 from synth.hin import Constraint, Query
+from tests._nets import _narrow_and_wide
 
 pytestmark = pytest.mark.gpu
 
@@ -150,4 +151,34 @@ def test_cache_off_again_matches(atp, oracle_mod, scholarly_small):
     for q in qs[10:20]:
         assert same(ctx.eval_query(q), oracle_mod.eval_full(hin, q))
     assert ctx.cache_stats()["queries"] == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("policy", ["ATP_CACHE_CBS2", "ATP_CACHE_OTREE"])
+def test_saturated_intermediate_is_not_served_from_the_cache(atp, oracle_mod, policy):
+    """A sub-chain whose counts reach 2^63 on rows the query's start never
+    reaches (a dead intermediate): the query itself is exact, and a later
+    query equal to that sub-chain must still report ATP_EOVERFLOW, as the
+    oracle does (Problem 1 with int64 counts), not a cached saturated copy."""
+    hin, q = _narrow_and_wide()
+    ref = oracle_mod.eval_full(hin, q)
+    assert ref[3] == oracle_mod.ORC_OK
+    suffix = Query("-".join(q.types[1:]), q.types[1:], [])
+    assert oracle_mod.eval_full(hin, suffix)[3] == oracle_mod.ORC_OVERFLOW
+    ctx = atp.Context(device=0)
+    ctx.load_hin(hin)
+    ctx.set_flags(no_restrict=True)  # suffix products on all their rows: cache candidates
+    ctx.cache_configure(getattr(atp, policy), 1 << 30)
+    p = len(q.types) - 1
+    rd = str(p - 1)
+    for i in range(p - 2, -1, -1):
+        rd = f"({i},{rd})"
+    for _ in range(3):  # the suffix recurs: every policy considers it
+        res = ctx.eval_query(q, plan=rd)
+        assert same(res, ref)
+        res.free()
+    for _ in range(2):
+        with pytest.raises(atp.AtpError) as e:
+            ctx.eval_query(suffix)
+        assert e.value.status == atp.ATP_EOVERFLOW
     ctx.close()

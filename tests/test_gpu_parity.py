@@ -9,6 +9,7 @@ import pytest
 from synth import configs
 from synth import tiny as tinygen
 from synth.hin import HIN, Constraint, Query, Relation
+from tests._nets import _csr_rel, _narrow_and_wide
 
 pytestmark = pytest.mark.gpu
 
@@ -110,14 +111,6 @@ def _bip(hin, a, b, pairs):
     rp2 = np.zeros(nb + 1, np.int64)
     np.cumsum(t.sum(1), out=rp2[1:])
     hin.relations[(b, a)] = Relation(b, a, rp2, np.nonzero(t)[1].astype(np.int32))
-
-
-def _csr_rel(hin, a, b, rows):
-    """relation a->b from per-row sorted column lists"""
-    rp = np.zeros(len(rows) + 1, np.int64)
-    np.cumsum([len(r) for r in rows], out=rp[1:])
-    col = np.concatenate([np.asarray(r, np.int32) for r in rows]) if rows else np.zeros(0, np.int32)
-    hin.relations[(a, b)] = Relation(a, b, rp, col.astype(np.int32))
 
 
 @pytest.mark.parametrize("n_out", [1, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513,
@@ -269,25 +262,6 @@ def test_overflow_is_detected_for_every_plan(atp, oracle_mod, widths, over):
     ctx.close()
 
 
-def _narrow_and_wide(n_wide_layers=10, width=128):
-    """L0 (1 node) -> L1..Lk (node 0 = a narrow lane, nodes 1..width = a wide
-    lane of complete bipartite layers) -> L_{k+1} (1 node).  The start only
-    enters the narrow lane, so R = [[1]], but suffix products reach width^(k-1)
-    paths from every wide node."""
-    k = n_wide_layers
-    names = [f"L{i}" for i in range(k + 2)]
-    counts = {names[0]: 1, names[-1]: 1}
-    for i in range(1, k + 1):
-        counts[names[i]] = width + 1
-    hin = HIN(counts=counts)
-    _csr_rel(hin, names[0], names[1], [[0]])
-    wide = list(range(1, width + 1))
-    for i in range(1, k):
-        _csr_rel(hin, names[i], names[i + 1], [[0]] + [wide] * width)
-    _csr_rel(hin, names[k], names[k + 1], [[0]] * (width + 1))
-    return hin, Query("-".join(names), names, [])
-
-
 def test_dead_intermediate_may_exceed_int64(atp, oracle_mod):
     """Suffix products hold counts of 2^63 on rows the start never reaches;
     the final count is 1, so every plan returns the exact result."""
@@ -306,6 +280,27 @@ def test_dead_intermediate_may_exceed_int64(atp, oracle_mod):
 
 # ---------------------------------------------------------------------------
 # errors
+
+def test_wait_limit_turns_a_stalled_read_into_a_device_error(atp, oracle_mod, monkeypatch):
+    """The host waits for a product's posted sizes at most ATP_WAIT_LIMIT_S
+    seconds; past it the query ends with ATP_EDEVICE (the context is then
+    unusable, as documented) instead of spinning.  The limit is forced tiny
+    from the host; the kernels themselves finish normally, and a context
+    created with the default limit returns the oracle's result."""
+    hin, rng = configs.make_hin("scholarly", 0.01)
+    q = [x for x in configs.make_queries("scholarly", hin, rng) if x.name == "T-P-A-P-T"][0]
+    monkeypatch.setenv("ATP_WAIT_LIMIT_S", "1e-9")
+    ctx = make_ctx(atp, hin)
+    for _ in range(2):
+        with pytest.raises(atp.AtpError) as e:
+            ctx.eval_query(q)
+        assert e.value.status == atp.ATP_EDEVICE
+    ctx.close()
+    monkeypatch.delenv("ATP_WAIT_LIMIT_S")
+    ctx = make_ctx(atp, hin)
+    assert_same(ctx.eval_query(q), oracle_mod.eval_full(hin, q, nthreads=8))
+    ctx.close()
+
 
 def test_error_paths_leave_the_context_usable(atp, oracle_mod, tiny_cfg):
     hin, qs = tiny_cfg
