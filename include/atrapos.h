@@ -146,6 +146,30 @@ atp_status atp_eval_plan(atp_ctx *ctx, const int32_t *types, int32_t n_types, co
                          const atp_constraint *cons, int32_t n_cons, const char *plan,
                          atp_result **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): atp_eval /
+ * atp_eval_plan (plan may be NULL) writing the result into caller-owned
+ * device arrays, with every temporary of the evaluation taken from a static
+ * device workspace of ATP_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends.  The call allocates no device
+ * memory and creates no stream: the masks, per-product arrays and slot
+ * arrays of the whole query must fit the workspace together, and the cache
+ * (if configured) is neither read nor updated.
+ *   row_ptr  device, count(types[0]) + 1 int64
+ *   col      device, cap int32;  val  device, cap int64  (NULL allowed when cap = 0)
+ *   *nnz     the result's nonzero count (set whenever the evaluation finished)
+ * The result is identical to atp_eval's.  Errors: ATP_EBUDGET when the query
+ * needs more workspace than ATP_NOALLOC_SCRATCH_BYTES; ATP_EINVAL for bad
+ * arguments or when the result has more than cap nonzeros (*nnz then tells
+ * the size needed); otherwise as atp_eval.  The call returns after the
+ * result is written (the context's stream is synchronised).  All calls on
+ * one GPU share its workspace: calls that overlap in time on the same GPU
+ * (from several contexts or threads) race and must not be made. */
+#define ATP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+atp_status atp_eval_noalloc(atp_ctx *ctx, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                            const atp_constraint *cons, int32_t n_cons, const char *plan, int64_t *row_ptr,
+                            int32_t *col, int64_t *val, int64_t cap, int64_t *nnz);
+
 /* Shape and device arrays of a result.  Pointers stay valid until
  * atp_result_free; any output pointer argument may be NULL. */
 atp_status atp_result_csr(const atp_result *res, int64_t *n_rows, int64_t *n_cols, int64_t *nnz,

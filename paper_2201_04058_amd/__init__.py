@@ -23,7 +23,7 @@ ATP_C_RANGE, ATP_C_IDSET = 1, 2
 
 EXPORTS = [
     "atp_create", "atp_destroy", "atp_add_node_type", "atp_add_relation", "atp_add_property",
-    "atp_eval", "atp_eval_plan", "atp_result_csr", "atp_result_to_host", "atp_result_stats",
+    "atp_eval", "atp_eval_plan", "atp_eval_noalloc", "atp_result_csr", "atp_result_to_host", "atp_result_stats",
     "atp_result_free", "atp_plan_chain", "atp_set_flags", "atp_kernel_times", "atp_kernel_times_reset",
     "atp_set_profile_kernel",
     "atp_device_bytes", "atp_status_str", "atp_cache_configure", "atp_cache_get_stats", "atp_otree_create",
@@ -126,6 +126,7 @@ def lib() -> ctypes.CDLL:
         "atp_add_property": ([vp, i32, ctypes.c_char_p, i32, vp, P(i32)], i32),
         "atp_eval": ([vp, vp, i32, vp, vp, i32, P(vp)], i32),
         "atp_eval_plan": ([vp, vp, i32, vp, vp, i32, ctypes.c_char_p, P(vp)], i32),
+        "atp_eval_noalloc": ([vp, vp, i32, vp, vp, i32, ctypes.c_char_p, vp, vp, vp, i64, P(i64)], i32),
         "atp_result_csr": ([vp, P(i64), P(i64), P(i64), P(vp), P(vp), P(vp)], i32),
         "atp_result_to_host": ([vp, vp, vp, vp], i32),
         "atp_result_stats": ([vp, P(atp_eval_stats), ctypes.c_char_p, ctypes.c_size_t], i32),
@@ -407,6 +408,25 @@ class Context:
 
     def eval_query(self, query, plan: str | None = None) -> Result:
         return self.eval(query.types, query.constraints, plan=plan)
+
+    def eval_noalloc(self, query, row_ptr: int, col: int, val: int, cap: int, plan: str | None = None) -> int:
+        """atp_eval_noalloc: the result into caller-owned device arrays (device
+        addresses row_ptr, col, val; col / val hold cap entries).  Returns the
+        result's nonzero count; raises AtpError (status and, for a result
+        larger than cap, the count needed as .nnz)."""
+        tids = np.array([self.type_ids[t] if isinstance(t, str) else int(t) for t in query.types], dtype=np.int32)
+        names = [t if isinstance(t, str) else None for t in query.types]
+        arr, keep = self._constraints(names, list(query.constraints))
+        nnz = ctypes.c_int64(-1)
+        st = lib().atp_eval_noalloc(self._h, tids.ctypes.data, len(tids), None, arr, len(query.constraints),
+                                    None if plan is None else plan.encode(), row_ptr, col, val, int(cap),
+                                    ctypes.byref(nnz))
+        del keep
+        if st != ATP_OK:
+            e = AtpError(st, "atp_eval_noalloc")
+            e.nnz = nnz.value
+            raise e
+        return nnz.value
 
     def _query(self, query):
         """(atp_query, arrays it points to) for a query object with types / constraints."""

@@ -14,6 +14,34 @@
 
 using namespace atp;
 
+// Device workspace of atp_eval_noalloc: every temporary of such a call is
+// carved out of it in order (Pool arena mode).  One copy per GPU, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel or
+// a copy (on the host it only names the symbol): it uses the per-device
+// address looked up once by scratch_address().
+static __device__ __align__(256) unsigned char scratch[ATP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device ordinal -> address of that device's copy
+
+// The current device's copy of `scratch` (the device must be current).
+atp_status scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return ATP_EDEVICE;
+        }
+        it = g_scratch_ptr.emplace(device, ptr).first;
+    }
+    *out = it->second;
+    return ATP_OK;
+}
+}  // namespace
+
 namespace atp {
 
 void timer_begin(KernelTimer *t, const char *name, hipStream_t s) {
@@ -803,7 +831,8 @@ atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std
 }
 
 atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
-                     const atp_constraint *cons, int32_t n_cons, const char *plan, int weight, atp_result **out) {
+                     const atp_constraint *cons, int32_t n_cons, const char *plan, int weight, atp_result **out,
+                     bool use_cache = true) {
     if (out) *out = nullptr;
     if (!c || !types || !out) return ATP_EINVAL;
     if (c->broken) return ATP_EDEVICE;
@@ -940,7 +969,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     // ---- workload cache: Overlap Tree update and cached sub-chains ----
     CacheState &cs = c->cache;
     std::unique_lock<std::mutex> cache_lock(cs.mu);
-    const bool caching = cs.policy != ATP_CACHE_OFF && p >= 2;
+    const bool caching = use_cache && cs.policy != ATP_CACHE_OFF && p >= 2;
     std::vector<std::string> pkeys;
     std::vector<std::vector<int64_t>> cached_item(p, std::vector<int64_t>(p, -1));
     std::map<int64_t, PayloadRef> pins;  // cached results this query may read
@@ -1556,6 +1585,11 @@ atp_status atp_create(const atp_options *o, atp_ctx **out) {
     c->main.pool.budget = d.mem_budget_bytes;
     c->main.pool.on_oom = [c]() { release_pool_caches(c); };
     c->main.wait_limit_s = c->wait_limit_s;
+    // the static workspace of atp_eval_noalloc on this device (looked up once per device)
+    if (scratch_address(d.device, &c->scratch) != ATP_OK) {
+        delete c;
+        return ATP_EDEVICE;
+    }
     if (lane_mailbox(&c->main) != ATP_OK) {
         delete c;
         return ATP_ENOMEM;
@@ -1699,6 +1733,53 @@ atp_status atp_eval_plan(atp_ctx *c, const int32_t *types, int32_t n_types, cons
                          const atp_constraint *cons, int32_t n_cons, const char *plan, atp_result **out) {
     if (c) (void)hipSetDevice(c->device);
     return eval_impl(c, &c->main, types, n_types, rel_ids, cons, n_cons, plan, 1, out);
+}
+
+atp_status atp_eval_noalloc(atp_ctx *c, const int32_t *types, int32_t n_types, const int32_t *rel_ids,
+                            const atp_constraint *cons, int32_t n_cons, const char *plan, int64_t *row_ptr,
+                            int32_t *col, int64_t *val, int64_t cap, int64_t *nnz) {
+    if (nnz) *nnz = -1;
+    if (!c || !row_ptr || !nnz || cap < 0 || (cap > 0 && (!col || !val))) return ATP_EINVAL;
+    if (c->broken) return ATP_EDEVICE;
+    if (!c->scratch) return ATP_ESTATE;
+    (void)hipSetDevice(c->device);
+    Lane *L = &c->main;
+    {
+        std::lock_guard<std::recursive_mutex> g(L->pool.mu);
+        L->pool.arena = (char *)c->scratch;
+        L->pool.arena_size = ATP_NOALLOC_SCRATCH_BYTES;
+        L->pool.arena_used = 0;
+    }
+    // the bins of a product stay on the context's stream (side streams would be created on first use)
+    const uint32_t saved_flags = c->flags;
+    c->flags |= ATP_OPT_SERIAL_BINS;
+    atp_result *r = nullptr;
+    atp_status st = eval_impl(c, L, types, n_types, rel_ids, cons, n_cons, plan, 1, &r, false);
+    if (st == ATP_OK) {
+        // eval_impl has synchronised the stream: the result is complete in the workspace
+        *nnz = r->nnz;
+        if (r->nnz > cap) {
+            st = ATP_EINVAL;
+        } else if (hipMemcpyAsync(row_ptr, r->rp.p, 8 * (size_t)(r->rows + 1), hipMemcpyDeviceToDevice, L->stream) !=
+                       hipSuccess ||
+                   (r->nnz && hipMemcpyAsync(col, r->col.p, 4 * (size_t)r->nnz, hipMemcpyDeviceToDevice,
+                                             L->stream) != hipSuccess) ||
+                   (r->nnz && hipMemcpyAsync(val, r->val.p, 8 * (size_t)r->nnz, hipMemcpyDeviceToDevice,
+                                             L->stream) != hipSuccess) ||
+                   hipStreamSynchronize(L->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            c->broken = true;
+            st = ATP_EDEVICE;
+        }
+    }
+    if (r) (void)atp_result_free(r);  // its arrays are workspace blocks: nothing is released
+    c->flags = saved_flags;
+    {
+        std::lock_guard<std::recursive_mutex> g(L->pool.mu);
+        L->pool.arena = nullptr;
+        L->pool.arena_size = L->pool.arena_used = 0;
+    }
+    return st;
 }
 
 atp_status atp_result_csr(const atp_result *r, int64_t *n_rows, int64_t *n_cols, int64_t *nnz,

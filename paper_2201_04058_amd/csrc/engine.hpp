@@ -83,6 +83,13 @@ struct Pool {
     std::recursive_mutex mu;  // lanes release each other's buffers (cache eviction, results)
     size_t cached = 0;                // bytes of free blocks in `cache`
     size_t cache_limit = (size_t)16 << 30;
+    // Arena mode (atp_eval_noalloc): allocations are carved in order out of a
+    // fixed device region (the library's static workspace); nothing is
+    // obtained from or returned to the runtime, releases of arena blocks are
+    // ignored (they are not in `live`), and running past the region's end
+    // fails with ATP_EBUDGET.
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
     int64_t n_malloc = 0, n_free = 0;  // runtime allocations and frees (diagnostics)
     double malloc_s = 0, free_s = 0;
 
@@ -108,12 +115,22 @@ struct Pool {
     }
     std::function<void()> on_oom;  // frees the cached blocks of every pool of the context
     atp_status alloc(size_t bytes, void **out) {
+        if (arena) return alloc_arena(bytes, out);
         atp_status st = alloc_once(bytes, out);
         if (st == ATP_ENOMEM && on_oom) {  // other lanes may hold the memory in their caches
             on_oom();
             st = alloc_once(bytes, out);
         }
         return st;
+    }
+    atp_status alloc_arena(size_t bytes, void **out) {
+        std::lock_guard<std::recursive_mutex> g(mu);
+        *out = nullptr;
+        const size_t n = ((bytes ? bytes : 1) + 255) / 256 * 256;
+        if (n > arena_size - arena_used) return ATP_EBUDGET;
+        *out = arena + arena_used;
+        arena_used += n;
+        return ATP_OK;
     }
     atp_status alloc_once(size_t bytes, void **out) {
         std::lock_guard<std::recursive_mutex> g(mu);
@@ -175,7 +192,7 @@ struct Pool {
         cache.emplace(n, p);
         cached += n;
         // keep at most cache_limit bytes of free blocks: drop the largest first
-        while (cached > cache_limit && !cache.empty()) {
+        while (!arena && cached > cache_limit && !cache.empty()) {
             auto last = std::prev(cache.end());
             (void)hipFree(last->second);
             held -= (int64_t)last->first;
@@ -458,6 +475,7 @@ struct atp_ctx {
     int64_t chunk_hist_cap = std::getenv("ATP_CHUNK_HIST_CAP") ? std::atoll(std::getenv("ATP_CHUNK_HIST_CAP"))
                                                                : atp::kChunkHistCap;
     atp::Server *server = nullptr;  // owned; created and destroyed by serve.cpp
+    void *scratch = nullptr;        // this device's copy of the static workspace (atp_eval_noalloc)
     // longest host wait for values a lane's kernels post (ATP_WAIT_LIMIT_S, seconds): a stream that
     // neither finishes nor fails within it is treated as a device error
     double wait_limit_s = std::getenv("ATP_WAIT_LIMIT_S") ? std::atof(std::getenv("ATP_WAIT_LIMIT_S")) : 600.0;
