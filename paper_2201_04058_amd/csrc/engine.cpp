@@ -970,10 +970,12 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     CacheState &cs = c->cache;
     std::unique_lock<std::mutex> cache_lock(cs.mu);
     const bool caching = use_cache && cs.policy != ATP_CACHE_OFF && p >= 2;
+    const int32_t cache_policy = cs.policy;
     std::vector<std::string> pkeys;
     std::vector<std::vector<int64_t>> cached_item(p, std::vector<int64_t>(p, -1));
     std::map<int64_t, PayloadRef> pins;  // cached results this query may read
     std::vector<std::vector<int64_t>> freq(p, std::vector<int64_t>(p, 0));  // Overlap Tree f of each sub-chain
+    std::vector<std::vector<char>> overlap(p, std::vector<char>(p, 0));    // its string is an internal node
     std::vector<ChainStats> cached_stats_store(p * p);
     std::vector<std::vector<const ChainStats *>> cached_stats(p, std::vector<const ChainStats *>(p, nullptr));
     auto sub_types = [&](int a, int b) { return std::vector<int32_t>(types + a, types + b + 2); };
@@ -992,6 +994,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
                 const int node = cs.tree->find(st_);
                 if (node >= 0) cs.tree->node(node).keys[key].f += weight;
                 freq[a][b] = cs.tree->frequency(st_);
+                overlap[a][b] = node >= 0 && !cs.tree->node(node).leaf();
                 auto it = cs.item_by_key.find(key);
                 if (it == cs.item_by_key.end()) continue;
                 if (node >= 0) cs.tree->node(node).keys[key].item = it->second;
@@ -1098,7 +1101,16 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     // intermediates whose sizes stay on the device (no read-back per product):
     // not the result, not kept by the cache, not timed or byte-counted, and not
     // a left operand whose size decides a restriction
-    const bool may_defer = !caching && !(c->flags & ATP_OPT_COUNT_BYTES) && !c->cost_sink;
+    // with a cache, only the products its insertion policy may keep need exact
+    // sizes: the result, and sub-chains computed on all their rows that CBS2
+    // keeps (every one) or the Overlap-Tree policies keep (overlaps)
+    const bool may_defer = !(c->flags & ATP_OPT_COUNT_BYTES) && !c->cost_sink;
+    auto cache_candidate = [&](int lo_, int hi_, bool partial) -> bool {
+        if (!caching || partial) return false;
+        if (cache_policy == ATP_CACHE_CBS2) return true;
+        if (cache_policy == ATP_CACHE_CBS1) return false;
+        return overlap[lo_][hi_] != 0;
+    };
     Buf nnz_acc;
     if (may_defer && p >= 3) {  // nonzeros and fault flag of the deferred products
         TRY(nnz_acc.alloc(&L->pool, 16));
@@ -1244,10 +1256,11 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
             HIPTRY(hipEventCreate(&rec.e1));
             HIPTRY(hipEventRecord(rec.e0, s));
         }
-        const bool defer = may_defer && v != forced_root && !feeds_restriction[v];
+        const bool defer_ok = may_defer && !cache_candidate(lo, hi, rs != nullptr);
+        const bool defer = defer_ok && v != forced_root && !feeds_restriction[v];
         // a left operand whose size decides its parent's restriction (size below half the rows
         // of the parent's right operand) can keep its size on the device when its bound decides
-        const int64_t defer_below = may_defer && v != forced_root && feeds_restriction[v]
+        const int64_t defer_below = defer_ok && v != forced_root && feeds_restriction[v]
                                         ? c->types[types[r1 + 1]].count / 2
                                         : 0;
         TRY(spgemm(c, L, X, Y, ycols_eff, as_left, outm, st, sat, defer, nnz_acc.as<int64_t>(), defer_below,
