@@ -42,7 +42,9 @@ def kernel_source_digest(kernel: str = "dense") -> str:
     with open(os.path.join(csrc, "kernels.hip")) as fh:
         text = fh.read()
     h = hashlib.sha256()
-    if kernel in KERNEL_SECTIONS:
+    if kernel == "all":  # every kernel: the whole file
+        h.update(text.encode())
+    elif kernel in KERNEL_SECTIONS:
         h.update(text[:text.index("// fills, scans")].encode())
         for a, b in KERNEL_SECTIONS[kernel]:
             h.update(text[text.index(a):text.index(b)].encode())
@@ -69,25 +71,41 @@ def traffic_for(kernel: str, workload: str, launches_per_step: float) -> float |
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(hin, queries, rows_per_query: int, threads: int) -> dict:
-    """The CPU oracle timed on a bounded sample: ``rows_per_query`` random start
-    rows of each query, scaled to whole queries (time x |S| / sample)."""
+def cpu_baseline(hin, queries, threads: int, seconds: float) -> dict:
+    """The CPU oracle as it stands (its plain left-to-right row chain, OpenMP
+    over start rows) timed on the host's cores on a bounded sample: for each
+    query a random subset of its start rows, grown by factors of four until it
+    takes about seconds / len(queries), timed, and scaled to the whole start
+    set (time x |S| / rows) -- an extrapolation, labelled as one."""
     import oracle
     oracle.build(force=False)
     rng = np.random.default_rng(1234)
-    est_total = 0.0
+    budget = seconds / max(1, len(queries))
+    est_total, per_query, rows_used, rows_all = 0.0, {}, 0, 0
     for q in queries:
         ids = [c for c in q.constraints if c.kind == "idset" and c.position == 0][0].ids
-        k = min(rows_per_query, len(ids))
-        rows = np.sort(rng.choice(ids, size=k, replace=False)).astype(np.int64)
-        t0 = time.perf_counter()
-        oracle.eval_rows(hin, q, rows, nthreads=threads)
-        dt = time.perf_counter() - t0
-        est_total += dt * len(ids) / k
-        log(f"cpu oracle {q.name}: {k} rows in {dt:.2f} s -> {dt * len(ids) / k:.1f} s per query")
+        k = min(threads, len(ids))
+        while True:
+            rows = np.sort(rng.choice(ids, size=k, replace=False)).astype(np.int64)
+            t0 = time.perf_counter()
+            oracle.eval_rows(hin, q, rows, nthreads=threads)
+            dt = time.perf_counter() - t0
+            if dt >= budget / 4 or k == len(ids):
+                break
+            k = min(len(ids), k * 4)
+        est = dt * len(ids) / k
+        est_total += est
+        rows_used += k
+        rows_all += len(ids)
+        per_query[q.name] = {"rows": k, "of": int(len(ids)), "s": round(dt, 3), "est_s_per_query": round(est, 3)}
+        log(f"cpu oracle {q.name}: {k} of {len(ids)} start rows in {dt:.2f} s on {threads} threads "
+            f"-> {est:.1f} s per query")
     return {"value": len(queries) / est_total, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows_per_query} random start rows per query of {len(queries)} "
-                      f"(of {len(ids)}), scaled by |start set| / sample"}
+            "extrapolated": rows_used < rows_all,
+            "sample": f"per query a random subset of its start rows ({rows_used} of {rows_all} over "
+                      f"{len(queries)} queries), timed on {threads} threads and scaled by |start set| / rows; "
+                      f"the oracle's left-to-right row chain",
+            "per_query": per_query}
 
 
 # session workloads: entity types that sessions start from, type-level predicates
@@ -232,9 +250,50 @@ def batch_mode(args) -> int:
     return 0 if not bad else 1
 
 
-def _serve(atp, ctx, arrivals, qs, lanes, max_batch, admit_bytes, cap_s):
+def _sampled_rows(r, q, rng, k: int = 12, max_nnz: int = 20_000_000):
+    """Up to k start rows of a result (non-empty ones first) with their
+    columns and counts, for an oracle check; None for a result too large to
+    copy to the host here."""
+    n_rows, _, nnz = r.shape()
+    if nnz > max_nnz:
+        return None
+    rp, col, val = r.to_host()
+    start = [c for c in q.constraints if c.kind == "idset" and c.position == 0]
+    ids = np.asarray(start[0].ids, np.int64) if start else np.arange(n_rows, dtype=np.int64)
+    lens = np.diff(rp)
+    ne = ids[lens[ids] > 0]
+    pick = list(rng.choice(ne, size=min(k - 2, len(ne)), replace=False)) + list(rng.choice(ids, size=min(2, len(ids)),
+                                                                                          replace=False))
+    rows = np.unique(np.asarray(pick, np.int64))
+    return {int(u): (col[rp[u]:rp[u + 1]].copy(), val[rp[u]:rp[u + 1]].copy()) for u in rows}
+
+
+def _oracle_check(hin, qs, samples) -> dict:
+    """Compare the sampled rows of served results with the CPU oracle."""
+    import oracle
+    oracle.build(force=False)
+    bad, rows_checked = [], 0
+    for z, got in samples.items():
+        if got is None:
+            continue
+        rows = np.array(sorted(got), np.int64)
+        rl, ocol, oval, st = oracle.eval_rows(hin, qs[z], rows, nthreads=max(1, min(len(os.sched_getaffinity(0)), 32)))
+        off = np.concatenate([[0], np.cumsum(rl)])
+        for i, u in enumerate(rows):
+            c, v = got[int(u)]
+            if not (np.array_equal(c, ocol[off[i]:off[i + 1]]) and np.array_equal(v, oval[off[i]:off[i + 1]].astype(np.int64))):
+                bad.append(int(z))
+                break
+        rows_checked += len(rows)
+    return {"queries_checked": sum(1 for g in samples.values() if g is not None),
+            "queries_too_large": sum(1 for g in samples.values() if g is None),
+            "rows_checked": rows_checked, "mismatches": len(bad), "mismatch_queries": bad[:8]}
+
+
+def _serve(atp, ctx, arrivals, qs, lanes, max_batch, admit_bytes, cap_s, check_every: int = 0):
     """Open-loop replay: submit each query at its arrival time, poll
-    completions; latency = completion - scheduled arrival."""
+    completions; latency = completion - scheduled arrival.  Every
+    check_every-th query's result is sampled for an oracle check."""
     import threading
     ctx.server_start(lanes=lanes, max_batch=max_batch, mem_budget_bytes=admit_bytes)
     n = len(qs)
@@ -255,11 +314,14 @@ def _serve(atp, ctx, arrivals, qs, lanes, max_batch, admit_bytes, cap_s):
     th = threading.Thread(target=feeder)
     th.start()
     next_log = time.perf_counter() + 10
+    samples, rng = {}, np.random.default_rng(99)
     while th.is_alive() or len(done) < submitted[0]:
         for cp in ctx.poll(256, wait_ms=50):
             r = cp["result"]
             done[cp["tag"]] = (cp["status"], r.shape()[2] if r is not None else -1, cp["t_done"], cp["batch"])
             if r is not None:
+                if check_every and cp["tag"] % check_every == 0:
+                    samples[cp["tag"]] = _sampled_rows(r, qs[cp["tag"]], rng)
                 r.free()
         if time.perf_counter() > next_log:
             log(f"  {len(done)} of {submitted[0]} submitted done")
@@ -276,7 +338,7 @@ def _serve(atp, ctx, arrivals, qs, lanes, max_batch, admit_bytes, cap_s):
             "errors": sum(1 for d in done.values() if d[0] != 0),
             "error_status": sorted({int(d[0]) for d in done.values() if d[0] != 0}),
             "error_queries": [qs[z].name for z in sorted(done) if done[z][0] != 0][:8],
-            "mean_batch": round(float(np.mean([d[3] for d in done.values()])), 3)}, done
+            "mean_batch": round(float(np.mean([d[3] for d in done.values()])), 3)}, done, samples
 
 
 def serve_mode(args) -> int:
@@ -303,7 +365,7 @@ def serve_mode(args) -> int:
     plain, dp = {"qps": 0.0, "p99_ms": None}, {}
     if not args.no_plain:
         log(f"plain path: {len(qs)} queries at {args.qps} QPS")
-        plain, dp = _serve(atp, ctx, arrivals, qs, 1, 1, 0, args.cap_s)
+        plain, dp, _ = _serve(atp, ctx, arrivals, qs, 1, 1, 0, args.cap_s)
         log(f"plain: {plain}")
     tuned = fitted = None
     if args.calibrate:  # Eq. 2 coefficients fitted on a stream of another seed
@@ -319,8 +381,8 @@ def serve_mode(args) -> int:
     if args.cache_gb > 0:
         ctx.cache_configure(atp.ATP_CACHE_OTREE, int(args.cache_gb * (1 << 30)))
     log(f"served: lanes {args.lanes}, max batch {args.max_batch}, cache {args.cache_gb} GB")
-    served, ds = _serve(atp, ctx, arrivals, qs, args.lanes, args.max_batch, int(args.admit_gb * (1 << 30)),
-                        args.cap_s)
+    served, ds, samples = _serve(atp, ctx, arrivals, qs, args.lanes, args.max_batch,
+                                 int(args.admit_gb * (1 << 30)), args.cap_s, check_every=args.check_every)
     st = ctx.cache_stats()
     served.update({"whole_hits": st["whole_hits"], "sub_hits": st["sub_hits"], "cache_queries": st["queries"],
                    "hit_rate": round((st["whole_hits"] + st["sub_hits"]) / max(1, st["queries"]), 3),
@@ -328,18 +390,21 @@ def serve_mode(args) -> int:
     log(f"served: {served}")
     ctx.close()
     bad = [z for z in ds if z in dp and ds[z][1] != dp[z][1]]
+    checked = _oracle_check(hin, qs, samples) if samples else None
+    log(f"oracle check of served results: {checked}")
     out = {"metric": "metapath queries/s + p50/p99 latency (served stream)", "value": served["qps"],
            "unit": "queries/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
            "config": {"workload": f"{args.workload}-{args.stream}-stream", "queries": len(qs), "arrival_qps": args.qps,
-                      "start_set": [args.start_min, args.start_max], "lanes": args.lanes,
+                      "start_set": [args.start_min, args.start_max] if args.stream == "walks" else 1,
+                      "lanes": args.lanes,
                       "max_batch": args.max_batch, "cache_gb": args.cache_gb, "admit_gb": args.admit_gb,
                       "pool": args.pool},
            "served": served, "plain": plain,
            "vs_plain_qps": round(served["qps"] / max(plain["qps"], 1e-9), 3),
            "vs_plain_p99": round(plain["p99_ms"] / max(served["p99_ms"], 1e-9), 3) if plain["p99_ms"] else None,
-           "result_mismatches": len(bad), "autotuned": tuned, "cost_model": fitted}
+           "result_mismatches": len(bad), "oracle_check": checked, "autotuned": tuned, "cost_model": fitted}
     print(json.dumps(out), flush=True)
-    return 0 if not bad else 1
+    return 0 if not bad and not (checked and checked["mismatches"]) else 1
 
 
 def costfit_mode(args) -> int:
@@ -399,80 +464,151 @@ def costfit_mode(args) -> int:
     return 0
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scholarly", choices=["scholarly", "news", "tiny"])
-    ap.add_argument("--cpu-rows", type=int, default=64)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-side-by-side", action="store_true",
-                    help="skip the second timed region (the step's queries side by side on four lanes)")
-    ap.add_argument("--plan-eac", action="store_true", help="paper's uniform E_ac planner")
-    ap.add_argument("--mode", default="plain", choices=["plain", "workload", "batch", "serve", "costfit"],
-                    help="plain: the workload's queries, one at a time; workload: a session query stream "
-                         "evaluated with each cache policy (Sec. 3.3-3.4) against the plain path; batch: random "
-                         "walks one at a time and as a batch; serve: an open-loop stream, plain path and server")
-    ap.add_argument("--lanes", type=int, default=4)
-    ap.add_argument("--max-batch", type=int, default=64)
-    ap.add_argument("--admit-gb", type=float, default=64.0, help="batch/serve: slot-memory admission budget")
-    ap.add_argument("--start-min", type=int, default=100)
-    ap.add_argument("--start-max", type=int, default=5000)
-    ap.add_argument("--qps", type=float, default=200.0, help="serve: arrival rate")
-    ap.add_argument("--cap-s", type=float, default=120.0, help="serve: stop submitting after this many seconds")
-    ap.add_argument("--pool", type=int, default=16, help="serve: start sets per type and windows in the pools")
-    ap.add_argument("--autotune", action="store_true", help="batch/serve: autotune the tunables first")
-    ap.add_argument("--calibrate", action="store_true", help="batch/serve: refit Eq. 2's coefficients first")
-    ap.add_argument("--tune-queries", type=int, default=24)
-    ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain-path run")
-    ap.add_argument("--batch-chunk", type=int, default=256, help="batch: queries per eval_batch call")
-    ap.add_argument("--stream", default="walks", choices=["walks", "sessions"],
-                    help="serve: extended schema walks with pooled constraints, or session queries")
-    ap.add_argument("--queries", type=int, default=500, help="workload/batch/serve: queries")
-    ap.add_argument("--cache-gb", type=float, default=4.0, help="workload/serve: cache budget")
-    ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="only run a device-to-device copy of this many MiB (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
-        return 2
+def _pmc_per_kernel(db: str) -> dict:
+    """kernel name -> (sum of the counter over its dispatches in KiB, dispatches)
+    from a rocprofv3 --pmc database holding one counter."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    agg = {}
+    for name, value, did in con.execute("select name, counter_value, dispatch_id from pmc_events"):
+        a = agg.setdefault(name, [0.0, set()])
+        a[0] += value
+        a[1].add(did)
+    con.close()
+    return {k: (v[0], len(v[1])) for k, v in agg.items()}
 
-    if args.copy_calibration:
-        import torch
-        n = args.copy_calibration << 20
-        a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
-        b = torch.empty_like(a)
-        a.fill_(1)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": n}), flush=True)
-        return 0
 
-    import paper_2201_04058_amd as atp
-    from synth import configs
+# kernels of the counting pass only (bench.py's untimed byte count), and the
+# runtime's copy kernels (network upload, small read-backs): not part of a step
+COUNTING_KERNELS = ("k_bin_stats", "k_mark_bytes")
 
-    if args.mode == "workload":
-        return workload_mode(args)
-    if args.mode == "batch":
-        return batch_mode(args)
-    if args.mode == "serve":
-        return serve_mode(args)
-    if args.mode == "costfit":
-        return costfit_mode(args)
 
+def counters_summary(args) -> int:
+    """profiles/traffic_dense_<w>.json (the dominant kernel) and
+    profiles/traffic_chain_<w>.json (every kernel of a step) from FETCH_SIZE /
+    WRITE_SIZE databases of `bench.py --workload <w> --steps 1 --warmup 0
+    --no-side-by-side --no-cpu-baseline --no-news` (each query evaluated in four
+    passes: shapes, byte count, serial profile, timed step) and of the copy
+    calibration, whose counters give the KiB-to-bytes scale."""
+    fdb, wdb, cfdb, cwdb = args.counters_summary
+    w = args.workload
+    copy_bytes = 1024 << 20
+
+    def copy_scale(db):
+        pk = _pmc_per_kernel(db)
+        name = max(pk, key=lambda k: pk[k][0] / pk[k][1])  # the 1 GiB copy dominates
+        per = pk[name][0] / pk[name][1]
+        return copy_bytes / (per * 1024.0), per
+
+    fscale, fcopy = copy_scale(cfdb)
+    wscale, wcopy = copy_scale(cwdb)
+    fk, wk = _pmc_per_kernel(fdb), _pmc_per_kernel(wdb)
+    passes = 4
+    rows, total = [], 0.0
+    for name in sorted(set(fk) | set(wk)):
+        if any(x in name for x in COUNTING_KERNELS) or name.startswith("__amd_rocclr"):
+            continue
+        f, nf = fk.get(name, (0.0, 0))
+        wv, nw = wk.get(name, (0.0, 0))
+        b = (f * fscale + wv * wscale) * 1024.0 / passes
+        total += b
+        rows.append((b, name, nf // passes, f / max(nf, 1), wv / max(nw, 1)))
+    rows.sort(reverse=True)
+    cmd = {"fetch": f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch_{w} -o run -- python3 bench.py --workload {w} "
+                    "--steps 1 --warmup 0 --no-side-by-side --no-cpu-baseline --no-news",
+           "write": f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write_{w} -o run -- python3 bench.py --workload {w} "
+                    "--steps 1 --warmup 0 --no-side-by-side --no-cpu-baseline --no-news",
+           "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_copy_fetch -o run -- python3 bench.py "
+                         "--copy-calibration 1024",
+           "copy_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_copy_write -o run -- python3 bench.py "
+                         "--copy-calibration 1024",
+           "summary": "python3 bench.py --workload W --counters-summary FETCH.db WRITE.db COPY_FETCH.db COPY_WRITE.db"}
+    calib = (f"a 1 GiB device-to-device copy: FETCH_SIZE {fcopy:.1f} KiB -> scale {fscale:.4f}, "
+             f"WRITE_SIZE {wcopy:.1f} KiB -> scale {wscale:.4f}")
+    chain = {"workload": w, "kernel_source": kernel_source_digest("all"), "bytes_per_step": round(total),
+             "passes": passes, "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+             "calibration": calib, "commands": cmd,
+             "per_kernel": [{"kernel": n, "bytes_per_step": round(b), "dispatches_per_step": d,
+                             "fetch_kib_per_dispatch": round(f, 1), "write_kib_per_dispatch": round(x, 1)}
+                            for b, n, d, f, x in rows]}
+    with open(os.path.join(ROOT, "profiles", f"traffic_chain_{w}.json"), "w") as fh:
+        json.dump(chain, fh, indent=1)
+    dn = [n for n in fk if "k_dense(" in n]
+    if dn:
+        f, nf = fk[dn[0]]
+        wv, nw = wk.get(dn[0], (0.0, 1))
+        dense = {"kernel": "dense", "workload": w, "kernel_source": kernel_source_digest("dense"),
+                 "fetch_kib_per_dispatch": round(f / nf, 1), "write_kib_per_dispatch": round(wv / nw, 1),
+                 "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4), "dispatches": nf,
+                 "bytes_per_launch": round((f / nf * fscale + wv / nw * wscale) * 1024.0),
+                 "calibration": calib, "commands": cmd}
+        with open(os.path.join(ROOT, "profiles", f"traffic_dense_{w}.json"), "w") as fh:
+            json.dump(dense, fh, indent=1)
+    lines = [f"# HBM traffic per step, workload {w} (rocprofv3 --pmc, one counter per run)",
+             f"# fetch: {cmd['fetch']}", f"# write: {cmd['write']}",
+             f"# copy calibration: {cmd['copy_fetch']} ; {cmd['copy_write']}",
+             f"{calib}", f"every kernel of a step (4 passes per run, counting kernels and runtime copies excluded): "
+             f"{total / 1e6:.1f} MB per step", "",
+             f"{'kernel':60s} {'disp/step':>9s} {'MB/step':>9s} {'fetch KiB/disp':>15s} {'write KiB/disp':>15s}"]
+    for b, n, d, f, x in rows[:16]:
+        lines.append(f"{n[:60]:60s} {d:9d} {b / 1e6:9.1f} {f:15.1f} {x:15.1f}")
+    with open(os.path.join(ROOT, "profiles", f"traffic_chain_{w}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines), flush=True)
+    return 0
+
+
+# numeric kernels whose algorithmic bytes make up a product's compulsory bytes
+# (operands read once, result written once); the compaction copy and the
+# scans are design overhead
+NUMERIC_KERNELS = ("hash_wave", "hash_block", "dense", "bucket")
+
+
+def host_info() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, the ones this process
+    may use, and the CPU model from lscpu (or /proc/cpuinfo)."""
+    import subprocess
+    info = {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in txt.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info["lscpu_" + k.strip().lower().replace("(s)", "s").replace(" ", "_")] = v.strip()
+    except Exception:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    info["model_name"] = ln.split(":", 1)[1].strip()
+                    break
+    return info
+
+
+def chain_traffic(workload: str) -> dict | None:
+    """Counter (FETCH_SIZE + WRITE_SIZE) bytes of every kernel of one step,
+    from the committed summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_chain_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("kernel_source") != kernel_source_digest("all"):
+        return None
+    return t
+
+
+def plain_record(atp, configs, args, workload: str, side_by_side: bool, cpu: bool) -> dict:
+    """One workload's queries evaluated one at a time: the JSON record."""
     t0 = time.perf_counter()
-    hin, queries = configs.load(args.workload)
-    log(f"workload {args.workload}: {len(queries)} queries, network ready in {time.perf_counter() - t0:.1f} s")
+    hin, queries = configs.load(workload)
+    log(f"workload {workload}: {len(queries)} queries, network ready in {time.perf_counter() - t0:.1f} s")
     stream = None
     try:
         import torch
         torch.cuda.init()
         stream = atp.torch_stream_handle(0)
     except Exception:
-        pass
+        torch = None
     ctx = atp.Context(device=0, stream=stream, plan_eac=args.plan_eac)
     ctx.load_hin(hin)
     log(f"network registered: {ctx.device_bytes() / 2**30:.2f} GiB on the device")
@@ -485,12 +621,16 @@ def main() -> int:
         r.free()
         log(f"  {q.name}: {plans[q.name]}")
 
-    # algorithmic bytes per kernel for one step (counting mode, untimed)
+    # algorithmic bytes per kernel, per query and per step (counting mode, untimed)
     ctx.set_flags(count_bytes=True, plan_eac=args.plan_eac)
-    ctx.kernel_times_reset()
+    bytes_per_step, comp_per_query = {}, {}
     for q in queries:
+        ctx.kernel_times_reset()
         ctx.eval_query(q).free()
-    bytes_per_step = {k: v[2] for k, v in ctx.kernel_times().items()}
+        kb = {k: v[2] for k, v in ctx.kernel_times().items()}
+        for k, v in kb.items():
+            bytes_per_step[k] = bytes_per_step.get(k, 0.0) + v
+        comp_per_query[q.name] = sum(kb.get(k, 0.0) for k in NUMERIC_KERNELS)
     ctx.set_flags(plan_eac=args.plan_eac)
 
     # dominant kernel: the most device time in one pass with a product's bins
@@ -532,6 +672,7 @@ def main() -> int:
     n_q = len(queries) * args.steps
     qps = n_q / elapsed
     lat_ms = np.array(lat) * 1e3
+    ms_per_step = elapsed / args.steps * 1e3
 
     # the same steps with each step's queries side by side on four lanes (the
     # engine's batch call; the queries differ, so nothing is fused); every
@@ -546,7 +687,7 @@ def main() -> int:
                 raise RuntimeError(f"{q.name}: {r.shape()[2]} nonzeros side by side, {plans[q.name]['nnz']} alone")
             r.free()
     conc_elapsed = None
-    if not args.no_side_by_side:
+    if side_by_side:
         for _ in range(max(1, args.warmup)):
             conc_step()
         if stream is not None:
@@ -562,13 +703,34 @@ def main() -> int:
     alg_bytes = bytes_per_step.get(dom, 0.0) * args.steps
     achieved = alg_bytes / (ms_total * 1e-3) / 1e9 if ms_total > 0 else 0.0
     launches_per_step = launches / args.steps
-    traffic = traffic_for(dom, args.workload, launches_per_step)
+    traffic = traffic_for(dom, workload, launches_per_step)
     # per kernel, from the serialised pass (one step): device ms, launches, algorithmic GB/s
     per_kernel = {k: {"serial_ms_per_step": round(v[0], 4), "launches_per_step": v[1],
                       "alg_GBps": round(bytes_per_step.get(k, 0.0) / (v[0] * 1e-3) / 1e9, 1)
                       if v[0] > 0 and bytes_per_step.get(k) else None}
                   for k, v in sorted(serial.items(), key=lambda kv: -kv[1][0])}
     per_kernel[dom]["timed_ms_per_step"] = round(ms_total / args.steps, 4)
+
+    # the whole chain: compulsory bytes of every product (operands read once,
+    # result written once, restricted to the rows launched) over the query's
+    # time, and the counters' HBM bytes of every kernel of the step
+    comp_step = sum(comp_per_query.values())
+    med = {q.name: float(np.median(lat_ms[i::len(queries)])) for i, q in enumerate(queries)}
+    chain = {"compulsory_bytes_per_step": round(comp_step),
+             "compulsory_GBps": round(comp_step / (ms_per_step * 1e-3) / 1e9, 1),
+             "frac": round(comp_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "per_query": {q.name: {"compulsory_bytes": round(comp_per_query[q.name]),
+                                    "median_ms": round(med[q.name], 3),
+                                    "compulsory_GBps": round(comp_per_query[q.name] / (med[q.name] * 1e-3) / 1e9, 1)}
+                           for q in queries}}
+    ct = chain_traffic(workload)
+    if ct:
+        cb = ct["bytes_per_step"]
+        chain.update({"counter_bytes_per_step": round(cb), "counter_GBps": round(cb / (ms_per_step * 1e-3) / 1e9, 1),
+                      "counter_frac": round(cb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    else:
+        chain.update({"counter_bytes_per_step": None, "counter_GBps": None, "counter_frac": None})
+    start = [c for c in queries[0].constraints if c.kind == "idset" and c.position == 0]
 
     out = {
         "metric": "metapath queries/s",
@@ -577,22 +739,21 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": args.workload,
+        "config": {"workload": workload,
                    "queries": [q.name for q in queries],
-                   "start_set": int(len([c for c in queries[0].constraints if c.kind == "idset"][0].ids)),
+                   "start_set": int(len(start[0].ids)) if start else None,
                    "network": {t: int(n) for t, n in hin.counts.items()},
                    "edges": int(sum(r.nnz for r in hin.relations.values())),
                    "parallelism": "single-gpu"},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                        "p99": round(float(np.percentile(lat_ms, 99)), 3),
-                       "per_query_median": {q.name: round(float(np.median(lat_ms[i::len(queries)])), 3)
-                                            for i, q in enumerate(queries)}},
+                       "per_query_median": {k: round(v, 3) for k, v in med.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
@@ -603,8 +764,10 @@ def main() -> int:
                      if traffic and launches else None,
                      "traffic_frac": round(traffic / (ms_total / launches * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                      if traffic and launches else None},
+        "chain": chain,
         "kernels": per_kernel,
         "serial_kernel_ms_per_step": round(sum(v[0] for v in serial.values()), 3),
+        "launches_per_query": round(sum(v[1] for v in serial.values()) / len(queries), 1),
         "plans": {k: v["plan"] for k, v in plans.items()},
         "n_op_per_step": int(sum(v["n_op"] for v in plans.values())),
         "products_per_s": round(sum(v["n_op"] for v in plans.values()) / (elapsed / args.steps), 1),
@@ -613,11 +776,107 @@ def main() -> int:
         "side_by_side": {"lanes": conc_lanes, "queries_per_s": round(n_q / conc_elapsed, 3),
                          "ms_per_step": round(conc_elapsed / args.steps * 1e3, 3)} if conc_elapsed else None,
     }
-    if not args.no_cpu_baseline:
-        threads = len(os.sched_getaffinity(0))
-        threads = min(threads, 16)
-        out["cpu_baseline"] = cpu_baseline(hin, queries, args.cpu_rows, threads)
     ctx.close()
+    if cpu:
+        threads = max(1, min(len(os.sched_getaffinity(0)), 64))
+        out["cpu_baseline"] = cpu_baseline(hin, queries, threads, args.cpu_seconds)
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="scholarly", choices=["scholarly", "news", "tiny"])
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU oracle baseline: about this many seconds of sampled work per workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-news", action="store_true", help="scholarly: skip the news sub-record")
+    ap.add_argument("--counters-summary", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write profiles/traffic_*_<workload>.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
+                         "databases of `bench.py --steps 1 --warmup 0 --no-side-by-side --no-cpu-baseline "
+                         "--no-news` and of `bench.py --copy-calibration 1024`")
+    ap.add_argument("--no-side-by-side", action="store_true",
+                    help="skip the second timed region (the step's queries side by side on four lanes)")
+    ap.add_argument("--plan-eac", action="store_true", help="paper's uniform E_ac planner")
+    ap.add_argument("--mode", default="plain", choices=["plain", "workload", "batch", "serve", "costfit"],
+                    help="plain: the workload's queries, one at a time; workload: a session query stream "
+                         "evaluated with each cache policy (Sec. 3.3-3.4) against the plain path; batch: random "
+                         "walks one at a time and as a batch; serve: an open-loop stream, plain path and server")
+    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--admit-gb", type=float, default=64.0, help="batch/serve: slot-memory admission budget")
+    ap.add_argument("--start-min", type=int, default=100)
+    ap.add_argument("--start-max", type=int, default=5000)
+    ap.add_argument("--qps", type=float, default=200.0, help="serve: arrival rate")
+    ap.add_argument("--cap-s", type=float, default=120.0, help="serve: stop submitting after this many seconds")
+    ap.add_argument("--pool", type=int, default=16, help="serve: start sets per type and windows in the pools")
+    ap.add_argument("--autotune", action="store_true", help="batch/serve: autotune the tunables first")
+    ap.add_argument("--calibrate", action="store_true", help="batch/serve: refit Eq. 2's coefficients first")
+    ap.add_argument("--tune-queries", type=int, default=24)
+    ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain-path run")
+    ap.add_argument("--check-every", type=int, default=10,
+                    help="serve: sample rows of every n-th served result and compare them with the CPU oracle")
+    ap.add_argument("--batch-chunk", type=int, default=256, help="batch: queries per eval_batch call")
+    ap.add_argument("--stream", default="walks", choices=["walks", "sessions"],
+                    help="serve: extended schema walks with pooled constraints, or session queries")
+    ap.add_argument("--queries", type=int, default=500, help="workload/batch/serve: queries")
+    ap.add_argument("--cache-gb", type=float, default=4.0, help="workload/serve: cache budget")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    if args.copy_calibration:
+        # three device-to-device copies of a known size through the HIP runtime
+        import ctypes
+        rt = ctypes.CDLL("libamdhip64.so.7")
+        rt.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+        rt.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
+        rt.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        rt.hipFree.argtypes = [ctypes.c_void_p]
+        n = args.copy_calibration << 20
+        a, b = ctypes.c_void_p(), ctypes.c_void_p()
+        if rt.hipMalloc(ctypes.byref(a), n) or rt.hipMalloc(ctypes.byref(b), n) or rt.hipMemset(a, 1, n):
+            raise RuntimeError("copy calibration: device allocation failed")
+        for _ in range(3):
+            if rt.hipMemcpy(b, a, n, 3):  # device to device
+                raise RuntimeError("copy calibration: copy failed")
+        rt.hipDeviceSynchronize()
+        rt.hipFree(a)
+        rt.hipFree(b)
+        print(json.dumps({"copy_bytes": n}), flush=True)
+        return 0
+
+    import paper_2201_04058_amd as atp
+    from synth import configs
+
+    if args.mode == "workload":
+        return workload_mode(args)
+    if args.mode == "batch":
+        return batch_mode(args)
+    if args.mode == "serve":
+        return serve_mode(args)
+    if args.mode == "costfit":
+        return costfit_mode(args)
+
+    if args.counters_summary:
+        return counters_summary(args)
+
+    out = plain_record(atp, configs, args, args.workload, side_by_side=not args.no_side_by_side,
+                       cpu=not args.no_cpu_baseline)
+    if args.workload == "scholarly" and not args.no_news:
+        # the news workload (its own network and queries), measured the same way
+        news = plain_record(atp, configs, args, "news", side_by_side=False, cpu=not args.no_cpu_baseline)
+        out["news"] = {k: news[k] for k in ("metric", "value", "unit", "ms_per_step", "config", "latency_ms",
+                                            "roofline", "chain", "plans", "n_op_per_step", "products_per_s",
+                                            "nnz_result_per_step", "launches_per_query", "cpu_baseline")
+                       if k in news}
+    out["host"] = host_info()
     print(json.dumps(out), flush=True)
     return 0
 
