@@ -36,7 +36,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "_liboracle.so")
+# ATP_ORACLE_LIBRARY names another build of oracle.c (the sanitizer build)
+_LIB = os.environ.get("ATP_ORACLE_LIBRARY") or os.path.join(_HERE, "_liboracle.so")
 
 ORC_OK, ORC_OVERFLOW, ORC_RANGE, ORC_NOMEM = 0, 1, 2, 3
 SAT63 = 1 << 63
@@ -44,12 +45,24 @@ SAT63 = 1 << 63
 
 def build(force: bool = True) -> str:
     """Compile oracle.c with gcc (plain C, OpenMP for the row loop)."""
+    if os.environ.get("ATP_ORACLE_LIBRARY"):
+        return _LIB  # a build made elsewhere (build_sanitized)
     if force or not os.path.exists(_LIB):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC",
                                _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_sanitized(out: str, clang: str = "/opt/rocm/llvm/bin/clang") -> str:
+    """oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer (clang,
+    the runtime of the library's sanitizer build; no OpenMP: one thread)."""
+    tmp = out + f".tmp{os.getpid()}"
+    subprocess.check_call([clang, "-O1", "-g", "-std=c11", "-shared", "-fPIC", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", _SRC, "-o", tmp])
+    os.replace(tmp, out)
+    return out
 
 
 class _Result(ctypes.Structure):

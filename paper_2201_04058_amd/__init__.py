@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libatrapos.so")
+# ATP_LIBRARY names another build of the same library (the sanitizer build of
+# build.py --sanitize); there is no fallback implementation
+LIB_PATH = os.environ.get("ATP_LIBRARY") or os.path.join(_HERE, "libatrapos.so")
 
 ATP_OK, ATP_EINVAL, ATP_ENOMEM, ATP_EOVERFLOW, ATP_ESCHEMA, ATP_EDEVICE, ATP_EBUDGET, ATP_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7

@@ -20,10 +20,30 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# host code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+# (device code is not: GPU sanitizers are not used); load it with the clang
+# ASan runtime preloaded, see sanitizer_env()
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-g"]
+LLVM = os.environ.get("ATP_LLVM", "/opt/rocm/llvm")
+
+
+def asan_runtime() -> str:
+    """The clang ASan runtime that a sanitizer build expects to be preloaded."""
+    import glob
+    libs = sorted(glob.glob(os.path.join(LLVM, "lib", "clang", "*", "lib", "linux", "libclang_rt.asan-x86_64.so")))
+    if not libs:
+        raise RuntimeError("clang ASan runtime not found under " + LLVM)
+    return libs[-1]
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str | None = None) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, "-x", "hip", *srcs, "-o", tmp]
+    lib = out or (os.path.join(HERE, "_san", "libatrapos.so") if sanitize else LIB)
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    tmp = lib + f".tmp{os.getpid()}"
+    cmd = [HIPCC, *FLAGS, *(SAN_FLAGS if sanitize else []), "-x", "hip", *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -35,10 +55,12 @@ def build(verbose: bool = False) -> str:
         lines = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln]
         if lines:
             sys.stderr.write("\n".join(lines) + "\n")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
-    print(LIB)
+    san = "--sanitize" in sys.argv[1:]
+    print(build(verbose=True, sanitize=san))
+    if san:
+        print("load with LD_PRELOAD=" + asan_runtime() + " ATP_LIBRARY=<the path above>")
