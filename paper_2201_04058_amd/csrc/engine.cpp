@@ -735,29 +735,29 @@ int64_t admit_item(CacheState &cs, const std::string &key, const std::vector<int
     return ok ? id : -1;
 }
 
-// Store a copy of a CSR result as item id's payload (the caller holds cs.mu).
-atp_status store_copy(CacheState &cs, Lane *L, int64_t id, int64_t rows, int64_t cols, int64_t nnz, const void *rp,
-                      const void *col, const void *val) {
-    hipStream_t s = L->stream;
+// Keep the arrays of a computed CSR result as item id's payload: they move
+// into the cache (no copy); a result handed to the caller shares them
+// (the caller holds cs.mu).
+PayloadRef store_moved(CacheState &cs, Lane *L, int64_t id, int64_t rows, int64_t cols, int64_t nnz, Buf &rp,
+                       Buf &col, Buf &val, atp_status &st) {
     auto P = std::make_shared<CachePayload>();
     P->rows = rows;
     P->cols = cols;
     P->nnz = nnz;
     P->bytes = cs.pol->item(id).size;
-    TRY(P->rp.alloc(&L->pool, 8 * (size_t)(rows + 1)));
-    TRY(P->col.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(nnz, 1)));
-    TRY(P->val.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(nnz, 1)));
-    HIPTRY(hipMemcpyAsync(P->rp.p, rp, 8 * (rows + 1), hipMemcpyDeviceToDevice, s));
-    if (nnz) {
-        HIPTRY(hipMemcpyAsync(P->col.p, col, 4 * nnz, hipMemcpyDeviceToDevice, s));
-        HIPTRY(hipMemcpyAsync(P->val.p, val, 8 * nnz, hipMemcpyDeviceToDevice, s));
-    }
+    P->rp = std::move(rp);
+    P->col = std::move(col);
+    P->val = std::move(val);
     P->n_active = -1;
-    HIPTRY(hipEventCreateWithFlags(&P->ready, hipEventDisableTiming));
-    HIPTRY(hipEventRecord(P->ready, s));
-    cs.payload[id] = std::move(P);
+    st = ATP_OK;
+    if (hipEventCreateWithFlags(&P->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(P->ready, L->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        st = ATP_EDEVICE;
+    }
+    cs.payload[id] = P;
     cs.stats.inserts += 1;
-    return ATP_OK;
+    return P;
 }
 
 // Cache insertion after a query (Sec. 3.4.1): record the hits on cached
@@ -765,9 +765,9 @@ atp_status store_copy(CacheState &cs, Lane *L, int64_t id, int64_t rows, int64_t
 // and, for the Overlap-Tree policies, the longest computed sub-metapath whose
 // string is an overlap (an internal Overlap-Tree node); CBS1 only the whole
 // query; CBS2 every computed product.  Replacement follows the policy.
-atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std::vector<KeptMat> &kept,
+atp_status cache_insert(atp_ctx *c, Lane *L, Mat &R, double root_cost, std::vector<KeptMat> &kept,
                         const std::vector<int64_t> &used, const int32_t *types, const std::vector<int> &rel,
-                        const std::vector<std::string> &pkeys, int p, int weight) {
+                        const std::vector<std::string> &pkeys, int p, int weight, PayloadRef *root_payload) {
     CacheState &cs = c->cache;  // the caller holds cs.mu
     hipStream_t s = L->stream;
     for (int64_t id : used)
@@ -783,7 +783,7 @@ atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std
         bool root;
     };
     std::vector<Cand> cands;
-    cands.push_back(Cand{0, p - 1, root_cost, const_cast<Mat *>(&R), true});
+    cands.push_back(Cand{0, p - 1, root_cost, &R, true});
     // a product holding a count of 2^63 or more is never kept: as a whole
     // query it must answer ATP_EOVERFLOW, which only a recomputation reports
     if (cs.policy == ATP_CACHE_CBS2) {
@@ -807,8 +807,10 @@ atp_status cache_insert(atp_ctx *c, Lane *L, const Mat &R, double root_cost, std
         const double bytes = 8.0 * (m.rows + 1) + 12.0 * m.nnz + (m.n_active >= 0 ? 4.0 * m.n_active : 0.0);
         const int64_t id = admit_item(cs, item_key(ty, rl, ps), ty, rl, ps, bytes, cd.cost);
         if (id < 0) continue;
-        if (cd.root) {  // the caller keeps R: copy it
-            TRY(store_copy(cs, L, id, m.rows, m.cols, m.nnz, m.rp.p, m.col.p, m.val.p));
+        if (cd.root) {  // the result the caller receives shares the kept arrays
+            atp_status st = ATP_OK;
+            *root_payload = store_moved(cs, L, id, m.rows, m.cols, m.nnz, cd.m->rp, cd.m->col, cd.m->val, st);
+            TRY(st);
             continue;
         }
         auto P = std::make_shared<CachePayload>();
@@ -1016,6 +1018,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     cache_lock.unlock();
 
     std::string plan_str;
+    double plan_cost = 0;                       // Eq. 2 estimate of the chosen plan (0 for a given plan)
     std::vector<std::vector<double>> span_nnz;  // planner estimate of every sub-chain (none for a given plan)
     // Eq. 1 over the leaves, with cached sub-chains at no cost when with_cache
     auto choose_plan = [&](bool with_cache) -> atp_status {
@@ -1042,6 +1045,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         PlanResult pr = plan_chain(lst, js, jsel, ch, csel, uniform ? Estimator::Uniform : Estimator::Sketch, cc,
                                    with_cache ? &cached_stats : nullptr);
         plan_str = pr.plan;
+        plan_cost = pr.cost;
         span_nnz = std::move(pr.span_nnz);
         return parse_plan(plan_str.c_str(), p, forced, forced_root) ? ATP_OK : ATP_ESTATE;
     };
@@ -1073,6 +1077,14 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         ident.nnz = n;
         ident.op = Operand{ident_rp.as<int64_t>(), ident_col.as<int32_t>(), nullptr, nullptr, nullptr, n, n, n};
     }
+
+    // several lanes at once: a heavy query (planned cost above heavy_ops products) runs alone,
+    // lighter ones overlap (a shared hold); concurrent heavy chains evict each other's operands
+    const bool multi = c->busy_lanes.load() > 1;
+    const bool heavy_query = multi && plan_cost > c->cost.beta * (double)c->heavy_ops;
+    std::unique_ptr<ProductHold> query_hold;
+    if (multi) query_hold.reset(new ProductHold(&c->queries, heavy_query));
+    if (heavy_query) c->heavy_alone += 1;
 
     StepStats st;
     int n_products = 0;
@@ -1234,11 +1246,14 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         const std::pair<int, int> ysp = span(nd.right);
         const bool fits =
             span_nnz.empty() || 12.0 * span_nnz[ysp.first][ysp.second] <= 0.8 * (double)cache_budget;
-        const bool keep_whole =
-            caching && whole_allowed && fits && ysp.second > ysp.first && freq[ysp.first][ysp.second] >= 2;
-        if (restrict_rows && x_small && !keep_whole && internal(nd.right)) {
+        const int64_t f_y = freq[ysp.first][ysp.second];
+        const bool whole_candidate = caching && whole_allowed && fits && ysp.second > ysp.first && f_y >= 2;
+        if (restrict_rows && x_small && internal(nd.right)) {
+            // computing the sub-chain whole costs about 1/share times its restricted form, where
+            // share is the part of its rows the left operand reaches; a string seen f times is
+            // expected back about f - 1 times, so the whole form is kept only when share * f >= 1
             TRY(make_restriction(X, y_rows, r2));
-            rp = &r2;
+            if (!(whole_candidate && (double)r2.n * (double)f_y >= (double)y_rows)) rp = &r2;
         }
         TRY(run(nd.right, false, rp, Y, r0, r1, cy));
         lo = l0;
@@ -1283,6 +1298,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         return ATP_OK;
     };
     Mat R;
+    PayloadRef result_payload;  // set when the result's arrays are (or become) a cached item's
     int lo = 0, hi = 0;
     atp_status stt;
     if (p == 1) {
@@ -1302,21 +1318,15 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         n_products = 1;
         overflow = sat;
     } else if (caching && tree[forced_root].block_lo == 0 && tree[forced_root].block_hi == p - 1) {
-        // the whole query is cached: hand out a copy
+        // the whole query is cached: the result shares the item's arrays (read-only, kept alive by
+        // the result even if the item is evicted)
         const int64_t id = cached_item[0][p - 1];
-        const CachePayload &P = *pins.at(id);
+        result_payload = pins.at(id);
+        const CachePayload &P = *result_payload;
         R.rows = P.rows;
         R.cols = P.cols;
         R.nnz = P.nnz;
         stt = hipStreamWaitEvent(s, P.ready, 0) == hipSuccess ? ATP_OK : ATP_EDEVICE;
-        if (stt == ATP_OK && (stt = R.rp.alloc(&L->pool, 8 * (size_t)(P.rows + 1))) == ATP_OK &&
-            (stt = R.col.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK &&
-            (stt = R.val.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(P.nnz, 1))) == ATP_OK) {
-            if (hipMemcpyAsync(R.rp.p, P.rp.p, 8 * (P.rows + 1), hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                (P.nnz && hipMemcpyAsync(R.col.p, P.col.p, 4 * P.nnz, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
-                (P.nnz && hipMemcpyAsync(R.val.p, P.val.p, 8 * P.nnz, hipMemcpyDeviceToDevice, s) != hipSuccess))
-                stt = ATP_EDEVICE;
-        }
         std::lock_guard<std::mutex> g(cs.mu);
         for (int w = 0; w < weight; ++w) {
             std::vector<int64_t> ev;
@@ -1350,7 +1360,8 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         if (stt == ATP_OK && caching && !overflow) {
             std::lock_guard<std::mutex> g(cs.mu);
             if (cs.pol)  // the cache may have been switched off meanwhile
-                stt = cache_insert(c, L, R, root_cost, kept, used_items, types, rel, pkeys, p, weight);
+                stt = cache_insert(c, L, R, root_cost, kept, used_items, types, rel, pkeys, p, weight,
+                                   &result_payload);
         }
     }
     if (stt != ATP_OK) {
@@ -1385,9 +1396,13 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     res->rows = R.rows;
     res->cols = R.cols;
     res->nnz = R.nnz;
-    res->rp = std::move(R.rp);
-    res->col = std::move(R.col);
-    res->val = std::move(R.val);
+    if (result_payload) {
+        res->shared = std::move(result_payload);
+    } else {
+        res->rp = std::move(R.rp);
+        res->col = std::move(R.col);
+        res->val = std::move(R.val);
+    }
     res->plan = plan_str;
     res->stats.n_products = n_products;
     res->stats.n_op_total = st.n_op;
@@ -1444,7 +1459,7 @@ bool cache_has_whole(atp_ctx *c, const QueryRef &q) {
     return it != cs.item_by_key.end() && cs.payload.count(it->second) > 0;
 }
 
-atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, const atp_result &r, double cost_s) {
+atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, atp_result &r, double cost_s) {
     std::vector<int32_t> ty, rl;
     std::vector<std::string> ps;
     const std::string key = whole_key(c, q, ty, rl, ps);
@@ -1457,12 +1472,17 @@ atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, const atp_r
     const double bytes = 8.0 * (r.rows + 1) + 12.0 * r.nnz;
     const int64_t id = admit_item(cs, key, ty, rl, ps, bytes, cost_s);
     if (id < 0) return ATP_OK;
-    return store_copy(cs, L, id, r.rows, r.cols, r.nnz, r.rp.p, r.col.p, r.val.p);
+    if (r.shared) return ATP_OK;  // already an item's arrays
+    atp_status st = ATP_OK;
+    r.shared = store_moved(cs, L, id, r.rows, r.cols, r.nnz, r.rp, r.col, r.val, st);
+    return st;
 }
 
 atp_status lane_init(atp_ctx *c, Lane *L, int id) {
     L->id = id;
     L->wait_limit_s = c->wait_limit_s;
+    // each lane has its own pool: a block it frees is reused only by later work on its own stream,
+    // which is ordered after the work that used the block
     L->pool.on_oom = [c]() { release_pool_caches(c); };
     L->pool.budget = c->main.pool.budget;
     L->pool.user_alloc = c->main.pool.user_alloc;
@@ -1616,6 +1636,7 @@ atp_status atp_destroy(atp_ctx *c) {
     (void)hipSetDevice(c->device);
     server_shutdown(c);
     if (std::getenv("ATP_POOL_STATS")) {  // diagnostics: runtime allocations per lane
+        std::fprintf(stderr, "queries that ran alone across lanes: %lld\n", (long long)c->heavy_alone.load());
         std::fprintf(stderr, "pool main: %lld mallocs %.3f s, %lld frees %.3f s, held %.2f GB\n",
                      (long long)c->main.pool.n_malloc, c->main.pool.malloc_s, (long long)c->main.pool.n_free,
                      c->main.pool.free_s, c->main.pool.held / 1e9);
@@ -1773,11 +1794,12 @@ atp_status atp_eval_noalloc(atp_ctx *c, const int32_t *types, int32_t n_types, c
         *nnz = r->nnz;
         if (r->nnz > cap) {
             st = ATP_EINVAL;
-        } else if (hipMemcpyAsync(row_ptr, r->rp.p, 8 * (size_t)(r->rows + 1), hipMemcpyDeviceToDevice, L->stream) !=
+        } else if (hipMemcpyAsync(row_ptr, r->rp_ptr(), 8 * (size_t)(r->rows + 1), hipMemcpyDeviceToDevice,
+                                  L->stream) !=
                        hipSuccess ||
-                   (r->nnz && hipMemcpyAsync(col, r->col.p, 4 * (size_t)r->nnz, hipMemcpyDeviceToDevice,
+                   (r->nnz && hipMemcpyAsync(col, r->col_ptr(), 4 * (size_t)r->nnz, hipMemcpyDeviceToDevice,
                                              L->stream) != hipSuccess) ||
-                   (r->nnz && hipMemcpyAsync(val, r->val.p, 8 * (size_t)r->nnz, hipMemcpyDeviceToDevice,
+                   (r->nnz && hipMemcpyAsync(val, r->val_ptr(), 8 * (size_t)r->nnz, hipMemcpyDeviceToDevice,
                                              L->stream) != hipSuccess) ||
                    hipStreamSynchronize(L->stream) != hipSuccess) {
             (void)hipGetLastError();
@@ -1801,18 +1823,18 @@ atp_status atp_result_csr(const atp_result *r, int64_t *n_rows, int64_t *n_cols,
     if (n_rows) *n_rows = r->rows;
     if (n_cols) *n_cols = r->cols;
     if (nnz) *nnz = r->nnz;
-    if (row_ptr) *row_ptr = r->rp.as<int64_t>();
-    if (col) *col = r->col.as<int32_t>();
-    if (val) *val = r->val.as<int64_t>();
+    if (row_ptr) *row_ptr = (const int64_t *)r->rp_ptr();
+    if (col) *col = (const int32_t *)r->col_ptr();
+    if (val) *val = (const int64_t *)r->val_ptr();
     return ATP_OK;
 }
 
 atp_status atp_result_to_host(const atp_result *r, int64_t *row_ptr, int32_t *col, int64_t *val) {
     if (!r) return ATP_EINVAL;
     hipStream_t s = r->stream;
-    if (row_ptr) HIPTRY(hipMemcpyAsync(row_ptr, r->rp.p, 8 * (r->rows + 1), hipMemcpyDeviceToHost, s));
-    if (col && r->nnz) HIPTRY(hipMemcpyAsync(col, r->col.p, 4 * r->nnz, hipMemcpyDeviceToHost, s));
-    if (val && r->nnz) HIPTRY(hipMemcpyAsync(val, r->val.p, 8 * r->nnz, hipMemcpyDeviceToHost, s));
+    if (row_ptr) HIPTRY(hipMemcpyAsync(row_ptr, r->rp_ptr(), 8 * (r->rows + 1), hipMemcpyDeviceToHost, s));
+    if (col && r->nnz) HIPTRY(hipMemcpyAsync(col, r->col_ptr(), 4 * r->nnz, hipMemcpyDeviceToHost, s));
+    if (val && r->nnz) HIPTRY(hipMemcpyAsync(val, r->val_ptr(), 8 * r->nnz, hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     return ATP_OK;
 }

@@ -82,7 +82,7 @@ struct Pool {
     std::map<void *, size_t> live;
     std::recursive_mutex mu;  // lanes release each other's buffers (cache eviction, results)
     size_t cached = 0;                // bytes of free blocks in `cache`
-    size_t cache_limit = (size_t)16 << 30;
+    size_t cache_limit = (size_t)32 << 30;  // an allocation that fails releases every pool's free blocks
     // Arena mode (atp_eval_noalloc): allocations are carved in order out of a
     // fixed device region (the library's static workspace); nothing is
     // obtained from or returned to the runtime, releases of arena blocks are
@@ -146,8 +146,11 @@ struct Pool {
             *out = p;
             return ATP_OK;
         }
+        // a free block of up to 1.25x the request is reused (2x for blocks of 64 MiB and more: a large
+        // runtime allocation costs milliseconds, and large requests vary from query to query)
         auto it = cache.lower_bound(n);
-        if (it != cache.end() && it->first <= n + n / 4) {
+        const size_t slack = n >= ((size_t)64 << 20) ? n : n / 4;
+        if (it != cache.end() && it->first <= n + slack) {
             void *p = it->second;
             size_t sz = it->first;
             cache.erase(it);
@@ -464,6 +467,9 @@ struct atp_ctx {
     atp::MemGate gate;
     atp::ProductGate products;     // a product above heavy_ops products runs alone across lanes
     int64_t heavy_ops = 64ll << 20;
+    // with several lanes busy, a query whose planned cost exceeds that of heavy_ops products
+    // runs alone (its products alternate with nothing else); lighter queries overlap
+    atp::ProductGate queries;
     int64_t tile_index_cap = std::getenv("ATP_TILE_INDEX_CAP") ? std::atoll(std::getenv("ATP_TILE_INDEX_CAP"))
                                                                : (int64_t)256 << 20;  // entries (4 B each)
     // the numeric bins of a product on the lane's side streams (ATP_SERIAL_BINS=1: all on one stream);
@@ -471,6 +477,7 @@ struct atp_ctx {
     // streams would outnumber the hardware queues)
     bool concurrent_bins = std::getenv("ATP_SERIAL_BINS") == nullptr;
     std::atomic<int> busy_lanes{0};  // lanes a batch or the server runs at once
+    std::atomic<int64_t> heavy_alone{0};  // queries that ran alone across lanes (diagnostics)
     // per-chunk tile counts of the bucket path kept up to this many entries (ATP_CHUNK_HIST_CAP)
     int64_t chunk_hist_cap = std::getenv("ATP_CHUNK_HIST_CAP") ? std::atoll(std::getenv("ATP_CHUNK_HIST_CAP"))
                                                                : atp::kChunkHistCap;
@@ -486,9 +493,13 @@ struct atp_result {
     atp_ctx *ctx;
     hipStream_t stream;  // the lane stream that produced it
     int64_t rows, cols, nnz;
-    atp::Buf rp, col, val;
+    atp::Buf rp, col, val;   // the arrays, unless `shared` holds them
+    atp::PayloadRef shared;  // arrays shared with a cached item (a result kept whole, or a whole hit)
     atp_eval_stats stats;
     std::string plan;
+    const void *rp_ptr() const { return shared ? shared->rp.p : rp.p; }
+    const void *col_ptr() const { return shared ? shared->col.p : col.p; }
+    const void *val_ptr() const { return shared ? shared->val.p : val.p; }
 };
 
 namespace atp {
@@ -511,7 +522,8 @@ void register_result(atp_ctx *c, atp_result *r);
 // workload cache, whole-query items (used by the batch layer): is q's result
 // cached; offer a result computed elsewhere (a fused batch member)
 bool cache_has_whole(atp_ctx *c, const QueryRef &q);
-atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, const atp_result &r, double cost_s);
+// (the result's arrays move into the cached item, which the result then shares)
+atp_status cache_offer_whole(atp_ctx *c, Lane *L, const QueryRef &q, atp_result &r, double cost_s);
 void release_pool_caches(atp_ctx *c);
 void server_shutdown(atp_ctx *c);
 

@@ -132,7 +132,7 @@ atp_status gather_member(atp_ctx *c, Lane *L, const atp_result &R, const Buf &d_
     KernelTimer *t = c->kt(L);
     TRY(out->rp.alloc(&L->pool, 8 * (size_t)(R.rows + 1)));
     launch_fill_i64(cnt.as<int64_t>(), R.rows, 0, s, t);
-    launch_gather_count(R.rp.as<int64_t>(), d_ids.as<int32_t>(), n_ids, cnt.as<int64_t>(), s, t);
+    launch_gather_count((const int64_t *)R.rp_ptr(), d_ids.as<int32_t>(), n_ids, cnt.as<int64_t>(), s, t);
     launch_scan_i64(cnt.as<int64_t>(), out->rp.as<int64_t>(), R.rows, tmp.as<int64_t>(), s, t, d_total);
     return ATP_OK;
 }
@@ -251,7 +251,8 @@ void run_fused(atp_ctx *c, Lane *L, std::vector<Member *> &g) {
             if ((e = o->col.alloc(&L->pool, 4 * (size_t)std::max<int64_t>(o->nnz, 1))) != ATP_OK ||
                 (e = o->val.alloc(&L->pool, 8 * (size_t)std::max<int64_t>(o->nnz, 1))) != ATP_OK)
                 break;
-            launch_gather_copy(R->rp.as<int64_t>(), R->col.as<int32_t>(), R->val.as<uint64_t>(), ids[z].as<int32_t>(),
+            launch_gather_copy((const int64_t *)R->rp_ptr(), (const int32_t *)R->col_ptr(),
+                               (const uint64_t *)R->val_ptr(), ids[z].as<int32_t>(),
                                (int64_t)g[z]->start.size(), o->rp.as<int64_t>(), o->col.as<int32_t>(),
                                o->val.as<uint64_t>(), s, t);
         }
