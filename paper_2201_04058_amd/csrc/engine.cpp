@@ -785,14 +785,18 @@ atp_status cache_insert(atp_ctx *c, Lane *L, Mat &R, double root_cost, std::vect
     std::vector<Cand> cands;
     cands.push_back(Cand{0, p - 1, root_cost, &R, true});
     // a product holding a count of 2^63 or more is never kept: as a whole
-    // query it must answer ATP_EOVERFLOW, which only a recomputation reports
+    // query it must answer ATP_EOVERFLOW, which only a recomputation reports;
+    // nor is one whose size stayed on the device (its arrays are sized by the
+    // symbolic bound: it was not a candidate when it was computed, though the
+    // Overlap Tree may have changed since, other lanes inserting queries)
+    auto keepable = [](const KeptMat &k) { return !k.partial && !k.m.saturated && !k.m.nnz_dev; };
     if (cs.policy == ATP_CACHE_CBS2) {
         for (auto &k : kept)
-            if (!k.partial && !k.m.saturated) cands.push_back(Cand{k.lo, k.hi, k.cost, &k.m, false});
+            if (keepable(k)) cands.push_back(Cand{k.lo, k.hi, k.cost, &k.m, false});
     } else if (cs.policy != ATP_CACHE_CBS1) {
         KeptMat *best = nullptr;
         for (auto &k : kept) {
-            if (k.partial || k.m.saturated) continue;
+            if (!keepable(k)) continue;
             const int node = cs.tree->find(std::vector<int32_t>(types + k.lo, types + k.hi + 2));
             if (node < 0 || cs.tree->node(node).leaf()) continue;
             if (!best || (k.hi - k.lo) > (best->hi - best->lo)) best = &k;
@@ -1018,7 +1022,6 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     cache_lock.unlock();
 
     std::string plan_str;
-    double plan_cost = 0;                       // Eq. 2 estimate of the chosen plan (0 for a given plan)
     std::vector<std::vector<double>> span_nnz;  // planner estimate of every sub-chain (none for a given plan)
     // Eq. 1 over the leaves, with cached sub-chains at no cost when with_cache
     auto choose_plan = [&](bool with_cache) -> atp_status {
@@ -1045,7 +1048,6 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         PlanResult pr = plan_chain(lst, js, jsel, ch, csel, uniform ? Estimator::Uniform : Estimator::Sketch, cc,
                                    with_cache ? &cached_stats : nullptr);
         plan_str = pr.plan;
-        plan_cost = pr.cost;
         span_nnz = std::move(pr.span_nnz);
         return parse_plan(plan_str.c_str(), p, forced, forced_root) ? ATP_OK : ATP_ESTATE;
     };
@@ -1078,13 +1080,6 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         ident.op = Operand{ident_rp.as<int64_t>(), ident_col.as<int32_t>(), nullptr, nullptr, nullptr, n, n, n};
     }
 
-    // several lanes at once: a heavy query (planned cost above heavy_ops products) runs alone,
-    // lighter ones overlap (a shared hold); concurrent heavy chains evict each other's operands
-    const bool multi = c->busy_lanes.load() > 1;
-    const bool heavy_query = multi && plan_cost > c->cost.beta * (double)c->heavy_ops;
-    std::unique_ptr<ProductHold> query_hold;
-    if (multi) query_hold.reset(new ProductHold(&c->queries, heavy_query));
-    if (heavy_query) c->heavy_alone += 1;
 
     StepStats st;
     int n_products = 0;
@@ -1636,7 +1631,6 @@ atp_status atp_destroy(atp_ctx *c) {
     (void)hipSetDevice(c->device);
     server_shutdown(c);
     if (std::getenv("ATP_POOL_STATS")) {  // diagnostics: runtime allocations per lane
-        std::fprintf(stderr, "queries that ran alone across lanes: %lld\n", (long long)c->heavy_alone.load());
         std::fprintf(stderr, "pool main: %lld mallocs %.3f s, %lld frees %.3f s, held %.2f GB\n",
                      (long long)c->main.pool.n_malloc, c->main.pool.malloc_s, (long long)c->main.pool.n_free,
                      c->main.pool.free_s, c->main.pool.held / 1e9);

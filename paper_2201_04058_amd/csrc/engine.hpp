@@ -467,9 +467,6 @@ struct atp_ctx {
     atp::MemGate gate;
     atp::ProductGate products;     // a product above heavy_ops products runs alone across lanes
     int64_t heavy_ops = 64ll << 20;
-    // with several lanes busy, a query whose planned cost exceeds that of heavy_ops products
-    // runs alone (its products alternate with nothing else); lighter queries overlap
-    atp::ProductGate queries;
     int64_t tile_index_cap = std::getenv("ATP_TILE_INDEX_CAP") ? std::atoll(std::getenv("ATP_TILE_INDEX_CAP"))
                                                                : (int64_t)256 << 20;  // entries (4 B each)
     // the numeric bins of a product on the lane's side streams (ATP_SERIAL_BINS=1: all on one stream);
@@ -477,7 +474,6 @@ struct atp_ctx {
     // streams would outnumber the hardware queues)
     bool concurrent_bins = std::getenv("ATP_SERIAL_BINS") == nullptr;
     std::atomic<int> busy_lanes{0};  // lanes a batch or the server runs at once
-    std::atomic<int64_t> heavy_alone{0};  // queries that ran alone across lanes (diagnostics)
     // per-chunk tile counts of the bucket path kept up to this many entries (ATP_CHUNK_HIST_CAP)
     int64_t chunk_hist_cap = std::getenv("ATP_CHUNK_HIST_CAP") ? std::atoll(std::getenv("ATP_CHUNK_HIST_CAP"))
                                                                : atp::kChunkHistCap;

@@ -388,14 +388,18 @@ struct Server {
 
 namespace {
 
-void worker(atp_ctx *c, Lane *L) {
+// Worker `rank` (0 = first lane) takes a request only while more than `rank`
+// requests are queued: at low load one lane serves everything (its products'
+// bins then run side by side on its side streams, and nothing else competes
+// for the device), and further lanes join as a backlog builds up.
+void worker(atp_ctx *c, Lane *L, int rank) {
     (void)hipSetDevice(c->device);
     Server &sv = *c->server;
     for (;;) {
         std::vector<std::unique_ptr<Request>> batch;
         {
             std::unique_lock<std::mutex> lk(sv.mu);
-            sv.cv_work.wait(lk, [&] { return sv.stopping || !sv.queue.empty(); });
+            sv.cv_work.wait(lk, [&] { return sv.stopping || (int)sv.queue.size() > rank; });
             if (sv.queue.empty()) return;  // stopping and drained
             batch.push_back(std::move(sv.queue.front()));
             sv.queue.pop_front();
@@ -410,11 +414,13 @@ void worker(atp_ctx *c, Lane *L) {
             }
             sv.running += (int)batch.size();
         }
+        c->busy_lanes += 1;  // lanes running a group now
         const double t_start = now_s(sv.t0);
         std::vector<Member *> g;
         for (auto &r : batch) g.push_back(&r->m);
         run_group_gated(c, L, g, sv.gate, sv.lanes);
         const double t_done = now_s(sv.t0);
+        c->busy_lanes -= 1;
         {
             std::lock_guard<std::mutex> lk(sv.mu);
             for (auto &r : batch) {
@@ -522,8 +528,8 @@ atp_status atp_server_start(atp_ctx *c, const atp_server_options *o) {
     c->server = new Server();
     c->server->max_batch = o->max_batch;
     c->server->lanes = o->lanes;
-    c->busy_lanes.store(o->lanes);
-    for (int l = 0; l < o->lanes; ++l) c->server->workers.emplace_back(worker, c, c->lanes[l].get());
+    c->busy_lanes.store(0);
+    for (int l = 0; l < o->lanes; ++l) c->server->workers.emplace_back(worker, c, c->lanes[l].get(), l);
     return ATP_OK;
 }
 
@@ -541,7 +547,7 @@ atp_status atp_submit(atp_ctx *c, const atp_query *q, uint64_t tag) {
         r->t_submit = now_s(sv.t0);
         sv.queue.push_back(std::move(r));
     }
-    sv.cv_work.notify_one();
+    sv.cv_work.notify_all();  // a longer queue may wake a further lane
     return ATP_OK;
 }
 
