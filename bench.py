@@ -520,13 +520,13 @@ def counters_summary(args) -> int:
         total += b
         rows.append((b, name, nf // passes, f / max(nf, 1), wv / max(nw, 1)))
     rows.sort(reverse=True)
-    cmd = {"fetch": f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch_{w} -o run -- python3 bench.py --workload {w} "
+    cmd = {"fetch": f"HSA_ENABLE_SDMA=0 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_FETCH_SIZE_{w} -o run -- python3 bench.py --workload {w} "
                     "--steps 1 --warmup 0 --no-side-by-side --no-cpu-baseline --no-news",
-           "write": f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write_{w} -o run -- python3 bench.py --workload {w} "
+           "write": f"HSA_ENABLE_SDMA=0 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_WRITE_SIZE_{w} -o run -- python3 bench.py --workload {w} "
                     "--steps 1 --warmup 0 --no-side-by-side --no-cpu-baseline --no-news",
-           "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_copy_fetch -o run -- python3 bench.py "
+           "copy_fetch": "HSA_ENABLE_SDMA=0 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_copy_FETCH_SIZE -o run -- python3 bench.py "
                          "--copy-calibration 1024",
-           "copy_write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_copy_write -o run -- python3 bench.py "
+           "copy_write": "HSA_ENABLE_SDMA=0 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_copy_WRITE_SIZE -o run -- python3 bench.py "
                          "--copy-calibration 1024",
            "summary": "python3 bench.py --workload W --counters-summary FETCH.db WRITE.db COPY_FETCH.db COPY_WRITE.db"}
     calib = (f"a 1 GiB device-to-device copy: FETCH_SIZE {fcopy:.1f} KiB -> scale {fscale:.4f}, "
@@ -550,6 +550,13 @@ def counters_summary(args) -> int:
                  "calibration": calib, "commands": cmd}
         with open(os.path.join(ROOT, "profiles", f"traffic_dense_{w}.json"), "w") as fh:
             json.dump(dense, fh, indent=1)
+        dl = [f"# HBM traffic of k_dense on workload {w} (rocprofv3 --pmc, one counter per run)",
+              f"# fetch: {cmd['fetch']}", f"# write: {cmd['write']}",
+              f"# copy calibration: {cmd['copy_fetch']} ; {cmd['copy_write']}", calib,
+              f"k_dense: {nf} dispatches, FETCH_SIZE {f / nf:.1f} KiB/dispatch, WRITE_SIZE {wv / nw:.1f} KiB/dispatch",
+              f"scaled HBM traffic per dispatch: {dense['bytes_per_launch'] / 1e6:.1f} MB"]
+        with open(os.path.join(ROOT, "profiles", f"traffic_dense_{w}.txt"), "w") as fh:
+            fh.write("\n".join(dl) + "\n")
     lines = [f"# HBM traffic per step, workload {w} (rocprofv3 --pmc, one counter per run)",
              f"# fetch: {cmd['fetch']}", f"# write: {cmd['write']}",
              f"# copy calibration: {cmd['copy_fetch']} ; {cmd['copy_write']}",
