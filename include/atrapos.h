@@ -321,8 +321,9 @@ atp_status atp_server_stop(atp_ctx *ctx);
  * kernel handles a row and how its work is split, never a result.
  *   part_target    expected products per part of a sparse row spanning several
  *                  column tiles (parts group consecutive tiles), >= 1
- *   part_hash_cap  a part with at most this many products uses an LDS hash
- *                  instead of a dense tile, 0..2048
+ *   part_hash_cap  a part with at most this many products is accumulated by
+ *                  column rank (a presence bitmap over its columns, then one
+ *                  value per present column) instead of in dense tiles, 0..4096
  *   task_ops       target products per dense task, >= 1
  *   bucket_pct     a row with more than 512 left entries whose entries x column
  *                  tiles x 100 exceed bucket_pct x its products is bucketed by

@@ -82,7 +82,7 @@ Tuning atp::tuning_from_env() {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         t.wg_slots = 2 * (int64_t)cus;
     (void)hipGetLastError();
-    if (t.part_hash_cap > 2048) t.part_hash_cap = 2048;  // the hash overlays one 8192-column tile
+    if (t.part_hash_cap > kRankCap) t.part_hash_cap = kRankCap;  // rank parts overlay one 8192-column tile
     if (t.part_target < 1) t.part_target = 1;
     if (t.task_ops < 1) t.task_ops = 1;
     return t;
@@ -980,7 +980,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     std::vector<std::string> pkeys;
     std::vector<std::vector<int64_t>> cached_item(p, std::vector<int64_t>(p, -1));
     std::map<int64_t, PayloadRef> pins;  // cached results this query may read
-    std::vector<std::vector<int64_t>> freq(p, std::vector<int64_t>(p, 0));  // Overlap Tree f of each sub-chain
+    std::vector<std::vector<int64_t>> kfreq(p, std::vector<int64_t>(p, 0));  // Overlap Tree f of each sub-chain's key
     std::vector<std::vector<char>> overlap(p, std::vector<char>(p, 0));    // its string is an internal node
     std::vector<ChainStats> cached_stats_store(p * p);
     std::vector<std::vector<const ChainStats *>> cached_stats(p, std::vector<const ChainStats *>(p, nullptr));
@@ -998,8 +998,10 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
                 const std::vector<int32_t> st_ = sub_types(a, b);
                 const std::string key = item_key(st_, sub_rels(a, b), sub_pos(a, b));
                 const int node = cs.tree->find(st_);
-                if (node >= 0) cs.tree->node(node).keys[key].f += weight;
-                freq[a][b] = cs.tree->frequency(st_);
+                if (node >= 0) {
+                    cs.tree->node(node).keys[key].f += weight;
+                    kfreq[a][b] = cs.tree->node(node).keys[key].f;
+                }
                 overlap[a][b] = node >= 0 && !cs.tree->node(node).leaf();
                 auto it = cs.item_by_key.find(key);
                 if (it == cs.item_by_key.end()) continue;
@@ -1174,6 +1176,7 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     } cost_recs;
     std::vector<int64_t> used_items;
     bool whole_allowed = true;
+    bool whole_taken = false;  // a sub-chain was computed on all its rows for the cache
     // post-order evaluation of node v into outm; rs restricts v's rows; cost =
     // seconds to compute it from the base relations in this query
     std::function<atp_status(int, bool, const Restriction *, Mat &, int &, int &, double &)> run =
@@ -1241,14 +1244,18 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
         const std::pair<int, int> ysp = span(nd.right);
         const bool fits =
             span_nnz.empty() || 12.0 * span_nnz[ysp.first][ysp.second] <= 0.8 * (double)cache_budget;
-        const int64_t f_y = freq[ysp.first][ysp.second];
+        const int64_t f_y = kfreq[ysp.first][ysp.second];
         const bool whole_candidate = caching && whole_allowed && fits && ysp.second > ysp.first && f_y >= 2;
         if (restrict_rows && x_small && internal(nd.right)) {
             // computing the sub-chain whole costs about 1/share times its restricted form, where
-            // share is the part of its rows the left operand reaches; a string seen f times is
-            // expected back about f - 1 times, so the whole form is kept only when share * f >= 1
+            // share is the part of its rows the left operand reaches; a sub-chain seen f times
+            // with the same constraints (its item key) is expected back about f - 1 times, so the
+            // whole form is kept only when share * f >= 1
             TRY(make_restriction(X, y_rows, r2));
-            if (!(whole_candidate && (double)r2.n * (double)f_y >= (double)y_rows)) rp = &r2;
+            if (!(whole_candidate && (double)r2.n * (double)f_y >= (double)y_rows))
+                rp = &r2;
+            else
+                whole_taken = true;
         }
         TRY(run(nd.right, false, rp, Y, r0, r1, cy));
         lo = l0;
@@ -1331,9 +1338,12 @@ atp_status eval_impl(atp_ctx *c, Lane *L, const int32_t *types, int32_t n_types,
     } else {
         double root_cost = 0;
         stt = run(forced_root, false, nullptr, R, lo, hi, root_cost);
-        if ((stt == ATP_ENOMEM || stt == ATP_EBUDGET) && caching) {
+        bool plan_blocks = false;  // the plan reads cached blocks
+        for (const PlanTree &nd : forced) plan_blocks |= nd.block_lo >= 0;
+        if ((stt == ATP_ENOMEM || stt == ATP_EBUDGET) && caching && (whole_taken || plan_blocks)) {
             // out of memory with the cache's choices (cached blocks in the plan, a sub-chain
-            // computed on all its rows to be kept): once more as without the cache
+            // computed on all its rows to be kept): once more as without the cache (a query
+            // that made neither choice would only fail the same way again)
             (void)hipStreamSynchronize(s);
             for (auto &r : cost_recs) {
                 if (r.e0) (void)hipEventDestroy(r.e0);
@@ -1997,7 +2007,7 @@ atp_status atp_get_tuning(const atp_ctx *c, atp_tuning *t) {
 
 atp_status atp_set_tuning(atp_ctx *c, const atp_tuning *t) {
     if (!c || !t) return ATP_EINVAL;
-    if (t->part_target < 1 || t->part_hash_cap < 0 || t->part_hash_cap > 2048 || t->task_ops < 1 ||
+    if (t->part_target < 1 || t->part_hash_cap < 0 || t->part_hash_cap > kRankCap || t->task_ops < 1 ||
         t->bucket_pct < 0 || t->split_ops < 1024 || t->bucket_chunk < 64)
         return ATP_EINVAL;
     c->tune.part_target = t->part_target;
@@ -2041,10 +2051,10 @@ atp_status atp_autotune(atp_ctx *c, const atp_query *sample, int32_t n, int32_t 
     };
     const std::vector<Knob> knobs = {
         {&Tuning::bucket_pct, {25, 50, 100, 200, 400, 800}},
-        {&Tuning::part_target, {300, 600, 1200, 2400}},
+        {&Tuning::part_target, {600, 1200, 2400, 3600}},
         {&Tuning::task_ops, {8192, 16384, 32768, 65536}},
         {&Tuning::split_ops, {16384, 65536, 262144}},
-        {&Tuning::part_hash_cap, {512, 1024, 2048}},
+        {&Tuning::part_hash_cap, {1024, 2048, 4096}},
         {&Tuning::bucket_chunk, {1024, 2048, 4096, 8192}},
     };
     double best = 0;

@@ -466,7 +466,8 @@ struct atp_ctx {
     atp::Tuning tune = atp::tuning_from_env();
     atp::MemGate gate;
     atp::ProductGate products;     // a product above heavy_ops products runs alone across lanes
-    int64_t heavy_ops = 64ll << 20;
+    // a product above this many products runs alone across lanes (ATP_HEAVY_OPS overrides it)
+    int64_t heavy_ops = std::getenv("ATP_HEAVY_OPS") ? std::atoll(std::getenv("ATP_HEAVY_OPS")) : 64ll << 20;
     int64_t tile_index_cap = std::getenv("ATP_TILE_INDEX_CAP") ? std::atoll(std::getenv("ATP_TILE_INDEX_CAP"))
                                                                : (int64_t)256 << 20;  // entries (4 B each)
     // the numeric bins of a product on the lane's side streams (ATP_SERIAL_BINS=1: all on one stream);

@@ -16,11 +16,13 @@ constexpr int kTileW = 1 << kTileShift;
 constexpr int kDenseThreads = 512;
 constexpr int kCursorCap = 512;     // X entries whose cursors fit in LDS (multi-tile chunks)
 constexpr int64_t kTaskOps = 8192;  // target products per dense task
-constexpr int64_t kPartTarget = 1200;  // expected products per part of a sparse long row
-constexpr int64_t kPartHashCap = 2048; // a part with at most this many products uses an LDS hash
+constexpr int64_t kPartTarget = 2400;  // expected products per part of a sparse long row
+constexpr int kRankCap = 4096;         // most products of a part accumulated by column rank
+constexpr int64_t kPartHashCap = kRankCap;  // a part with at most this many products is (default)
 constexpr int kPartMaxTiles = 16;      // ... if it spans at most this many tiles (its presence bitmap)
 constexpr int64_t kSplitOps = 65536;   // products per (row, tile) beyond which the row's entries are split
 constexpr int kMaxSplit = 64;
+constexpr int64_t kPartGroup = 4;      // most sparse parts handed out to one dense task
 constexpr int kQueues = 8;             // task counters of the dense kernel
 constexpr int kMaxBucketTiles = 4096;  // column tiles a bucketed row may span
 constexpr int kBucketThreads = 512;
@@ -140,7 +142,8 @@ struct SymbolicArgs {
     int64_t *scan_tmp;        // scan_tmp_elems(n_cand)
     int32_t *bin_lists;       // [BIN_COUNT * n_cand]
     int64_t *dense_chunks;    // [n_cand] tasks per dense candidate (indexed by dense list position)
-    int64_t *dense_split;     // [n_cand] split slot * 256 + split factor per dense candidate
+    int64_t *dense_split;     // [n_cand] per dense candidate: split slot * 256 + split factor (> 1), or
+                              // tiles per part << 16 | parts per task << 8 | 1
     int64_t *bucket_chunks;   // [n_cand] work items per bucket candidate (indexed by bucket list position)
     int64_t *bucket_nop;      // [n_cand] products per bucket candidate (indexed by bucket list position)
     StepHeader *hdr;
@@ -164,7 +167,7 @@ struct NumericArgs {
     int64_t *row_nnz;          // [X.rows] (zeroed)
     StepHeader *hdr;
     int64_t ycols;
-    const int64_t *dense_split;        // [n_dense] split slot * 256 + split factor
+    const int64_t *dense_split;        // [n_dense] as SymbolicArgs::dense_split
     unsigned long long *split_acc;     // [n_split * ntiles * kTileW] (zeroed)
     uint32_t *split_sat;               // [n_split * ntiles * kTileW / 32] (zeroed)
     int32_t *split_done;               // [n_split * ntiles] (zeroed)

@@ -541,21 +541,29 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(SymbolicArgs a) {
             }
             if (b == BIN_DENSE) {
                 int64_t nch = 1;
+                int64_t m = ntiles;  // tiles per part
+                int64_t grp = 1;     // parts per task
                 if (ntiles > 1) {
                     int64_t i = a.cand ? a.cand[c] : c;
                     int64_t xlen = a.X.rp[i + 1] - a.X.rp[i];
                     const int64_t per_tile = nop / ntiles;
-                    int64_t m = 1;  // tiles per part
+                    m = 1;
                     if (per_tile < a.tune.part_target) {
                         m = a.tune.part_target / (per_tile > 0 ? per_tile : 1);
                         m = m > kPartMaxTiles ? kPartMaxTiles : m;
+                        // small parts are handed out several to a task (the
+                        // row's set-up is paid once), while the step still
+                        // gives each resident workgroup several tasks
+                        grp = a.hdr->n_op_total / (a.tune.part_target * 4 * a.tune.wg_slots);
+                        grp = grp < 1 ? 1 : (grp > kPartGroup ? kPartGroup : grp);
                     } else if (xlen <= kCursorCap) {
                         int64_t chunks = (nop + a.tune.task_ops - 1) / a.tune.task_ops;
                         chunks = chunks < 1 ? 1 : chunks;
                         m = (ntiles + chunks - 1) / chunks;
                     }
                     m = m < 1 ? 1 : (m > ntiles ? ntiles : m);
-                    nch = (ntiles + m - 1) / m;
+                    const int64_t nparts = (ntiles + m - 1) / m;
+                    nch = (nparts + grp - 1) / grp;
                 }
                 // heavy rows: split the left entries over several workgroups per tile
                 int64_t ks = 1;
@@ -577,7 +585,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(SymbolicArgs a) {
                     const unsigned long long slot = atomicAdd((unsigned long long *)&a.hdr->n_split, 1ull);
                     a.dense_split[pos] = (int64_t)slot * 256 + ks;
                 } else {
-                    a.dense_split[pos] = 1;
+                    a.dense_split[pos] = (m << 16) | (grp << 8) | 1;
                 }
                 a.dense_chunks[pos] = nch;
             }
@@ -597,7 +605,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(SymbolicArgs a) {
 // the left / right operand carries values (else every value is 1).
 template <bool XV, bool YV, int NT, int U, typename F>
 __device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
-                                              int32_t tot, const uint64_t *xval, F f) {
+                                              int32_t tot, const uint64_t *xval, F f, int nb = NT) {
     constexpr int NWV = NT / 64;
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) & (NWV - 1);
     const int32_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~63;
@@ -606,7 +614,7 @@ __device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *s
     if (beg >= end) return;
     int32_t item = beg + lane;
     const int32_t first = item < end ? item : end - 1;
-    int lo = 0, hi = NT;  // last entry with seg_o <= first
+    int lo = 0, hi = nb;  // last entry with seg_o <= first (entries from nb on are empty)
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (seg_o[mid] <= first)
@@ -659,17 +667,17 @@ __device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *s
 // walk_products for whichever operands carry values
 template <int NT, int U = kProdUnroll, typename F>
 __device__ __forceinline__ void walk_products_any(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
-                                                  int32_t tot, const uint64_t *xval, F f) {
+                                                  int32_t tot, const uint64_t *xval, F f, int nb = NT) {
     if (xval) {
         if (Y.val)
-            walk_products<true, true, NT, U>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<true, true, NT, U>(Y, seg_o, seg_s, tot, xval, f, nb);
         else
-            walk_products<true, false, NT, U>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<true, false, NT, U>(Y, seg_o, seg_s, tot, xval, f, nb);
     } else {
         if (Y.val)
-            walk_products<false, true, NT, U>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<false, true, NT, U>(Y, seg_o, seg_s, tot, xval, f, nb);
         else
-            walk_products<false, false, NT, U>(Y, seg_o, seg_s, tot, xval, f);
+            walk_products<false, false, NT, U>(Y, seg_o, seg_s, tot, xval, f, nb);
     }
 }
 
@@ -773,7 +781,7 @@ __global__ __launch_bounds__(256) void k_hash_wave(const int32_t *list, int64_t 
                                       [&](int32_t j, uint64_t v) {
                                           const uint32_t h = hash_find<S>(keys, j, &a.hdr->fault);
                                           acc_add(&vals[h], satw, h, v);
-                                      });
+                                      }, (int)nb);
             else
                 accumulate_hash<S>(a.X, a.Y, eb, eb + nb, 0, 1, lane, 64, keys, vals, satw, &a.hdr->fault);
             wave_sync();
@@ -911,7 +919,7 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
                                       [&](int32_t j, uint64_t v) {
                                           const uint32_t h = hash_find<S>(keys, j, &a.hdr->fault);
                                           acc_add(&vals[h], satw, h, v);
-                                      });
+                                      }, (int)nb);
             else
                 accumulate_hash<S>(a.X, a.Y, eb, eb + nb, threadIdx.x >> 6, NT / 64, threadIdx.x & 63, 64, keys,
                                    vals, satw, &a.hdr->fault);
@@ -983,11 +991,12 @@ __global__ __launch_bounds__(NT) void k_hash_block(const int32_t *list, int64_t 
 // at least 1; a saturated one only sets the bit).  Each wavefront handles
 // groups of 64 consecutive slots, one slot per lane: a ballot gives the
 // group's presence mask, a block scan of the group counts gives positions,
-// and lanes write consecutive outputs.  gcnt holds kTileW/64 int32.  Every
-// thread of the block calls it.
+// and lanes write consecutive outputs.  gcnt holds kTileW/64 int32.  The
+// tile's entries go at `base` within the row's slots when base >= 0, else at
+// a position taken from the row's cursor.  Every thread of the block calls it.
 __device__ void emit_dense_tile(const NumericArgs &a, int32_t c, int64_t i, int64_t t, int64_t c0,
                                 unsigned long long *acc, uint32_t *satw, int32_t *gcnt, int64_t *sw,
-                                int64_t *s_base, int *s_sat) {
+                                int64_t *s_base, int *s_sat, int64_t base = -1) {
     constexpr int NG = kTileW / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -1003,11 +1012,11 @@ __device__ void emit_dense_tile(const NumericArgs &a, int32_t c, int64_t i, int6
     int64_t tot;
     const int64_t inc = block_inclusive_scan(x, sw, &tot);
     if (tid < NG) gcnt[tid] = (int32_t)(inc - x);
-    if (tid == 0)
+    if (tid == 0 && base < 0)
         *s_base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)tot) : 0;
     __syncthreads();
     if (tot > 0) {
-        const int64_t off = a.slot_off[c] + *s_base;
+        const int64_t off = a.slot_off[c] + (base >= 0 ? base : *s_base);
         const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
         bool sat = false;
         for (int g = wave; g < NG; g += nwaves) {
@@ -1162,84 +1171,84 @@ __device__ void flush_split_tile(const NumericArgs &a, int64_t gt, int64_t ks, i
     }
 }
 
-// hash_find with the table size 2^log2s known at run time (same probe bound)
-__device__ __forceinline__ uint32_t hash_find_rt(int32_t *keys, int32_t j, int log2s, int32_t *fault) {
-    const uint32_t mask = (1u << log2s) - 1u;
-    uint32_t h = hash_of(j, log2s);
-    for (uint32_t n = 0; n <= mask; ++n) {
-        int32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == j) return h;
-        if (k == kEmptyKey) {
-            int32_t prev = atomicCAS(&keys[h], kEmptyKey, j);
-            if (prev == kEmptyKey || prev == j) return h;
-        }
-        h = (h + 1) & mask;
-    }
-    atomicOr(fault, 1);
-    return 0;
-}
+// Sparse parts (columns [c0p, c1p) of one row, at most kPartMaxTiles tiles
+// and kRankCap products) are accumulated by column rank in the tile memory:
+// a presence bitmap over the part's columns (marked by a first walk of the
+// products), each bitmap word's rank (present columns in the words before
+// it, a block scan of the words' popcounts), and one value slot per present
+// column in column order, which a second walk adds into.  No probing, and
+// emission is in column order by construction.  The memory is left all zero.
+constexpr int kRankWrOff = kPartMaxTiles * kTileW / 64;         // u64 words of the bitmap
+constexpr int kRankValOff = kRankWrOff + kPartMaxTiles * kTileW / 128;  // ... then u16 word ranks
+static_assert(kRankValOff + kRankCap <= kTileW, "rank parts fit the tile memory");
+static_assert(kRankCap <= 65535 && kRankCap <= kTileW, "word ranks and saturation bits");
 
-// Emit a sparse part of row i (candidate c), columns [c0p, c1p): values in
-// an LDS hash of 2^log2s slots and presence in a bitmap over the part's
-// columns, both overlaid on the tile memory acc (keys, then values, then the
-// bitmap).  The bitmap is walked in column order and each column looked up;
-// the part becomes one segment at tile t0; the memory is cleared again.
-// Every thread of the block calls it.
+// Word ranks of a marked bitmap of nwords words (every thread of the block
+// calls it); returns the number of present columns.
 template <int NT>
-__device__ void emit_hash_part(const NumericArgs &a, int32_t c, int64_t i, int64_t t0, int64_t c0p, int64_t c1p,
-                               int log2s, unsigned long long *acc, uint32_t *satw, int64_t *sw, int64_t *s_base,
-                               int *s_sat) {
+__device__ int64_t rank_words(const uint32_t *bm, uint16_t *wr, int nwords, int64_t *sw) {
     const int tid = threadIdx.x;
-    const int S = 1 << log2s;
-    int32_t *keys = reinterpret_cast<int32_t *>(acc);
-    unsigned long long *vals = acc + S / 2;
-    uint32_t *bm = reinterpret_cast<uint32_t *>(acc + S / 2 + S);
-    const int nwords = (int)((c1p - c0p + 31) / 32);
     const int wpt = (nwords + NT - 1) / NT;  // words per thread, contiguous
     const int w0 = tid * wpt, w1 = (w0 + wpt < nwords) ? w0 + wpt : nwords;
     int64_t local = 0;
     for (int w = w0; w < w1; ++w) local += __popc(bm[w]);
     int64_t cnt;
-    const int64_t incl = block_inclusive_scan(local, sw, &cnt);
-    if (tid == 0) *s_base = (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)cnt);
+    int64_t run = block_inclusive_scan(local, sw, &cnt) - local;
+    for (int w = w0; w < w1; ++w) {
+        wr[w] = (uint16_t)run;
+        run += __popc(bm[w]);
+    }
     __syncthreads();
-    const int64_t off = a.slot_off[c] + *s_base;
-    int64_t pos = off + incl - local;
+    return cnt;
+}
+
+// Value slot of part column r (marked in the bitmap)
+__device__ __forceinline__ uint32_t rank_of(const uint32_t *bm, const uint16_t *wr, int64_t r) {
+    const int w = (int)(r >> 5);
+    return (uint32_t)wr[w] + (uint32_t)__popc(bm[w] & ((1u << (r & 31)) - 1u));
+}
+
+// Emit a sparse part of row i (candidate c): its cnt present columns in
+// column order, as one segment at tile t0.  The entries go at `base` within
+// the row's slots when base >= 0, else at a position taken from the row's
+// cursor.  Bitmap words, word ranks, values and saturation bits are cleared
+// as they are emitted.  Every thread of the block calls it.
+template <int NT>
+__device__ void emit_rank_part(const NumericArgs &a, int32_t c, int64_t i, int64_t t0, int64_t c0p, int nwords,
+                               int64_t cnt, uint32_t *bm, uint16_t *wr, unsigned long long *vals, uint32_t *satw,
+                               int64_t *s_base, int *s_sat, int64_t base) {
+    const int tid = threadIdx.x;
+    if (tid == 0 && base < 0)
+        *s_base = cnt > 0 ? (int64_t)atomicAdd((unsigned long long *)&a.row_cursor[c], (unsigned long long)cnt) : 0;
+    __syncthreads();
+    const int64_t off = a.slot_off[c] + (base >= 0 ? base : *s_base);
+    const int wpt = (nwords + NT - 1) / NT;
+    const int w0 = tid * wpt, w1 = (w0 + wpt < nwords) ? w0 + wpt : nwords;
     bool sat = false;
-    const uint32_t hmask = (uint32_t)S - 1u;
     for (int w = w0; w < w1; ++w) {
         uint32_t bits = bm[w];
+        uint32_t k = wr[w];
         while (bits) {
             const int b = __builtin_ctz(bits);
             bits &= bits - 1;
-            const int32_t col = (int32_t)(c0p + (int64_t)w * 32 + b);
-            uint32_t h = hash_of(col, log2s);
-            for (uint32_t n = 0; keys[h] != col; ++n) {  // present: inserted by hash_find_rt
-                if (n > hmask) {  // not found (only after a fault of the insertion): emit garbage, flagged
-                    atomicOr(&a.hdr->fault, 1);
-                    break;
-                }
-                h = (h + 1) & hmask;
-            }
-            const bool sb = (satw[h >> 5] >> (h & 31)) & 1u;
+            const bool sb = (satw[k >> 5] >> (k & 31)) & 1u;
             sat |= sb;
-            a.slot_col[pos] = col;
-            a.slot_val[pos] = sb ? kSat : vals[h];
-            ++pos;
+            a.slot_col[off + k] = (int32_t)(c0p + (int64_t)w * 32 + b);
+            a.slot_val[off + k] = sb ? kSat : vals[k];
+            vals[k] = 0;
+            if (sb) atomicAnd(&satw[k >> 5], ~(1u << (k & 31)));
+            ++k;
         }
+        bm[w] = 0;
+        wr[w] = 0;
     }
     if (sat) *s_sat = 1;
-    if (tid == 0) {
+    if (tid == 0 && cnt > 0) {
         const int64_t sg = a.seg_base[c] + t0;
         a.seg_cnt[sg] = cnt;
         a.seg_src[sg] = off;
         atomicAdd((unsigned long long *)&a.row_nnz[i], (unsigned long long)cnt);
     }
-    __syncthreads();
-    // restore the all-zero tile memory and bitmaps
-    const int zero_words = S / 2 + S + (nwords + 1) / 2;
-    for (int t = tid; t < zero_words; t += NT) acc[t] = 0;
-    for (int t = tid; t < (S + 31) / 32; t += NT) satw[t] = 0;
     __syncthreads();
 }
 
@@ -1247,15 +1256,15 @@ __device__ void emit_hash_part(const NumericArgs &a, int32_t c, int64_t i, int64
 // entry's segment of its right row inside the part is located (from the right
 // operand's tile index when there is one, else by binary search or the row
 // start), the segment lengths are block-scanned, and:
-//  * a part with at most part_hash_cap products is accumulated in an LDS hash
-//    overlaid on the tile memory, with a presence bitmap over the part's
-//    columns; emission walks the bitmap in column order;
+//  * a part with at most part_hash_cap products is accumulated by column
+//    rank (a presence bitmap over the part's columns, word ranks, one value
+//    slot per present column), overlaid on the tile memory;
 //  * otherwise the part is walked tile by tile: per tile the segments are
 //    found again (cursors carried between tiles when the row's entries fit one
 //    batch and there is no tile index), and the flattened products are shared
 //    evenly by the wavefronts into a dense LDS tile.
 // Left entries are taken in batches of kDenseThreads.
-__global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, int64_t n_list, const int64_t *task_base,
+__global__ __launch_bounds__(kDenseThreads, 4) void k_dense(const int32_t *list, int64_t n_list, const int64_t *task_base,
                                                          int64_t n_tasks, NumericArgs a) {
     constexpr int W = kTileW;
     constexpr int NW = W / 32;
@@ -1290,19 +1299,32 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
     // cur[] when from_cursor.  The bound searches are shared out to groups of
     // lanes (all 512 threads on few entries, one thread per entry on many).
     // Returns the batch's product count (block-uniform).
+    // With the tile index, a row of at most NT entries keeps each entry's
+    // right row (column id and row start, or -1 when X's column mask drops
+    // it) in ent_k / ent_b for the whole task (the cursor memory, unused then).
+    static_assert(kCursorCap >= NT, "the kept entries overlay the cursor memory");
+    int32_t *ent_k = reinterpret_cast<int32_t *>(cur);
+    int32_t *ent_b = ent_k + NT;
     auto segments = [&](int64_t xb, int64_t xlen, int64_t eb, int64_t c0, int64_t c1, bool from_cursor,
                         bool keep_cursor) -> int64_t {
         const int64_t nb = (xlen - eb < NT) ? xlen - eb : NT;
         if (a.ytile) {  // the right operand's tile index gives both bounds directly
             if (tid < nb) {
-                const int64_t e = eb + tid;
-                const int32_t k = a.X.col[xb + e];
-                if (a.X.cmask && !bit_test(a.X.cmask, k)) {
+                int32_t k;
+                int64_t yb;
+                if (from_cursor) {  // entries kept for the task
+                    k = ent_k[tid];
+                    yb = ent_b[tid];
+                } else {
+                    k = a.X.col[xb + eb + tid];
+                    if (a.X.cmask && !bit_test(a.X.cmask, k)) k = -1;
+                    yb = k >= 0 ? a.Y.rp[k] : 0;
+                }
+                if (k < 0) {
                     seg_s[tid] = 0;
                     seg_l[tid] = 0;
                 } else {
                     const int32_t *yt = a.ytile + (int64_t)k * (ntiles + 1);
-                    const int64_t yb = a.Y.rp[k];
                     const int32_t lo = yt[c0 >> kTileShift], hi = yt[(c1 + W - 1) >> kTileShift];
                     seg_s[tid] = yb + lo;
                     seg_l[tid] = hi - lo;
@@ -1365,8 +1387,8 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
         return tot;
     };
     // visit the flattened products of the current batch: f(column, value)
-    auto products = [&](int64_t tot, const uint64_t *xval, auto f) {
-        walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f);
+    auto products = [&](int64_t tot, int64_t nb, const uint64_t *xval, auto f) {
+        walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f, nb < NT ? (int)nb : NT);
     };
 
     // tasks from the dense queue (rows of very different cost stay balanced)
@@ -1379,15 +1401,17 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
             if (tid == 0) {
                 s_task[0] = pp;
                 s_task[1] = task - task_base[pp];
-                s_task[2] = task_base[pp + 1] - task_base[pp];
             }
         }
         __syncthreads();
         const int64_t p = s_task[0], qq = s_task[1];
         const int64_t sp = a.dense_split[p];
-        const int64_t ks = sp & 255, sslot = sp >> 8;
-        const int64_t nparts = s_task[2] / ks;
-        const int64_t q = qq / ks, r = qq % ks;  // part, split
+        const int64_t ks = sp & 255;
+        const int64_t sslot = ks > 1 ? sp >> 8 : 0;
+        const int64_t m = ks > 1 ? 1 : sp >> 16;           // tiles per part
+        const int64_t grp = ks > 1 ? 1 : (sp >> 8) & 255;  // parts per task
+        const int64_t nparts = (ntiles + m - 1) / m;
+        const int64_t q = qq / ks, r = qq % ks;  // task of the row, split
         const int32_t c = list[p];
         const int64_t i = a.cand ? a.cand[c] : c;
         int64_t xb = a.X.rp[i], xlen = a.X.rp[i + 1] - xb;
@@ -1397,96 +1421,144 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(const int32_t *list, in
             xb += e0 < xlen ? e0 : xlen;
             xlen = e1 > e0 ? e1 - e0 : 0;
         }
-        const int64_t m = (ntiles + nparts - 1) / nparts;
-        const int64_t t0 = q * m;
-        const int64_t t1 = (t0 + m < ntiles) ? t0 + m : ntiles;
-        if (t0 >= t1) continue;  // block-uniform
-        const int64_t c0p = t0 * W, c1p = (t1 * W < ycols) ? t1 * W : ycols;
+        const int64_t pa = q * grp, pb = (pa + grp < nparts) ? pa + grp : nparts;
+        if (pa >= pb) continue;  // block-uniform
         const bool single = xlen <= NT;
-
-        // part-level product count, when the part may be sparse enough for the
-        // LDS hash (a row whose mean part holds more than twice the hash
-        // capacity goes straight to the dense tiles)
-        const bool may_hash = ks == 1 && (c1p - c0p) <= (int64_t)kPartMaxTiles * W &&
-                              a.nop[c] <= 2 * a.tune.part_hash_cap * nparts;
-        int64_t ltot = 0;
-        if (may_hash) {
-            for (int64_t eb = 0; eb < xlen; eb += NT) ltot += segments(xb, xlen, eb, c0p, c1p, false, false);
-            if (ltot == 0) continue;
-        }
-
-        if (may_hash && ltot <= a.tune.part_hash_cap) {
-            // sparse part: values in an LDS hash, presence in a bitmap over the
-            // part's columns (both overlaid on the tile memory); emission walks
-            // the bitmap in column order and looks each column up.
-            int log2s = 6;
-            while ((int64_t(1) << log2s) < 2 * ltot) ++log2s;
-            const int S = 1 << log2s;
-            int32_t *keys = reinterpret_cast<int32_t *>(acc);
-            unsigned long long *vals = acc + S / 2;
-            uint32_t *bm = reinterpret_cast<uint32_t *>(acc + S / 2 + S);
-            for (int t = tid; t < S; t += NT) keys[t] = kEmptyKey;  // vals and bm are already zero
+        const int64_t nop_c = a.nop[c];
+        // Where the row's parts write: the row has ub = min(products, usable
+        // columns) slots.  With a slot per column of Y, a part's entries go
+        // at its first column; with a slot per product (and the tile index),
+        // at the row's products in tiles below the part, which bound the
+        // entries before it; otherwise at a position taken from the row's
+        // cursor.  Every task of a row takes the same choice.
+        const int64_t cap = a.slot_off[c + 1] - a.slot_off[c];
+        const int mode = ks > 1 ? 0 : cap >= ycols ? 1 : (a.ytile && cap >= nop_c) ? 2 : 0;
+        const bool keep = a.ytile && single;  // the row's entries kept for the task
+        const bool no_sat = sat_mul(vm, (uint64_t)nop_c) < kSat;  // plain adds (see vm)
+        int64_t pbase = 0;  // mode 2: the row's products in tiles below the current part
+        if (keep) {  // (with the prefix of mode 2 from the same round of loads)
+            int64_t lo = 0;
+            if (tid < xlen) {
+                int32_t k = a.X.col[xb + tid];
+                if (a.X.cmask && !bit_test(a.X.cmask, k)) k = -1;
+                ent_k[tid] = k;
+                ent_b[tid] = k >= 0 ? (int32_t)a.Y.rp[k] : 0;
+                if (mode == 2 && pa > 0 && k >= 0) lo = a.ytile[(int64_t)k * (ntiles + 1) + pa * m];
+            }
+            if (mode == 2 && pa > 0) block_inclusive_scan(lo, sw, &pbase);
             __syncthreads();
+        } else if (mode == 2 && pa > 0) {
+            const int64_t tb = pa * m;
             for (int64_t eb = 0; eb < xlen; eb += NT) {
-                const int64_t tot = single ? ltot : segments(xb, xlen, eb, c0p, c1p, false, false);
-                const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
-                products(tot, xval, [&](int32_t j, uint64_t v) {
-                    const uint32_t h = hash_find_rt(keys, j, log2s, &a.hdr->fault);
-                    acc_add(&vals[h], satw, h, v);
-                    const int64_t r = j - c0p;
-                    atomicOr(&bm[r >> 5], 1u << (r & 31));
-                });
+                int64_t lo = 0;
+                if (eb + tid < xlen) {
+                    const int32_t k = a.X.col[xb + eb + tid];
+                    if (!(a.X.cmask && !bit_test(a.X.cmask, k))) lo = a.ytile[(int64_t)k * (ntiles + 1) + tb];
+                }
+                int64_t tot;
+                block_inclusive_scan(lo, sw, &tot);
+                pbase += tot;
                 __syncthreads();
             }
-            emit_hash_part<NT>(a, c, i, t0, c0p, c1p, log2s, acc, satw, sw, &s_base, &s_sat);
-            continue;
         }
 
-        // dense part: tile by tile (cursors only without the tile index)
-        const bool cursors = single && !a.ytile;
-        const bool no_sat = sat_mul(vm, (uint64_t)a.nop[c]) < kSat;
-        if (cursors) {  // cursors at the part start
-            for (int64_t e = tid; e < xlen; e += NT) {
-                int32_t k = a.X.col[xb + e];
-                cur[e] = a.Y.rp[k];
+        for (int64_t part = pa; part < pb; ++part) {
+            const int64_t t0 = part * m;
+            const int64_t t1 = (t0 + m < ntiles) ? t0 + m : ntiles;
+            const int64_t c0p = t0 * W, c1p = (t1 * W < ycols) ? t1 * W : ycols;
+
+            // part-level product count, when the part may be sparse enough for
+            // the LDS hash (a row whose mean part holds more than twice the
+            // hash capacity goes straight to the dense tiles)
+            const bool may_hash = ks == 1 && (c1p - c0p) <= (int64_t)kPartMaxTiles * W &&
+                                  nop_c <= 2 * a.tune.part_hash_cap * nparts;
+            int64_t ltot = 0;
+            if (may_hash) {
+                for (int64_t eb = 0; eb < xlen; eb += NT) ltot += segments(xb, xlen, eb, c0p, c1p, keep, false);
+                if (ltot == 0) continue;
             }
-            __syncthreads();
-            if (c0p > 0) {
-                int g = 64;
-                while (g > 1 && (int64_t)(NT / g) < xlen) g >>= 1;
-                const int li = tid & (g - 1);
-                const uint64_t gm = group_mask(g);
-                for (int64_t x = tid / g; x < xlen; x += NT / g) {
-                    const int32_t k = a.X.col[xb + x];
-                    const int64_t r = group_lower_bound(a.Y.col, a.Y.rp[k], a.Y.rp[k + 1], (int32_t)c0p, g, li, gm);
-                    if (li == 0) cur[x] = r;
+
+            if (may_hash && ltot <= a.tune.part_hash_cap) {
+                // sparse part, accumulated by column rank: mark, rank the words, add
+                const int nwords = (int)((c1p - c0p + 31) / 32);
+                uint32_t *bm = reinterpret_cast<uint32_t *>(acc);
+                uint16_t *wr = reinterpret_cast<uint16_t *>(acc + kRankWrOff);
+                unsigned long long *vals = acc + kRankValOff;
+                for (int64_t eb = 0; eb < xlen; eb += NT) {
+                    const int64_t tot = single ? ltot : segments(xb, xlen, eb, c0p, c1p, false, false);
+                    const int nb = (int)(xlen - eb < NT ? xlen - eb : NT);
+                    walk_products<false, false, NT, kProdUnroll>(a.Y, seg_o, seg_s, (int32_t)tot, nullptr,
+                                                                 [&](int32_t j, uint64_t) {
+                                                                     const int64_t r = j - c0p;
+                                                                     atomicOr(&bm[r >> 5], 1u << (r & 31));
+                                                                 }, nb);
+                    __syncthreads();
+                }
+                const int64_t cnt = rank_words<NT>(bm, wr, nwords, sw);
+                for (int64_t eb = 0; eb < xlen; eb += NT) {
+                    const int64_t tot = single ? ltot : segments(xb, xlen, eb, c0p, c1p, false, false);
+                    const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
+                    products(tot, xlen - eb, xval, [&](int32_t j, uint64_t v) {
+                        const uint32_t k = rank_of(bm, wr, j - c0p);
+                        acc_add(&vals[k], satw, k, v);
+                    });
+                    __syncthreads();
+                }
+                emit_rank_part<NT>(a, c, i, t0, c0p, nwords, cnt, bm, wr, vals, satw, &s_base, &s_sat,
+                                   mode == 1 ? c0p : mode == 2 ? pbase : -1);
+                pbase += ltot;
+                continue;
+            }
+
+            // dense part: tile by tile (cursors only without the tile index)
+            const bool cursors = single && !a.ytile;
+            if (cursors) {  // cursors at the part start
+                for (int64_t e = tid; e < xlen; e += NT) {
+                    int32_t k = a.X.col[xb + e];
+                    cur[e] = a.Y.rp[k];
+                }
+                __syncthreads();
+                if (c0p > 0) {
+                    int g = 64;
+                    while (g > 1 && (int64_t)(NT / g) < xlen) g >>= 1;
+                    const int li = tid & (g - 1);
+                    const uint64_t gm = group_mask(g);
+                    for (int64_t x = tid / g; x < xlen; x += NT / g) {
+                        const int32_t k = a.X.col[xb + x];
+                        const int64_t r = group_lower_bound(a.Y.col, a.Y.rp[k], a.Y.rp[k + 1], (int32_t)c0p, g, li, gm);
+                        if (li == 0) cur[x] = r;
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int64_t t = t0; t < t1; ++t) {
+                const int64_t c0 = t * W;
+                const int64_t c1 = (c0 + W < ycols) ? c0 + W : ycols;
+                int64_t ttot = 0;
+                for (int64_t eb = 0; eb < xlen; eb += NT) {
+                    const int64_t tot = segments(xb, xlen, eb, c0, c1, cursors || keep, cursors);
+                    ttot += tot;
+                    const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
+                    products(tot, xlen - eb, xval, [&](int32_t j, uint64_t v) {
+                        const uint32_t slot = (uint32_t)(j - c0);
+                        if (no_sat)
+                            (void)__hip_atomic_fetch_add(&acc[slot], (unsigned long long)v, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                        else
+                            acc_add(&acc[slot], satw, slot, v);
+                    });
+                    __syncthreads();
+                }
+                if (ks == 1) {
+                    emit_dense_tile(a, c, i, t, c0, acc, satw, seg_o, sw, &s_base, &s_sat,
+                                    mode == 1 ? c0 : mode == 2 ? pbase : -1);
+                    pbase += ttot;
+                } else {
+                    const int64_t gt = sslot * ntiles + t;
+                    flush_split_tile(a, gt, ks, c, i, t, c0, acc, satw, seg_o, sw, &s_base, &s_sat, &s_last);
                 }
                 __syncthreads();
             }
-        }
-        for (int64_t t = t0; t < t1; ++t) {
-            const int64_t c0 = t * W;
-            const int64_t c1 = (c0 + W < ycols) ? c0 + W : ycols;
-            for (int64_t eb = 0; eb < xlen; eb += NT) {
-                const int64_t tot = segments(xb, xlen, eb, c0, c1, cursors, cursors);
-                const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
-                products(tot, xval, [&](int32_t j, uint64_t v) {
-                    const uint32_t slot = (uint32_t)(j - c0);
-                    if (no_sat)
-                        (void)__hip_atomic_fetch_add(&acc[slot], (unsigned long long)v, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-                    else
-                        acc_add(&acc[slot], satw, slot, v);
-                });
-                __syncthreads();
-            }
-            if (ks == 1) {
-                emit_dense_tile(a, c, i, t, c0, acc, satw, seg_o, sw, &s_base, &s_sat);
-            } else {
-                const int64_t gt = sslot * ntiles + t;
-                flush_split_tile(a, gt, ks, c, i, t, c0, acc, satw, seg_o, sw, &s_base, &s_sat, &s_last);
-            }
-            __syncthreads();
         }
     }
     __syncthreads();
@@ -1638,7 +1710,7 @@ __device__ __forceinline__ void walk_entry_range(const NumericArgs &a, int64_t e
         const int64_t tot = row_segments<kBucketThreads>(a.X, a.Y, eb, nb, seg_s, seg_o, sw);
         if (tot < kWalkMax) {
             walk_products_any<kBucketThreads, kBucketUnroll>(a.Y, seg_o, seg_s, (int32_t)tot,
-                                                              a.X.val ? a.X.val + eb : nullptr, f);
+                                                              a.X.val ? a.X.val + eb : nullptr, f, (int)nb);
         } else {
             const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
             for (int64_t e = eb + wave; e < eb + nb; e += kBucketThreads / 64) {
@@ -1837,27 +1909,24 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
         const int32_t c = b.list[p];
         const int64_t i = a.cand ? a.cand[c] : c;
         if (t1 - t > 1 && off[t1] - off[t] <= a.tune.part_hash_cap) {
-            // a sparse part: one LDS hash over its columns (as the dense kernel's hash parts)
+            // a sparse part, accumulated by column rank (as the dense kernel's sparse parts)
             const int64_t c0p = t * W, c1p = (t1 * W < a.ycols) ? t1 * W : a.ycols;
-            const int64_t ltot = off[t1] - off[t];
-            int log2s = 6;
-            while ((int64_t(1) << log2s) < 2 * ltot) ++log2s;
-            const int S = 1 << log2s;
-            int32_t *keys = reinterpret_cast<int32_t *>(acc);
-            unsigned long long *vals = acc + S / 2;
-            uint32_t *bm = reinterpret_cast<uint32_t *>(acc + S / 2 + S);
-            for (int q = tid; q < S; q += kDenseThreads) keys[q] = kEmptyKey;  // vals and bm are zero
-            __syncthreads();
+            const int nwords = (int)((c1p - c0p + 31) / 32);
+            uint32_t *bm = reinterpret_cast<uint32_t *>(acc);
+            uint16_t *wr = reinterpret_cast<uint16_t *>(acc + kRankWrOff);
+            unsigned long long *vals = acc + kRankValOff;
             for (int64_t e = off[t] + tid; e < off[t1]; e += kDenseThreads) {
-                const int32_t j = b.prod_col[e];
-                const uint64_t v = valued ? b.prod_val[e] : 1ull;
-                const uint32_t h = hash_find_rt(keys, j, log2s, &a.hdr->fault);
-                acc_add(&vals[h], satw, h, v);
-                const int64_t r = j - c0p;
+                const int64_t r = b.prod_col[e] - c0p;
                 atomicOr(&bm[r >> 5], 1u << (r & 31));
             }
             __syncthreads();
-            emit_hash_part<kDenseThreads>(a, c, i, t, c0p, c1p, log2s, acc, satw, sw, &s_base, &s_sat);
+            const int64_t cnt = rank_words<kDenseThreads>(bm, wr, nwords, sw);
+            for (int64_t e = off[t] + tid; e < off[t1]; e += kDenseThreads) {
+                const uint32_t k = rank_of(bm, wr, b.prod_col[e] - c0p);
+                acc_add(&vals[k], satw, k, valued ? b.prod_val[e] : 1ull);
+            }
+            __syncthreads();
+            emit_rank_part<kDenseThreads>(a, c, i, t, c0p, nwords, cnt, bm, wr, vals, satw, &s_base, &s_sat, -1);
             continue;
         }
         for (int64_t tt = t; tt < t1; ++tt) {  // tile by tile

@@ -198,6 +198,36 @@ def test_server_results_equal_oracle(atp, net, mixed, cache):
     ctx.close()
 
 
+def test_heavy_products_run_alone_and_equal_oracle(atp, net, mixed, monkeypatch):
+    """With every product counted as heavy (a threshold of one product), each
+    product's numeric phase holds the device alone across the server's four
+    lanes (the others wait at the gate), so the lanes take turns; every
+    request still completes with the oracle's result, and so does a batch on
+    four lanes afterwards."""
+    monkeypatch.setenv("ATP_HEAVY_OPS", "1")
+    qs, ref = mixed
+    ctx = atp.Context(device=0)
+    ctx.load_hin(net)
+    ctx.server_start(lanes=4, max_batch=4)
+    for z, q in enumerate(qs):
+        ctx.submit(q, tag=z)
+    got = {}
+    while len(got) < len(qs):
+        for cp in ctx.poll(64, wait_ms=2000):
+            got[cp["tag"]] = cp
+    for z in range(len(qs)):
+        assert got[z]["status"] == atp.ATP_OK, (z, got[z]["status"])
+        assert same(host(got[z]["result"]), ref[z]), (z, qs[z].name)
+        got[z]["result"].free()
+    ctx.server_stop()
+    res = ctx.eval_batch(qs, lanes=4, max_batch=1)
+    for z, (r, want) in enumerate(zip(res, ref)):
+        assert not isinstance(r, Exception), (z, r)
+        assert same(host(r), want), (z, qs[z].name)
+        r.free()
+    ctx.close()
+
+
 def test_server_submit_during_run_and_stop_drains(atp, net, mixed):
     qs, ref = mixed
     ctx = atp.Context(device=0)
@@ -230,8 +260,8 @@ def test_tuning_get_set_and_autotune(atp, net, mixed):
     ctx = atp.Context(device=0)
     ctx.load_hin(net)
     t0 = ctx.tuning()
-    assert t0["bucket_pct"] == 400 and t0["part_hash_cap"] == 2048
-    for bad in ({"part_target": 0}, {"part_hash_cap": 4096}, {"bucket_pct": -1}, {"split_ops": 10},
+    assert t0["bucket_pct"] == 400 and t0["part_hash_cap"] == 4096
+    for bad in ({"part_target": 0}, {"part_hash_cap": 4097}, {"bucket_pct": -1}, {"split_ops": 10},
                 {"bucket_chunk": 8}):
         with pytest.raises(atp.AtpError) as e:
             ctx.set_tuning(**bad)
@@ -243,8 +273,8 @@ def test_tuning_get_set_and_autotune(atp, net, mixed):
     ctx.set_tuning(**t0)
     got = ctx.autotune(qs[:10], rounds=1)
     assert got["bucket_pct"] in (25, 50, 100, 200, 400, 800)
-    assert got["part_target"] in (300, 600, 1200, 2400)
-    assert got["part_hash_cap"] in (512, 1024, 2048)
+    assert got["part_target"] in (600, 1200, 2400, 3600)
+    assert got["part_hash_cap"] in (1024, 2048, 4096)
     assert got["bucket_chunk"] in (1024, 2048, 4096, 8192)
     assert got["ms_after"] <= got["ms_before"] * 1.0001
     assert {k: ctx.tuning()[k] for k in atp.TUNABLES} == {k: got[k] for k in atp.TUNABLES}

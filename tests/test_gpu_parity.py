@@ -262,6 +262,42 @@ def test_overflow_is_detected_for_every_plan(atp, oracle_mod, widths, over):
     ctx.close()
 
 
+@pytest.mark.parametrize("w,over", [(128, True), (127, False)])
+def test_counts_beyond_int64_in_sparse_parts(atp, oracle_mod, w, over):
+    """The last product of the left-deep plan is one start row (w entries of
+    2^56 paths each) times a 60,000-column relation in which every one of
+    the w nodes reaches the same 40 columns spread over eight column tiles:
+    few products per tile, so the row is accumulated in sparse parts by
+    column rank.  Each column receives w contributions of 2^56: 128 reach
+    exactly 2^63 (ATP_EOVERFLOW, as the oracle reports), 127 stay exact."""
+    k = 9
+    names = [f"L{i}" for i in range(k + 2)]
+    counts = {names[0]: 1, names[k]: w, names[k + 1]: 60000}
+    for i in range(1, k):
+        counts[names[i]] = 128
+    hin = HIN(counts=counts)
+    for i in range(k):
+        a, b = counts[names[i]], counts[names[i + 1]]
+        _csr_rel(hin, names[i], names[i + 1], [list(range(b))] * a)
+    cols = [c * 1500 + 7 for c in range(40)]
+    _csr_rel(hin, names[k], names[k + 1], [cols] * w)
+    q = Query("-".join(names), names, [])
+    ref = oracle_mod.eval_full(hin, q)
+    assert ref[3] == (oracle_mod.ORC_OVERFLOW if over else oracle_mod.ORC_OK)
+    ctx = make_ctx(atp, hin)
+    ld = "0"
+    for i in range(1, k + 1):
+        ld = f"({ld},{i})"
+    for plan in [ld, None]:
+        if over:
+            with pytest.raises(atp.AtpError) as e:
+                ctx.eval_query(q, plan=plan)
+            assert e.value.status == atp.ATP_EOVERFLOW, plan
+        else:
+            assert_same(ctx.eval_query(q, plan=plan), ref, str(plan))
+    ctx.close()
+
+
 def test_dead_intermediate_may_exceed_int64(atp, oracle_mod):
     """Suffix products hold counts of 2^63 on rows the start never reaches;
     the final count is 1, so every plan returns the exact result."""
@@ -345,10 +381,11 @@ def test_memory_budget(atp, oracle_mod, tiny_cfg):
                                   {"ATP_SPLIT_OPS": "1024", "ATP_PART_TARGET": "64", "ATP_BUCKET_PCT": "100"},
                                   {"ATP_TILE_INDEX_CAP": "0"}, {"ATP_TILE_INDEX_CAP": "0", "ATP_PART_TARGET": "1"},
                                   {"ATP_BUCKET_PCT": "0", "ATP_BUCKET_CHUNK": "64"}, {"ATP_SERIAL_BINS": "1"},
-                                  {"ATP_BUCKET_PCT": "0", "ATP_CHUNK_HIST_CAP": "0"}, {"ATP_NO_MAILBOX": "1"}])
+                                  {"ATP_BUCKET_PCT": "0", "ATP_CHUNK_HIST_CAP": "0"}, {"ATP_NO_MAILBOX": "1"},
+                                  {"ATP_PART_TARGET": "4000"}, {"ATP_PART_TARGET": "4000", "ATP_BUCKET_PCT": "0"}])
 def test_every_kernel_path_under_forced_tunings(atp, oracle_mod, tune, monkeypatch):
-    """The binning thresholds only move rows between kernels (hash parts,
-    dense tiles, split tiles, tile buckets) and segment bounds between the tile
+    """The binning thresholds only move rows between kernels (rank-accumulated
+    sparse parts, dense tiles, split tiles, tile buckets) and segment bounds between the tile
     index and searches, the bins run on one stream or beside each other, and
     step totals come back through the mapped mailbox or by copies; results
     must not change."""
