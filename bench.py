@@ -571,6 +571,101 @@ def counters_summary(args) -> int:
     return 0
 
 
+def probe_mode(args) -> int:
+    """Each query of the workload once, the bins of every product serialised:
+    under `rocprofv3 --pmc` the k_dense dispatches then come in the order
+    this prints ({"query", "product"} per dispatch, one JSON line), so that
+    `--dense-counters` can label them."""
+    os.environ["ATP_PROFILE_STEPS"] = "1"  # kernel names carry the product's index
+    import paper_2201_04058_amd as atp
+    from synth import configs
+    hin, queries = configs.load(args.workload)
+    ctx = _ctx_with_network(atp, hin)
+    order = []
+    for q in queries:
+        ctx.set_flags(profile=True, serial_bins=True)
+        ctx.kernel_times_reset()
+        ctx.eval_query(q).free()
+        names = [k for k, v in ctx.kernel_times().items() if k.startswith("dense#") and v[1] > 0]
+        for k in sorted(names, key=lambda x: int(x.split("#")[1])):
+            order.append({"query": q.name, "product": int(k.split("#")[1])})
+    ctx.set_flags()
+    ctx.close()
+    print(json.dumps({"workload": args.workload, "dense_dispatches": order}), flush=True)
+    return 0
+
+
+DENSE_COUNTER_GROUPS = (
+    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_ACTIVE_INST_VALU "
+    "SQ_INSTS_VALU",
+    "SQ_INSTS_LDS SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_WAIT_INST_LDS "
+    "TCC_HIT_sum TCC_MISS_sum")
+
+
+def dense_counters(args) -> int:
+    """profiles/counters_dense_<workload>.txt: every k_dense dispatch of
+    `bench.py --probe` runs under rocprofv3 --pmc (one database per counter
+    group), labelled with the probe's query and product."""
+    probe_json, dbs = args.dense_counters[0], args.dense_counters[1:]
+    with open(probe_json) as fh:
+        probe = json.loads(fh.read().strip().splitlines()[-1])
+    labels = probe["dense_dispatches"]
+    w = probe["workload"]
+    import sqlite3
+    per = {}  # label index -> counter -> value
+    durs = {}
+    for db in dbs:
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, name, counter_name, counter_value, duration from pmc_events").fetchall()
+        con.close()
+        disp = {}
+        for did, name, cn, cv, du in rows:
+            if "k_dense(" not in name:
+                continue
+            disp.setdefault(did, {}).setdefault(cn, 0.0)
+            disp[did][cn] += cv
+            disp[did]["_dur"] = du
+        ids = sorted(disp)
+        if len(ids) != len(labels):
+            raise SystemExit(f"{db}: {len(ids)} k_dense dispatches, the probe lists {len(labels)}")
+        for i, did in enumerate(ids):
+            durs.setdefault(i, []).append(disp[did].pop("_dur") / 1e3)
+            per.setdefault(i, {}).update(disp[did])
+    lines = [f"# k_dense counters on workload {w}, one k_dense dispatch per row (rocprofv3 --pmc, one group per run)",
+             f"# probe: python3 bench.py --workload {w} --probe > probe_{w}.json"]
+    for z, g in enumerate(DENSE_COUNTER_GROUPS):
+        lines.append(f"# group {z + 1}: timeout -s KILL 120 rocprofv3 --pmc {g} -d gpurun_out/pmc_dense{z + 1}_{w} -o run "
+                     f"-- python3 bench.py --workload {w} --probe")
+    lines.append(f"# summary: python3 bench.py --dense-counters probe_{w}.json "
+                 + " ".join(f"gpurun_out/pmc_dense{z + 1}_{w}/run_results.db" for z in range(len(DENSE_COUNTER_GROUPS))))
+    lines.append("# SQ_* counts are summed over the device; *_CYCLES and SQ_WAIT_* / SQ_ACTIVE_* are wave-cycles of the")
+    lines.append("# sequencers (in the same unit, so their ratios hold); TCC_* are L2 requests")
+    lines.append("")
+    cols = ["dur_us", "waves", "valu/wave", "salu/wave", "vmem/wave", "lds/wave", "wait_any", "wait_inst", "valu_busy",
+            "lds_bank", "L2_hit"]
+    lines.append(f"{'query':24s} {'prod':>4s} " + " ".join(f"{c:>10s}" for c in cols))
+    for i, lab in enumerate(labels):
+        c = per.get(i, {})
+        wv = max(c.get("SQ_WAVES", 0.0), 1.0)
+        wc = max(c.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        hit, miss = c.get("TCC_HIT_sum", 0.0), c.get("TCC_MISS_sum", 0.0)
+        vals = [sum(durs.get(i, [0])) / max(len(durs.get(i, [])), 1), c.get("SQ_WAVES", 0.0),
+                c.get("SQ_INSTS_VALU", 0.0) / wv, c.get("SQ_INSTS_SALU", 0.0) / wv, c.get("SQ_INSTS_VMEM_RD", 0.0) / wv,
+                c.get("SQ_INSTS_LDS", 0.0) / wv, c.get("SQ_WAIT_ANY", 0.0) / wc, c.get("SQ_WAIT_INST_ANY", 0.0) / wc,
+                c.get("SQ_ACTIVE_INST_VALU", 0.0) / wc,
+                c.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(c.get("SQ_ACTIVE_INST_LDS", 0.0), 1.0),
+                hit / max(hit + miss, 1.0)]
+        lines.append(f"{lab['query']:24s} {lab['product']:4d} " + " ".join(f"{v:10.3f}" if v < 100 else f"{v:10.0f}"
+                                                                        for v in vals))
+    lines += ["", "wait_any, wait_inst, valu_busy: SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_VALU over SQ_WAVE_CYCLES "
+              "(share of a wave's life); lds_bank: SQ_LDS_BANK_CONFLICT over SQ_ACTIVE_INST_LDS; L2_hit: TCC hits over "
+              "hits + misses; per-wave columns: instructions per wave"]
+    with open(os.path.join(ROOT, "profiles", f"counters_dense_{w}.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines), flush=True)
+    return 0
+
+
 # numeric kernels whose algorithmic bytes make up a product's compulsory bytes
 # (operands read once, result written once); the compaction copy and the
 # scans are design overhead
@@ -810,6 +905,11 @@ def main() -> int:
                     help="write profiles/traffic_*_<workload>.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
                          "databases of `bench.py --steps 1 --warmup 0 --no-side-by-side --no-cpu-baseline "
                          "--no-news` and of `bench.py --copy-calibration 1024`")
+    ap.add_argument("--probe", action="store_true",
+                    help="each query once, bins serialised; prints the order of the k_dense dispatches")
+    ap.add_argument("--dense-counters", nargs="+", metavar="PATH",
+                    help="PROBE_JSON DB...: write profiles/counters_dense_<workload>.txt from rocprofv3 --pmc "
+                         "databases of `bench.py --probe`")
     ap.add_argument("--no-side-by-side", action="store_true",
                     help="skip the second timed region (the step's queries side by side on four lanes)")
     ap.add_argument("--plan-eac", action="store_true", help="paper's uniform E_ac planner")
@@ -877,6 +977,10 @@ def main() -> int:
     if args.mode == "costfit":
         return costfit_mode(args)
 
+    if args.dense_counters:
+        return dense_counters(args)
+    if args.probe:
+        return probe_mode(args)
     if args.counters_summary:
         return counters_summary(args)
 

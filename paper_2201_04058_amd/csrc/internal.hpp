@@ -24,6 +24,7 @@ constexpr int64_t kSplitOps = 65536;   // products per (row, tile) beyond which 
 constexpr int kMaxSplit = 64;
 constexpr int64_t kPartGroup = 4;      // most sparse parts handed out to one dense task
 constexpr int kQueues = 8;             // task counters of the dense kernel
+constexpr int64_t kAlignTiles = 16;    // products with this many column tiles align dense tasks to the counters
 constexpr int kMaxBucketTiles = 4096;  // column tiles a bucketed row may span
 constexpr int kBucketThreads = 512;
 

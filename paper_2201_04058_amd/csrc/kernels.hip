@@ -587,6 +587,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(SymbolicArgs a) {
                 } else {
                     a.dense_split[pos] = (m << 16) | (grp << 8) | 1;
                 }
+                // with many column tiles, every row's task count is padded to a multiple
+                // of kQueues (the extra tasks do nothing): a row's tasks then start at a
+                // multiple of kQueues, task q of a row goes out through counter q mod
+                // kQueues, whose workgroups sit mostly on one XCD, and the tasks of a
+                // column tile (one part per task) gather that tile's slice of Y on one XCD
+                // (its L2) for every row
+                if (ntiles >= kAlignTiles) nch = (nch + kQueues - 1) / kQueues * kQueues;
                 a.dense_chunks[pos] = nch;
             }
         }
