@@ -632,11 +632,11 @@ def dense_counters(args) -> int:
             durs.setdefault(i, []).append(disp[did].pop("_dur") / 1e3)
             per.setdefault(i, {}).update(disp[did])
     lines = [f"# k_dense counters on workload {w}, one k_dense dispatch per row (rocprofv3 --pmc, one group per run)",
-             f"# probe: python3 bench.py --workload {w} --probe > probe_{w}.json"]
+             f"# probe: python3 bench.py --workload {w} --probe > gpurun_out/probe_{w}.json"]
     for z, g in enumerate(DENSE_COUNTER_GROUPS):
         lines.append(f"# group {z + 1}: timeout -s KILL 120 rocprofv3 --pmc {g} -d gpurun_out/pmc_dense{z + 1}_{w} -o run "
                      f"-- python3 bench.py --workload {w} --probe")
-    lines.append(f"# summary: python3 bench.py --dense-counters probe_{w}.json "
+    lines.append(f"# summary: python3 bench.py --dense-counters gpurun_out/probe_{w}.json "
                  + " ".join(f"gpurun_out/pmc_dense{z + 1}_{w}/run_results.db" for z in range(len(DENSE_COUNTER_GROUPS))))
     lines.append("# SQ_* counts are summed over the device; *_CYCLES and SQ_WAIT_* / SQ_ACTIVE_* are wave-cycles of the")
     lines.append("# sequencers (in the same unit, so their ratios hold); TCC_* are L2 requests")
