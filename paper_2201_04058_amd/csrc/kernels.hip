@@ -612,7 +612,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_rows(SymbolicArgs a) {
 // the left / right operand carries values (else every value is 1).
 template <bool XV, bool YV, int NT, int U, typename F>
 __device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
-                                              int32_t tot, const uint64_t *xval, F f, int nb = NT) {
+                                              int32_t tot, const uint64_t *xval, F f, int nb = NT,
+                                              bool plain = false) {
     constexpr int NWV = NT / 64;
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) & (NWV - 1);
     const int32_t chunk = (((tot + NWV - 1) / NWV) + 63) & ~63;
@@ -666,18 +667,21 @@ __device__ __forceinline__ void walk_products(const Operand &Y, const int32_t *s
         for (int u = 0; u < U; ++u) {
             if (item + 64 * u >= end) break;
             if (Y.cmask && !bit_test(Y.cmask, js[u])) continue;
-            f(js[u], YV ? (XV ? sat_mul(xs[u], ys[u]) : ys[u]) : (XV ? xs[u] : 1ull));
+            f(js[u], YV ? (XV ? (plain ? xs[u] * ys[u] : sat_mul(xs[u], ys[u])) : ys[u]) : (XV ? xs[u] : 1ull));
         }
     }
 }
 
 // walk_products for whichever operands carry values
+// (plain: no product can reach 2^63, so values multiply without the
+// saturation check)
 template <int NT, int U = kProdUnroll, typename F>
 __device__ __forceinline__ void walk_products_any(const Operand &Y, const int32_t *seg_o, const int64_t *seg_s,
-                                                  int32_t tot, const uint64_t *xval, F f, int nb = NT) {
+                                                  int32_t tot, const uint64_t *xval, F f, int nb = NT,
+                                                  bool plain = false) {
     if (xval) {
         if (Y.val)
-            walk_products<true, true, NT, U>(Y, seg_o, seg_s, tot, xval, f, nb);
+            walk_products<true, true, NT, U>(Y, seg_o, seg_s, tot, xval, f, nb, plain);
         else
             walk_products<true, false, NT, U>(Y, seg_o, seg_s, tot, xval, f, nb);
     } else {
@@ -1394,8 +1398,8 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(const int32_t *list,
         return tot;
     };
     // visit the flattened products of the current batch: f(column, value)
-    auto products = [&](int64_t tot, int64_t nb, const uint64_t *xval, auto f) {
-        walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f, nb < NT ? (int)nb : NT);
+    auto products = [&](int64_t tot, int64_t nb, const uint64_t *xval, bool plain, auto f) {
+        walk_products_any<NT>(a.Y, seg_o, seg_s, (int32_t)tot, xval, f, nb < NT ? (int)nb : NT, plain);
     };
 
     // tasks from the dense queue (rows of very different cost stay balanced)
@@ -1505,7 +1509,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(const int32_t *list,
                 for (int64_t eb = 0; eb < xlen; eb += NT) {
                     const int64_t tot = single ? ltot : segments(xb, xlen, eb, c0p, c1p, false, false);
                     const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
-                    products(tot, xlen - eb, xval, [&](int32_t j, uint64_t v) {
+                    products(tot, xlen - eb, xval, no_sat, [&](int32_t j, uint64_t v) {
                         const uint32_t k = rank_of(bm, wr, j - c0p);
                         acc_add(&vals[k], satw, k, v);
                     });
@@ -1546,7 +1550,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(const int32_t *list,
                     const int64_t tot = segments(xb, xlen, eb, c0, c1, cursors || keep, cursors);
                     ttot += tot;
                     const uint64_t *xval = a.X.val ? a.X.val + xb + eb : nullptr;
-                    products(tot, xlen - eb, xval, [&](int32_t j, uint64_t v) {
+                    products(tot, xlen - eb, xval, no_sat, [&](int32_t j, uint64_t v) {
                         const uint32_t slot = (uint32_t)(j - c0);
                         if (no_sat)
                             (void)__hip_atomic_fetch_add(&acc[slot], (unsigned long long)v, __ATOMIC_RELAXED,
