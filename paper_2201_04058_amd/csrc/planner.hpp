@@ -36,10 +36,16 @@ struct ColumnHist {
     double total = 0;  // sum of in-degrees
 };
 
+// Default coefficients, in units of one product: a left-operand entry costs a
+// segment set-up (its right row's bounds, a scan slot) worth about a dozen
+// products, a product is mostly an L2-resident gather and one LDS add, a
+// result entry is written and compacted.  Eq. 2 fitted on timed
+// multiplications of random walks puts alpha / beta at about 15 on the
+// scholarly network (beta near 0 on the news network).
 struct CostCoeffs {
     double alpha = 12.0;   // per nonzero of the left operand
-    double beta = 12.0;    // per product (N_op)
-    double gamma = 24.0;   // per nonzero of the result
+    double beta = 1.0;     // per product (N_op)
+    double gamma = 2.0;    // per nonzero of the result
     double delta = 2.0e5;  // fixed cost of one product (launches and synchronisation)
 };
 
