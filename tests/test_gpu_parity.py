@@ -407,6 +407,34 @@ def test_every_kernel_path_under_forced_tunings(atp, oracle_mod, tune, monkeypat
     ctx.close()
 
 
+@pytest.mark.parametrize("tune", [{}, {"ATP_PART_TARGET": "4000"}, {"ATP_PART_HASH_CAP": "0"},
+                                  {"ATP_TILE_INDEX_CAP": "0"}])
+def test_masks_at_the_junction_and_the_end(atp, oracle_mod, tune, monkeypatch):
+    """Id-set constraints on the middle type and on the last type of
+    A-P-X-P-A (a column mask on the root's left operand and on its right
+    operand, so a dense row's slots number fewer than its products and fewer
+    than the columns): sparse parts, dense tiles and rows without the tile
+    index must skip exactly the masked columns and keep their output ranges
+    apart."""
+    for k, v in tune.items():
+        monkeypatch.setenv(k, v)
+    hin, rng = configs.make_hin("scholarly", 0.02)
+    ctx = make_ctx(atp, hin)
+    for mid in ("V", "T"):
+        types = ["A", "P", mid, "P", "A"]
+        n_a, n_m = hin.counts["A"], hin.counts[mid]
+        start = np.sort(rng.choice(n_a, size=min(300, n_a), replace=False)).astype(np.int32)
+        keep_m = np.sort(rng.choice(n_m, size=max(1, n_m // 2), replace=False)).astype(np.int32)
+        keep_a = np.sort(rng.choice(n_a, size=n_a // 3, replace=False)).astype(np.int32)
+        q = Query("-".join(types), types, [Constraint(0, "idset", ids=start), Constraint(2, "idset", ids=keep_m),
+                                            Constraint(4, "idset", ids=keep_a),
+                                            Constraint(1, "range", prop="year", lo=2005, hi=32767)])
+        ref = oracle_mod.eval_full(hin, q, nthreads=8)
+        for plan in (None, "((0,1),(2,3))", "(((0,1),2),3)"):
+            assert_same(ctx.eval_query(q, plan=plan), ref, f"{tune} {q.name} {plan}")
+    ctx.close()
+
+
 def test_profiling_one_kernel(atp, oracle_mod):
     """Timing every launch, then only one kernel's, leaves results as they
     are; the restricted table names only that kernel."""
