@@ -1478,18 +1478,18 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(const int32_t *list,
             const int64_t t1 = (t0 + m < ntiles) ? t0 + m : ntiles;
             const int64_t c0p = t0 * W, c1p = (t1 * W < ycols) ? t1 * W : ycols;
 
-            // part-level product count, when the part may be sparse enough for
-            // the LDS hash (a row whose mean part holds more than twice the
-            // hash capacity goes straight to the dense tiles)
-            const bool may_hash = ks == 1 && (c1p - c0p) <= (int64_t)kPartMaxTiles * W &&
+            // part-level product count, when the part may be sparse enough to
+            // go by column rank (a row whose mean part holds more than twice
+            // the rank capacity goes straight to the dense tiles)
+            const bool may_rank = ks == 1 && (c1p - c0p) <= (int64_t)kPartMaxTiles * W &&
                                   nop_c <= 2 * a.tune.part_hash_cap * nparts;
             int64_t ltot = 0;
-            if (may_hash) {
+            if (may_rank) {
                 for (int64_t eb = 0; eb < xlen; eb += NT) ltot += segments(xb, xlen, eb, c0p, c1p, keep, false);
                 if (ltot == 0) continue;
             }
 
-            if (may_hash && ltot <= a.tune.part_hash_cap) {
+            if (may_rank && ltot <= a.tune.part_hash_cap) {
                 // sparse part, accumulated by column rank: mark, rank the words, add
                 const int nwords = (int)((c1p - c0p + 31) / 32);
                 uint32_t *bm = reinterpret_cast<uint32_t *>(acc);
