@@ -398,7 +398,11 @@ def serve_mode(args) -> int:
                    "whole_hit_rate": round(st["whole_hits"] / max(1, st["queries"]), 3)})
     log(f"served: {served}")
     ctx.close()
-    bad = [z for z in ds if z in dp and ds[z][1] != dp[z][1]]
+    # a size that differs is a wrong result; a status that differs (one path out of device memory,
+    # e.g. with the cache holding part of it, or under another plan) is not
+    both = [z for z in ds if z in dp]
+    bad = [z for z in both if ds[z][0] == 0 and dp[z][0] == 0 and ds[z][1] != dp[z][1]]
+    status_diff = [z for z in both if (ds[z][0] == 0) != (dp[z][0] == 0)]
     checked = _oracle_check(hin, qs, samples) if samples else None
     log(f"oracle check of served results: {checked}")
     out = {"metric": "metapath queries/s + p50/p99 latency (served stream)", "value": served["qps"],
@@ -411,7 +415,9 @@ def serve_mode(args) -> int:
            "served": served, "plain": plain,
            "vs_plain_qps": round(served["qps"] / max(plain["qps"], 1e-9), 3),
            "vs_plain_p99": round(plain["p99_ms"] / max(served["p99_ms"], 1e-9), 3) if plain["p99_ms"] else None,
-           "result_mismatches": len(bad), "oracle_check": checked, "autotuned": tuned, "cost_model": fitted}
+           "result_mismatches": len(bad), "status_differences": len(status_diff),
+           "status_difference_queries": [qs[z].name for z in status_diff][:8],
+           "oracle_check": checked, "autotuned": tuned, "cost_model": fitted}
     print(json.dumps(out), flush=True)
     return 0 if not bad and not (checked and checked["mismatches"]) else 1
 
