@@ -16,11 +16,11 @@ constexpr int kTileW = 1 << kTileShift;
 constexpr int kDenseThreads = 512;
 constexpr int kCursorCap = 512;     // X entries whose cursors fit in LDS (multi-tile chunks)
 constexpr int64_t kTaskOps = 8192;  // target products per dense task
-constexpr int64_t kPartTarget = 2400;  // expected products per part of a sparse long row
+constexpr int64_t kPartTarget = 3600;  // expected products per part of a sparse long row
 constexpr int kRankCap = 4096;         // most products of a part accumulated by column rank
 constexpr int64_t kPartHashCap = kRankCap;  // default part_hash_cap: parts of at most this many products go by rank
 constexpr int kPartMaxTiles = 16;      // ... if it spans at most this many tiles (its presence bitmap)
-constexpr int64_t kSplitOps = 65536;   // products per (row, tile) beyond which the row's entries are split
+constexpr int64_t kSplitOps = 16384;   // products per (row, tile) beyond which the row's entries are split
 constexpr int kMaxSplit = 64;
 constexpr int64_t kPartGroup = 4;      // most sparse parts handed out to one dense task
 constexpr int kQueues = 8;             // task counters of the dense kernel
