@@ -1711,20 +1711,25 @@ __device__ __forceinline__ int64_t bucket_part_tiles(int64_t nop, int64_t ntiles
 
 constexpr int kBucketUnroll = 2;  // products per lane per step of the bucket passes' walk
 
-// Products of X entries [e0, e1) of one row in batches of kBucketThreads
-// entries, walked flattened: f(column, value) for each.
+// Products of X entries [e0, e1) of one row, f(column, value) for each: every
+// wavefront takes batches of 64 consecutive entries in turn (its batches are
+// kBucketThreads entries apart) and walks each batch's products flattened,
+// with no workgroup barrier between batches.  seg_s holds 64 and seg_o 65
+// entries per wavefront.
 template <typename F>
 __device__ __forceinline__ void walk_entry_range(const NumericArgs &a, int64_t e0, int64_t e1, int64_t *seg_s,
-                                                 int32_t *seg_o, int64_t *sw, F f) {
-    for (int64_t eb = e0; eb < e1; eb += kBucketThreads) {
-        const int64_t nb = (e1 - eb < kBucketThreads) ? e1 - eb : kBucketThreads;
-        const int64_t tot = row_segments<kBucketThreads>(a.X, a.Y, eb, nb, seg_s, seg_o, sw);
+                                                 int32_t *seg_o, F f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t *ws = seg_s + wave * 64;
+    int32_t *wo = seg_o + wave * 65;
+    for (int64_t eb = e0 + (int64_t)wave * 64; eb < e1; eb += kBucketThreads) {
+        const int64_t nb = (e1 - eb < 64) ? e1 - eb : 64;
+        const int64_t tot = row_segments<64>(a.X, a.Y, eb, nb, ws, wo, nullptr);
         if (tot < kWalkMax) {
-            walk_products_any<kBucketThreads, kBucketUnroll>(a.Y, seg_o, seg_s, (int32_t)tot,
-                                                              a.X.val ? a.X.val + eb : nullptr, f, (int)nb);
+            walk_products_any<64, kBucketUnroll>(a.Y, wo, ws, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr, f,
+                                                 (int)nb);
         } else {
-            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-            for (int64_t e = eb + wave; e < eb + nb; e += kBucketThreads / 64) {
+            for (int64_t e = eb; e < eb + nb; ++e) {
                 const int32_t k = a.X.col[e];
                 if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
                 const uint64_t xv = a.X.val ? a.X.val[e] : 1ull;
@@ -1735,15 +1740,14 @@ __device__ __forceinline__ void walk_entry_range(const NumericArgs &a, int64_t e
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, NumericArgs a) {
     __shared__ int32_t hist[kMaxBucketTiles];
     __shared__ int64_t seg_s[kBucketThreads];
-    __shared__ int32_t seg_o[kBucketThreads + 1];
-    __shared__ int64_t sw[kBucketThreads / 64];
+    __shared__ int32_t seg_o[kBucketThreads / 64 * 65];
     for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
         int64_t p, q;
         bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
@@ -1759,7 +1763,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, N
                 if (r.head) atomicAdd(&hist[tile], r.len);
             });
         else
-            walk_entry_range(a, e0, e1, seg_s, seg_o, sw,
+            walk_entry_range(a, e0, e1, seg_s, seg_o,
                              [&](int32_t j, uint64_t) { atomicAdd(&hist[j >> kTileShift], 1); });
         __syncthreads();
         int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
@@ -1771,48 +1775,96 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, N
     }
 }
 
-// per bucket row: tile_off = prod_base + exclusive scan of the tile counts; counts become cursors.
-// With per-chunk counts, each chunk's count of a tile becomes the chunk's base in that bucket (the
-// tile's offset plus the counts of the row's earlier chunks).
-__global__ __launch_bounds__(256) void k_bucket_scan(BucketArgs b, Tuning tune) {
-    __shared__ int64_t sw[4];
-    for (int64_t p = blockIdx.x; p < b.n_list; p += gridDim.x) {
-        if (threadIdx.x == 0) {
+// per bucket row: tile_off = prod_base + exclusive scan of the tile counts.
+// Without per-chunk counts: one workgroup per row, and the counts become the
+// scatter's cursors.  With per-chunk counts, each chunk's count of a tile
+// becomes the chunk's base in that bucket (the tile's offset plus the counts
+// of the row's earlier chunks): a row's tiles are spread over workgroups of
+// kBucketScanThreads tiles (each scans the row's counts up to its own tiles),
+// and when a workgroup has fewer tiles than threads, each tile's chunks are
+// split over a group of threads (a sum per thread, a scan across the group,
+// then a second pass that writes the bases).
+constexpr int kBucketScanThreads = 256;
+constexpr int kBucketScanLoads = 16;  // chunk counts loaded together
+
+__global__ __launch_bounds__(kBucketScanThreads) void k_bucket_scan(BucketArgs b, Tuning tune) {
+    constexpr int NT = kBucketScanThreads, U = kBucketScanLoads;
+    __shared__ int64_t sw[NT / 64];
+    __shared__ int64_t s_off[NT];
+    __shared__ int64_t s_inc[NT];
+    const int tid = threadIdx.x;
+    const int64_t tbn = b.chunk_hist ? (b.ntiles + NT - 1) / NT : 1;  // workgroups per row
+    for (int64_t id = blockIdx.x; id < b.n_list * tbn; id += gridDim.x) {
+        const int64_t p = id / tbn, tb = id - p * tbn;
+        if (tb == 0 && tid == 0) {
             const int64_t m = bucket_part_tiles(b.prod_base[p + 1] - b.prod_base[p], b.ntiles, tune);
             b.part_cnt[p] = (b.ntiles + m - 1) / m;
         }
         int64_t *cnt = b.tile_cnt + p * (b.ntiles + 1);
         int64_t *off = b.tile_off + p * (b.ntiles + 1);
+        // tiles [0, t_end): up to this workgroup's own tiles (all of them in the
+        // row's last workgroup, which writes the total)
+        const int64_t t_end = (tb == tbn - 1) ? b.ntiles : (tb + 1) * NT;
         int64_t carry = b.prod_base[p];
-        for (int64_t base = 0; base < b.ntiles; base += blockDim.x) {
-            int64_t t = base + threadIdx.x;
-            int64_t x = t < b.ntiles ? cnt[t] : 0;
+        for (int64_t base = 0; base < t_end; base += NT) {
+            const int64_t t = base + tid;
+            const int64_t x = t < b.ntiles ? cnt[t] : 0;
             int64_t tot;
-            int64_t inc = block_inclusive_scan(x, sw, &tot);
-            if (t < b.ntiles) {
-                off[t] = carry + inc - x;
-                cnt[t] = carry + inc - x;
+            const int64_t inc = block_inclusive_scan(x, sw, &tot);
+            if (base >= tb * NT) {  // own tiles (with one workgroup per row: every pass)
+                const int64_t o = carry + inc - x;
+                s_off[tid] = o;
+                if (t < b.ntiles) {
+                    off[t] = o;
+                    if (!b.chunk_hist) cnt[t] = o;
+                }
             }
             carry += tot;
         }
-        if (threadIdx.x == 0) off[b.ntiles] = carry;
+        if (tb == tbn - 1 && tid == 0) off[b.ntiles] = carry;
         __syncthreads();
-        if (b.chunk_hist) {
-            const int64_t q0 = b.chunk_base[p], q1 = b.chunk_base[p + 1];
-            for (int64_t t = threadIdx.x; t < b.ntiles; t += blockDim.x) {
-                int64_t run = off[t];
-                for (int64_t q = q0; q < q1; q += 8) {  // eight chunks' counts loaded together
-                    int64_t v[8];
+        if (b.chunk_hist) {  // tbn > 1 only with chunk counts: s_off holds this workgroup's tiles
+            const int64_t q0 = b.chunk_base[p], q1 = b.chunk_base[p + 1], nq = q1 - q0;
+            const int64_t own = (b.ntiles - tb * NT < NT) ? b.ntiles - tb * NT : NT;
+            int g = 1;  // threads per tile (uniform)
+            while (2 * g * own <= NT && 2 * g <= nq) g *= 2;
+            const int lt = tid / g, r = tid & (g - 1);
+            const bool live = lt < own;
+            const int64_t t = tb * NT + lt;
+            const int64_t per = (nq + g - 1) / g;
+            const int64_t qa = q0 + r * per < q1 ? q0 + r * per : q1;
+            const int64_t qz = qa + per < q1 ? qa + per : q1;
+            int64_t run = live ? s_off[lt] : 0;
+            if (g > 1) {  // the counts of the group's earlier threads
+                int64_t sum = 0;
+                if (live)
+                    for (int64_t q = qa; q < qz; q += U) {
+                        int64_t v[U];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) v[u] = q + u < q1 ? b.chunk_hist[(q + u) * b.ntiles + t] : 0;
+                        for (int u = 0; u < U; ++u) v[u] = q + u < qz ? b.chunk_hist[(q + u) * b.ntiles + t] : 0;
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        if (q + u < q1) b.chunk_hist[(q + u) * b.ntiles + t] = run;
+                        for (int u = 0; u < U; ++u) sum += v[u];
+                    }
+                int64_t tot;
+                const int64_t inc = block_inclusive_scan(sum, sw, &tot);
+                s_inc[tid] = inc;
+                __syncthreads();
+                const int g0 = tid & ~(g - 1);
+                run += inc - sum - (g0 > 0 ? s_inc[g0 - 1] : 0);
+            }
+            if (live)
+                for (int64_t q = qa; q < qz; q += U) {
+                    int64_t v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) v[u] = q + u < qz ? b.chunk_hist[(q + u) * b.ntiles + t] : 0;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (q + u < qz) b.chunk_hist[(q + u) * b.ntiles + t] = run;
                         run += v[u];
                     }
                 }
-            }
         }
+        __syncthreads();  // LDS reuse by the next row
     }
 }
 
@@ -1820,8 +1872,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
     __shared__ int32_t hist[kMaxBucketTiles];
     __shared__ int64_t base[kMaxBucketTiles];
     __shared__ int64_t seg_s[kBucketThreads];
-    __shared__ int32_t seg_o[kBucketThreads + 1];
-    __shared__ int64_t sw[kBucketThreads / 64];
+    __shared__ int32_t seg_o[kBucketThreads / 64 * 65];
     for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
         int64_t p, q;
         bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
@@ -1845,7 +1896,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
                                      if (r.head) atomicAdd(&hist[tile], r.len);
                                  });
             else
-                walk_entry_range(a, e0, e1, seg_s, seg_o, sw,
+                walk_entry_range(a, e0, e1, seg_s, seg_o,
                                  [&](int32_t j, uint64_t) { atomicAdd(&hist[j >> kTileShift], 1); });
             __syncthreads();
             int64_t *cur = b.tile_cnt + p * (b.ntiles + 1);
@@ -1870,7 +1921,7 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
                 }
             });
         else
-            walk_entry_range(a, e0, e1, seg_s, seg_o, sw, [&](int32_t j, uint64_t v) {
+            walk_entry_range(a, e0, e1, seg_s, seg_o, [&](int32_t j, uint64_t v) {
                 const int32_t tile = j >> kTileShift;
                 const int64_t pos = base[tile] + atomicAdd(&hist[tile], 1);
                 b.prod_col[pos] = j;
@@ -2392,8 +2443,9 @@ void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *c
     const int cus = device_cus();
     const int64_t gc = n_chunks < (int64_t)cus * 4 ? n_chunks : (int64_t)cus * 4;
     ATP_LAUNCH("bucket", 0, 0, s, k_bucket_count, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);
-    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scan, dim3((unsigned)(n_list < 1024 ? n_list : 1024)), dim3(256), 0, s, b,
-               a.tune);
+    const int64_t gs_n = n_list * (chunk_hist ? (ntiles + kBucketScanThreads - 1) / kBucketScanThreads : 1);
+    const int64_t gs = gs_n < (int64_t)cus * 8 ? gs_n : (int64_t)cus * 8;
+    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scan, dim3((unsigned)gs), dim3(kBucketScanThreads), 0, s, b, a.tune);
     launch_scan_i64(b.part_cnt, b.part_base, n_list, b.part_base + n_list + 1, s, t);
     ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scatter, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);
     const int64_t n_tasks = n_list * ntiles;
