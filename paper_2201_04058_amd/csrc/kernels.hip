@@ -1931,6 +1931,30 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
     }
 }
 
+constexpr int kBucketAccLoads = 4;  // bucket entries per thread loaded together
+
+// f(column, value) for bucket entries [lo, hi), kDenseThreads threads, each
+// loading kBucketAccLoads entries before applying them (a heavy row's tile
+// holds up to ~10^6 entries, walked by one workgroup); value 1 when !valued.
+template <typename F>
+__device__ __forceinline__ void bucket_products(const BucketArgs &b, int64_t lo, int64_t hi, bool valued, F f) {
+    constexpr int U = kBucketAccLoads;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += (int64_t)kDenseThreads * U) {
+        int32_t js[U];
+        uint64_t vs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t x = e + (int64_t)kDenseThreads * u;
+            const int64_t y = x < hi ? x : e;  // past the range: repeat the first (in bounds), not applied
+            js[u] = b.prod_col[y];
+            vs[u] = valued ? b.prod_val[y] : 1ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e + (int64_t)kDenseThreads * u < hi) f(js[u], vs[u]);
+    }
+}
+
 __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs b, NumericArgs a) {
     constexpr int W = kTileW;
     constexpr int NW = W / 32;
@@ -1977,16 +2001,16 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
             uint32_t *bm = reinterpret_cast<uint32_t *>(acc);
             uint16_t *wr = reinterpret_cast<uint16_t *>(acc + kRankWrOff);
             unsigned long long *vals = acc + kRankValOff;
-            for (int64_t e = off[t] + tid; e < off[t1]; e += kDenseThreads) {
-                const int64_t r = b.prod_col[e] - c0p;
+            bucket_products(b, off[t], off[t1], false, [&](int32_t j, uint64_t) {
+                const int64_t r = j - c0p;
                 atomicOr(&bm[r >> 5], 1u << (r & 31));
-            }
+            });
             __syncthreads();
             const int64_t cnt = rank_words<kDenseThreads>(bm, wr, nwords, sw);
-            for (int64_t e = off[t] + tid; e < off[t1]; e += kDenseThreads) {
-                const uint32_t k = rank_of(bm, wr, b.prod_col[e] - c0p);
-                acc_add(&vals[k], satw, k, valued ? b.prod_val[e] : 1ull);
-            }
+            bucket_products(b, off[t], off[t1], valued, [&](int32_t j, uint64_t v) {
+                const uint32_t k = rank_of(bm, wr, j - c0p);
+                acc_add(&vals[k], satw, k, v);
+            });
             __syncthreads();
             emit_rank_part<kDenseThreads>(a, c, i, t, c0p, nwords, cnt, bm, wr, vals, satw, &s_base, &s_sat, -1);
             continue;
@@ -1996,12 +2020,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
             if (lo == hi) continue;  // uniform across the block
             const int64_t c0 = tt * W;
             const bool sparse = (hi - lo) < (int64_t)(W / 4);  // block-uniform
-            for (int64_t e = lo + tid; e < hi; e += kDenseThreads) {
-                const uint32_t slot = (uint32_t)(b.prod_col[e] - c0);
-                const uint64_t v = valued ? b.prod_val[e] : 1ull;
+            bucket_products(b, lo, hi, valued, [&](int32_t j, uint64_t v) {
+                const uint32_t slot = (uint32_t)(j - c0);
                 if (sparse) atomicOr(&pres[slot >> 5], 1u << (slot & 31));
                 acc_add(&acc[slot], satw, slot, v);
-            }
+            });
             __syncthreads();
             if (sparse)
                 emit_sparse_tile(a, c, i, tt, c0, acc, pres, satw, sw, &s_base, &s_sat);
