@@ -59,7 +59,7 @@ struct Tuning {
     int64_t bucket_pct = 400;  // bucket a row when left entries x tiles x 100 > pct x products
     int64_t split_ops = kSplitOps;
     int64_t wg_slots = 512;    // resident dense workgroups (2 per compute unit)
-    int64_t bucket_chunk = 4096;  // left-operand entries per bucketing work item
+    int64_t bucket_chunk = 8192;  // left-operand entries per bucketing work item
 };
 
 // Per-step device scratch header read back by the host (one small copy).
