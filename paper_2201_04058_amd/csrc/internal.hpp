@@ -104,6 +104,8 @@ void launch_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, h
 // kSmallScanTiles * 2048 elements the sequence is a single launch.
 constexpr int kMaxScanJobs = 8;
 constexpr int64_t kSmallScanTiles = 8;
+// up to this many tiles, the tile sums are added up by each tile (two launches instead of three)
+constexpr int64_t kScanFoldTiles = 1024;
 struct ScanJob {
     const int64_t *in;
     int64_t *out;    // n + 1 entries

@@ -309,6 +309,28 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(ScanJobs sj, const i
     }
 }
 
+// As k_scan_down after k_scan_top, from the raw tile sums of k_scan_reduce:
+// each block adds up the sums of the tiles before it (block 0: of every
+// tile, the total) instead of a separate scan of the sums.  For at most
+// kScanFoldTiles tiles, so that the re-read sums stay few.
+__global__ __launch_bounds__(kScanThreads) void k_scan_down_fold(ScanJobs sj, const int64_t *tmp) {
+    __shared__ int64_t sw[kScanThreads / 64];
+    const ScanJob &j = sj.job[blockIdx.y];
+    const int64_t nb = scan_blocks(j.n);
+    if ((int64_t)blockIdx.x >= nb) return;  // uniform
+    const int64_t *t = tmp + blockIdx.y * sj.stride;
+    const int64_t upto = blockIdx.x == 0 ? nb : (int64_t)blockIdx.x;
+    int64_t x = 0;
+    for (int64_t i = threadIdx.x; i < upto; i += kScanThreads) x += t[i];
+    int64_t sum;
+    block_inclusive_scan(x, sw, &sum);  // its closing barrier frees sw for the tile scan
+    scan_tile(j, j.n, (int64_t)blockIdx.x * kScanTile, blockIdx.x == 0 ? 0 : sum, sw);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        j.out[j.n] = sum;
+        if (j.total) *j.total = sum;
+    }
+}
+
 // short arrays: one block per job walks its tiles with a running carry
 __global__ __launch_bounds__(kScanThreads) void k_scan_small(ScanJobs sj) {
     __shared__ int64_t sw[kScanThreads / 64];
@@ -2333,6 +2355,11 @@ void launch_scan_multi(const ScanJob *jobs, int n_jobs, int64_t *tmp, hipStream_
     }
     ATP_LAUNCH("scan", 0, 0, s, k_scan_reduce, dim3((unsigned)nb, (unsigned)n_jobs), dim3(kScanThreads), 0, s, sj,
                tmp);
+    if (nb <= kScanFoldTiles) {
+        ATP_LAUNCH("scan", 0, 0, s, k_scan_down_fold, dim3((unsigned)nb, (unsigned)n_jobs), dim3(kScanThreads), 0, s,
+                   sj, (const int64_t *)tmp);
+        return;
+    }
     ATP_LAUNCH("scan", 0, 0, s, k_scan_top, dim3((unsigned)n_jobs), dim3(kScanThreads), 0, s, sj, tmp);
     ATP_LAUNCH("scan", 0, 0, s, k_scan_down, dim3((unsigned)nb, (unsigned)n_jobs), dim3(kScanThreads), 0, s, sj,
                (const int64_t *)tmp);
