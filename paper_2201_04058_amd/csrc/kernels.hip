@@ -1736,26 +1736,56 @@ constexpr int kBucketUnroll = 2;  // products per lane per step of the bucket pa
 // Products of X entries [e0, e1) of one row, f(column, value) for each: every
 // wavefront takes batches of 64 consecutive entries in turn (its batches are
 // kBucketThreads entries apart) and walks each batch's products flattened,
-// with no workgroup barrier between batches.  seg_s holds 64 and seg_o 65
-// entries per wavefront.
+// with no workgroup barrier between batches.  The batch set-up is pipelined:
+// a batch's left columns are loaded two batches ahead and their column-mask
+// words one batch ahead, so that only the right row bounds and the walk's
+// gathers wait within a batch.  seg_s holds 64 and seg_o 65 entries per
+// wavefront.
 template <typename F>
 __device__ __forceinline__ void walk_entry_range(const NumericArgs &a, int64_t e0, int64_t e1, int64_t *seg_s,
                                                  int32_t *seg_o, F f) {
+    constexpr int64_t B = kBucketThreads;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t *ws = seg_s + wave * 64;
     int32_t *wo = seg_o + wave * 65;
-    for (int64_t eb = e0 + (int64_t)wave * 64; eb < e1; eb += kBucketThreads) {
+    const uint32_t *cm = a.X.cmask;
+    int64_t eb = e0 + (int64_t)wave * 64;
+    // stages (an entry past e1 reads column 0, in bounds, and is not used)
+    int32_t k0 = eb + lane < e1 ? a.X.col[eb + lane] : 0;          // this batch's columns
+    int32_t k1 = eb + B + lane < e1 ? a.X.col[eb + B + lane] : 0;  // the next batch's
+    uint32_t w0 = cm ? cm[k0 >> 5] : ~0u;                          // this batch's mask words
+    for (; eb < e1; eb += B) {
         const int64_t nb = (e1 - eb < 64) ? e1 - eb : 64;
-        const int64_t tot = row_segments<64>(a.X, a.Y, eb, nb, ws, wo, nullptr);
+        const int32_t k = k0;
+        const uint32_t w = w0;
+        w0 = cm ? cm[k1 >> 5] : ~0u;
+        k0 = k1;
+        k1 = eb + 2 * B + lane < e1 ? a.X.col[eb + 2 * B + lane] : 0;
+        int64_t len = 0;
+        if (lane < nb && ((w >> (k & 31)) & 1u)) {
+            const int64_t yb = a.Y.rp[k];
+            len = a.Y.rp[k + 1] - yb;
+            ws[lane] = yb;
+        }
+        int64_t inc = len;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t o = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += o;
+        }
+        const int64_t tot = __shfl(inc, 63, 64);
+        wo[lane] = (int32_t)(inc - len);
+        if (lane == 63) wo[64] = (int32_t)inc;
+        wave_sync();
         if (tot < kWalkMax) {
             walk_products_any<64, kBucketUnroll>(a.Y, wo, ws, (int32_t)tot, a.X.val ? a.X.val + eb : nullptr, f,
                                                  (int)nb);
         } else {
             for (int64_t e = eb; e < eb + nb; ++e) {
-                const int32_t k = a.X.col[e];
-                if (a.X.cmask && !bit_test(a.X.cmask, k)) continue;
+                const int32_t kk = a.X.col[e];
+                if (cm && !bit_test(cm, kk)) continue;
                 const uint64_t xv = a.X.val ? a.X.val[e] : 1ull;
-                for (int64_t fpos = a.Y.rp[k] + lane; fpos < a.Y.rp[k + 1]; fpos += 64) {
+                for (int64_t fpos = a.Y.rp[kk] + lane; fpos < a.Y.rp[kk + 1]; fpos += 64) {
                     const int32_t j = a.Y.col[fpos];
                     if (a.Y.cmask && !bit_test(a.Y.cmask, j)) continue;
                     f(j, a.Y.val ? sat_mul(xv, a.Y.val[fpos]) : xv);
@@ -1890,9 +1920,12 @@ __global__ __launch_bounds__(kBucketScanThreads) void k_bucket_scan(BucketArgs b
     }
 }
 
+// dynamic LDS: base[ntiles] (int64), then hist[ntiles] (int32), sized to the
+// product's tiles (at most kMaxBucketTiles) so that more workgroups fit a CU
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b, NumericArgs a) {
-    __shared__ int32_t hist[kMaxBucketTiles];
-    __shared__ int64_t base[kMaxBucketTiles];
+    extern __shared__ int64_t scatter_lds[];
+    int64_t *base = scatter_lds;
+    int32_t *hist = reinterpret_cast<int32_t *>(scatter_lds + b.ntiles);
     __shared__ int64_t seg_s[kBucketThreads];
     __shared__ int32_t seg_o[kBucketThreads / 64 * 65];
     for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
@@ -2497,7 +2530,8 @@ void launch_numeric_bucket(const int32_t *list, int64_t n_list, const int64_t *c
     const int64_t gs = gs_n < (int64_t)cus * 8 ? gs_n : (int64_t)cus * 8;
     ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scan, dim3((unsigned)gs), dim3(kBucketScanThreads), 0, s, b, a.tune);
     launch_scan_i64(b.part_cnt, b.part_base, n_list, b.part_base + n_list + 1, s, t);
-    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scatter, dim3((unsigned)gc), dim3(kBucketThreads), 0, s, b, a);
+    ATP_LAUNCH("bucket", 0, 0, s, k_bucket_scatter, dim3((unsigned)gc), dim3(kBucketThreads),
+               (unsigned)(12 * ntiles), s, b, a);
     const int64_t n_tasks = n_list * ntiles;
     const int64_t ga = n_tasks < (int64_t)cus * 2 ? n_tasks : (int64_t)cus * 2;
     ATP_LAUNCH("bucket_acc", 0, 0, s, k_bucket_accumulate, dim3((unsigned)ga), dim3(kDenseThreads), 0, s, b, a);
