@@ -1624,19 +1624,17 @@ __global__ __launch_bounds__(256) void k_tile_index(Operand Y, int64_t ntiles, i
 // column tiles.  Their products are generated once, counting-sorted into
 // column-tile buckets, and each bucket is accumulated in a dense LDS tile.
 
-// chunk id -> (bucket list position, chunk index)
-__device__ __forceinline__ void bucket_chunk(const int64_t *chunk_base, int64_t n_list, int64_t id, int64_t *p,
-                                             int64_t *q) {
-    int64_t lo = 0, hi = n_list;
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (chunk_base[mid] <= id)
-            lo = mid;
-        else
-            hi = mid;
+// Last p in [0, n) with base[p] <= key (base[0] <= key), found by the first
+// wavefront (a 64-ary search: a few dependent loads instead of log2 n) and
+// handed to the workgroup through *slot.  Every thread calls it; the caller
+// keeps the slot from being rewritten before every thread has read it.
+__device__ __forceinline__ int64_t block_find_row(const int64_t *base, int64_t n, int64_t key, int64_t *slot) {
+    if (threadIdx.x < 64) {
+        const int64_t p = group_lower_bound(base, 0, n, key + 1, 64, (int)threadIdx.x, ~0ull) - 1;
+        if (threadIdx.x == 0) *slot = p;
     }
-    *p = lo;
-    *q = id - chunk_base[lo];
+    __syncthreads();
+    return *slot;
 }
 
 // Runs of one lane group: consecutive active lanes whose products fall into
@@ -1798,11 +1796,12 @@ __device__ __forceinline__ void walk_entry_range(const NumericArgs &a, int64_t e
 
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(BucketArgs b, NumericArgs a) {
     __shared__ int32_t hist[kMaxBucketTiles];
+    __shared__ int64_t s_row;
     __shared__ int64_t seg_s[kBucketThreads];
     __shared__ int32_t seg_o[kBucketThreads / 64 * 65];
-    for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
-        int64_t p, q;
-        bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
+    for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {  // the body ends with a barrier
+        const int64_t p = block_find_row(b.chunk_base, b.n_list, id, &s_row);
+        const int64_t q = id - b.chunk_base[p];
         const int32_t c = b.list[p];
         const int64_t i = a.cand ? a.cand[c] : c;
         const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
@@ -1926,11 +1925,12 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(BucketArgs b,
     extern __shared__ int64_t scatter_lds[];
     int64_t *base = scatter_lds;
     int32_t *hist = reinterpret_cast<int32_t *>(scatter_lds + b.ntiles);
+    __shared__ int64_t s_row;
     __shared__ int64_t seg_s[kBucketThreads];
     __shared__ int32_t seg_o[kBucketThreads / 64 * 65];
-    for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {
-        int64_t p, q;
-        bucket_chunk(b.chunk_base, b.n_list, id, &p, &q);
+    for (int64_t id = blockIdx.x; id < b.n_chunks; id += gridDim.x) {  // the body ends with a barrier
+        const int64_t p = block_find_row(b.chunk_base, b.n_list, id, &s_row);
+        const int64_t q = id - b.chunk_base[p];
         const int32_t c = b.list[p];
         const int64_t i = a.cand ? a.cand[c] : c;
         const int64_t xb = a.X.rp[i], xe = a.X.rp[i + 1];
@@ -2019,6 +2019,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
     __shared__ int32_t gcnt[W / 64];
     __shared__ int64_t sw[kDenseThreads / 64];
     __shared__ int64_t s_base;
+    __shared__ int64_t s_rows[2];
     __shared__ int s_sat;
     const int tid = threadIdx.x;
     for (int t = tid; t < W; t += kDenseThreads) acc[t] = 0;
@@ -2032,16 +2033,9 @@ __global__ __launch_bounds__(kDenseThreads) void k_bucket_accumulate(BucketArgs 
     // mean products per tile); part_base enumerates them
     const int64_t n_tasks = b.part_base[b.n_list];
     const bool valued = b.prod_val != nullptr;
-    for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
-        int64_t lo = 0, hi = b.n_list;  // last p with part_base[p] <= task
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (b.part_base[mid] <= task)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const int64_t p = lo;
+    int parity = 0;  // the row slot alternates: a task may end without a barrier
+    for (int64_t task = blockIdx.x; task < n_tasks; task += gridDim.x, parity ^= 1) {
+        const int64_t p = block_find_row(b.part_base, b.n_list, task, &s_rows[parity]);
         const int64_t m = bucket_part_tiles(b.prod_base[p + 1] - b.prod_base[p], b.ntiles, a.tune);
         const int64_t t = (task - b.part_base[p]) * m;
         const int64_t t1 = (t + m < b.ntiles) ? t + m : b.ntiles;
