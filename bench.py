@@ -193,6 +193,17 @@ def batch_mode(args) -> int:
     hin, _ = configs.load(args.workload)
     qs = workload.random_walk_batch(hin, 3, args.queries, start_sizes=(args.start_min, args.start_max))
     ctx = _ctx_with_network(atp, hin)
+    # the planner's coefficients and the tunables are set before both runs, so
+    # that both evaluate the same plans with the same kernels
+    tuned = fitted = None
+    if args.calibrate:  # Eq. 2 coefficients fitted on walks of another seed
+        fitted = ctx.calibrate_cost_model(
+            workload.random_walk_batch(hin, 21, args.tune_queries, start_sizes=(args.start_min, args.start_max)))
+        log(f"cost model: {fitted}")
+    if args.autotune:  # on queries of another seed, not the measured ones
+        sample = workload.random_walk_batch(hin, 13, args.tune_queries, start_sizes=(args.start_min, args.start_max))
+        tuned = ctx.autotune(sample)
+        log(f"autotuned: {tuned}")
     for q in qs[:8]:  # warm-up (a query larger than the device memory fails here as in the runs)
         try:
             ctx.eval_query(q).free()
@@ -213,15 +224,6 @@ def batch_mode(args) -> int:
             log(f"  one at a time: {z + 1} of {len(qs)} done, {time.perf_counter() - t0:.1f} s")
     t_plain = time.perf_counter() - t0
     log(f"one at a time: {len(qs)} queries in {t_plain:.2f} s")
-    tuned = fitted = None
-    if args.calibrate:  # Eq. 2 coefficients fitted on walks of another seed
-        fitted = ctx.calibrate_cost_model(
-            workload.random_walk_batch(hin, 21, args.tune_queries, start_sizes=(args.start_min, args.start_max)))
-        log(f"cost model: {fitted}")
-    if args.autotune:  # on queries of another seed, not the measured ones
-        sample = workload.random_walk_batch(hin, 13, args.tune_queries, start_sizes=(args.start_min, args.start_max))
-        tuned = ctx.autotune(sample)
-        log(f"autotuned: {tuned}")
     ctx.eval_batch(qs[:8], lanes=args.lanes, max_batch=args.max_batch)
     t0 = time.perf_counter()
     bad, status_diff = [], []
@@ -366,16 +368,7 @@ def serve_mode(args) -> int:
         gaps = np.random.default_rng(4).exponential(1.0 / args.qps, size=len(qs))
         arrivals = np.cumsum(gaps) - gaps[0]
     ctx = _ctx_with_network(atp, hin)
-    for q in qs[:8]:  # warm-up (a query larger than the device memory fails here as in the runs)
-        try:
-            ctx.eval_query(q).free()
-        except atp.AtpError:
-            pass
-    plain, dp = {"qps": 0.0, "p99_ms": None}, {}
-    if not args.no_plain:
-        log(f"plain path: {len(qs)} queries at {args.qps} QPS")
-        plain, dp, _ = _serve(atp, ctx, arrivals, qs, 1, 1, 0, args.cap_s)
-        log(f"plain: {plain}")
+    # the planner's coefficients and the tunables are set before both paths run
     tuned = fitted = None
     if args.calibrate:  # Eq. 2 coefficients fitted on a stream of another seed
         _, sample = workload.serving_stream(hin, 6, args.tune_queries, start_sizes=(args.start_min, args.start_max),
@@ -387,6 +380,16 @@ def serve_mode(args) -> int:
                                             pool=args.pool)
         tuned = ctx.autotune(sample)
         log(f"autotuned: {tuned}")
+    for q in qs[:8]:  # warm-up (a query larger than the device memory fails here as in the runs)
+        try:
+            ctx.eval_query(q).free()
+        except atp.AtpError:
+            pass
+    plain, dp = {"qps": 0.0, "p99_ms": None}, {}
+    if not args.no_plain:
+        log(f"plain path: {len(qs)} queries at {args.qps} QPS")
+        plain, dp, _ = _serve(atp, ctx, arrivals, qs, 1, 1, 0, args.cap_s)
+        log(f"plain: {plain}")
     if args.cache_gb > 0:
         ctx.cache_configure(atp.ATP_CACHE_OTREE, int(args.cache_gb * (1 << 30)))
     log(f"served: lanes {args.lanes}, max batch {args.max_batch}, cache {args.cache_gb} GB")
