@@ -1489,7 +1489,7 @@ atp_status lane_init(atp_ctx *c, Lane *L, int id) {
     // each lane has its own pool: a block it frees is reused only by later work on its own stream,
     // which is ordered after the work that used the block
     L->pool.on_oom = [c]() { release_pool_caches(c); };
-    L->pool.cache_limit = c->lane_cache_limit;
+    L->pool.cache_limit = c->pool_cache_total;  // until ensure_lanes shares it out
     L->pool.budget = c->main.pool.budget;
     L->pool.user_alloc = c->main.pool.user_alloc;
     L->pool.user_free = c->main.pool.user_free;
@@ -1623,17 +1623,14 @@ atp_status atp_create(const atp_options *o, atp_ctx **out) {
     c->main.pool.user = d.alloc_user;
     c->main.pool.budget = d.mem_budget_bytes;
     c->main.pool.on_oom = [c]() { release_pool_caches(c); };
-    {  // the main pool may keep up to half the device's memory in free blocks, each lane's an eighth
+    {  // free blocks kept for reuse: up to half the device's memory
         size_t fr = 0, total = 0;
-        if (hipMemGetInfo(&fr, &total) == hipSuccess && total > 0) {
-            c->main_cache_limit = std::max<size_t>(c->main_cache_limit, total / 2);
-            c->lane_cache_limit = std::max<size_t>(c->lane_cache_limit, total / 8);
-        }
+        if (hipMemGetInfo(&fr, &total) == hipSuccess && total > 0)
+            c->pool_cache_total = std::max<size_t>(c->pool_cache_total, total / 2);
         (void)hipGetLastError();
-        if (const char *e = std::getenv("ATP_POOL_CACHE_GB")) {  // diagnostics: both limits
-            c->main_cache_limit = c->lane_cache_limit = (size_t)(std::atof(e) * (double)(1ull << 30));
-        }
-        c->main.pool.cache_limit = c->main_cache_limit;
+        if (const char *e = std::getenv("ATP_POOL_CACHE_GB"))  // diagnostics
+            c->pool_cache_total = (size_t)(std::atof(e) * (double)(1ull << 30));
+        c->main.pool.cache_limit = c->pool_cache_total;
     }
     c->main.wait_limit_s = c->wait_limit_s;
     // the static workspace of atp_eval_noalloc on this device (looked up once per device)

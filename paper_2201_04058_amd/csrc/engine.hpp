@@ -465,10 +465,11 @@ struct atp_ctx {
     bool step_names = std::getenv("ATP_PROFILE_STEPS") != nullptr;  // diagnostics: kernel names per product
     atp::Tuning tune = atp::tuning_from_env();
     atp::MemGate gate;
-    // free blocks a pool keeps for reuse (set from the device's memory at creation; a multi-GB
+    // free blocks the pools in use keep for reuse, in all (half the device's memory, set at
+    // creation): the main pool may keep all of it, each of n lanes in use an n-th.  A multi-GB
     // block dropped and obtained again costs milliseconds each way, so a query whose
-    // intermediates exceed a small limit would pay that on every run)
-    size_t main_cache_limit = (size_t)32 << 30, lane_cache_limit = (size_t)32 << 30;
+    // intermediates exceed a small limit would pay that on every run.
+    size_t pool_cache_total = (size_t)32 << 30;
     atp::ProductGate products;     // a product above heavy_ops products runs alone across lanes
     // a product above this many products runs alone across lanes (ATP_HEAVY_OPS overrides it)
     int64_t heavy_ops = std::getenv("ATP_HEAVY_OPS") ? std::atoll(std::getenv("ATP_HEAVY_OPS")) : 64ll << 20;

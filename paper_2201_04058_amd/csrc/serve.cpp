@@ -357,6 +357,14 @@ atp_status ensure_lanes(atp_ctx *c, int n) {
         }
         c->lanes.push_back(std::move(ln));
     }
+    // the n lanes about to run share the free-block allowance (a pool above its new limit
+    // drops blocks on its next release); the main pool's free blocks, idle while lanes run,
+    // go back to the device first, or the lanes' allocations would find it full
+    c->main.pool.release_cache();
+    for (int i = 0; i < n; ++i) {
+        std::lock_guard<std::recursive_mutex> g(c->lanes[i]->pool.mu);
+        c->lanes[i]->pool.cache_limit = c->pool_cache_total / (size_t)n;
+    }
     return ATP_OK;
 }
 
