@@ -113,6 +113,23 @@ struct Pool {
         cached = 0;
         free_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
+    // every free block, taken out of this pool (held drops with them); for another pool's adopt()
+    std::vector<std::pair<size_t, void *>> take_cache() {
+        std::lock_guard<std::recursive_mutex> g(mu);
+        std::vector<std::pair<size_t, void *>> out(cache.begin(), cache.end());
+        for (auto &kv : out) held -= (int64_t)kv.first;
+        cache.clear();
+        cached = 0;
+        return out;
+    }
+    // a free block of n bytes from another pool of the same device; the caller has ordered
+    // every use of it before this pool's stream (no runtime allocation or free either way)
+    void adopt(size_t n, void *p) {
+        std::lock_guard<std::recursive_mutex> g(mu);
+        cache.emplace(n, p);
+        cached += n;
+        held += (int64_t)n;
+    }
     std::function<void()> on_oom;  // frees the cached blocks of every pool of the context
     atp_status alloc(size_t bytes, void **out) {
         if (arena) return alloc_arena(bytes, out);

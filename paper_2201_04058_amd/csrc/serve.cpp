@@ -358,12 +358,27 @@ atp_status ensure_lanes(atp_ctx *c, int n) {
         c->lanes.push_back(std::move(ln));
     }
     // the n lanes about to run share the free-block allowance (a pool above its new limit
-    // drops blocks on its next release); the main pool's free blocks, idle while lanes run,
-    // go back to the device first, or the lanes' allocations would find it full
-    c->main.pool.release_cache();
+    // drops blocks on its next release)
     for (int i = 0; i < n; ++i) {
         std::lock_guard<std::recursive_mutex> g(c->lanes[i]->pool.mu);
         c->lanes[i]->pool.cache_limit = c->pool_cache_total / (size_t)n;
+    }
+    // the main pool's free blocks, idle while lanes run, move to the lanes (largest first, each
+    // to the lane holding the fewest free bytes) once the main stream has finished with them:
+    // returning them to the runtime and obtaining them again costs milliseconds per large block
+    if (!c->main.pool.arena && !c->main.pool.user_alloc && !c->main.pool.cache.empty()) {
+        if (hipStreamSynchronize(c->main.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return ATP_EDEVICE;
+        }
+        auto blocks = c->main.pool.take_cache();
+        std::sort(blocks.begin(), blocks.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        for (auto &kv : blocks) {
+            Pool *best = &c->lanes[0]->pool;
+            for (int i = 1; i < n; ++i)
+                if (c->lanes[i]->pool.cached < best->cached) best = &c->lanes[i]->pool;
+            best->adopt(kv.first, kv.second);
+        }
     }
     return ATP_OK;
 }
