@@ -67,7 +67,9 @@ typedef struct atp_result atp_result;
 typedef struct {
     int device;                 /* HIP device ordinal */
     void *hip_stream;           /* hipStream_t to issue work on, or NULL for the default stream */
-    /* optional device allocator; both NULL = the library's own caching pool */
+    /* optional device allocator; both NULL = the library's own caching pools, which keep
+     * freed blocks for reuse, up to half the device's memory in all (mem_budget_bytes
+     * bounds what each pool holds; a failed allocation releases every pool's free blocks) */
     void *(*alloc)(size_t bytes, void *user);
     void (*free)(void *ptr, void *user);
     void *alloc_user;
